@@ -1,0 +1,208 @@
+/*
+ * abilu.h - C ABI of libabilu.so: asynchronous block ILU(0) preconditioning of 4x4-block sparse
+ * (BSR) Jacobians on one AMD Instinct MI355X (gfx950), inside restarted FGMRES.
+ *
+ * Method: Kashi & Nadarajah, "An asynchronous incomplete block LU preconditioner for
+ * computational fluid dynamics on unstructured grids", arXiv:1912.00539.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrix: BSR with block size b = 4 (the d+2 conserved variables of a 2-D cell, Section 2).
+ *    rowptr int32[N+1] (rowptr[0] = 0), colidx int32[Z] strictly ascending within each row,
+ *    every diagonal block present. Values double[Z][4][4], each block contiguous and row-major.
+ *    Vectors double[4N], the 4 unknowns of a cell consecutive.
+ *  - Factor: the combined array LU[Z][4][4] shares A's pattern (ILU(0), Section 6): for i > j the
+ *    block is L_ij (L has an implicit identity block diagonal), for i <= j it is U_ij.
+ *    Dinv[N][4][4] holds U_ii^{-1}. Element type double (ABILU_F64) or float (ABILU_F32).
+ *  - Memory: every pointer named d_* is device memory on the current HIP device, allocated and
+ *    owned by the caller. The library owns only the pattern object (device arrays plus a small
+ *    pinned host buffer); the compute entry points allocate nothing. Scratch space is a
+ *    caller-provided workspace of at least abilu_workspace_bytes() bytes, 256-byte aligned.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream). Every call is ordered on it.
+ *    Only abilu_build_pattern, fgmres_solve, abilu_ilu_residual, abilu_read_flags and
+ *    abilu_profile_report block, and they wait on `stream` only.
+ *  - Errors: the return value is an abilu_status; negative = error (nothing was launched unless
+ *    stated), positive = warning. Nothing throws or aborts across the ABI. Device-side events
+ *    (a singular diagonal block replaced, a non-finite value) set bits of a flag word in the
+ *    workspace; they are returned by the next blocking call on that workspace (fgmres_solve,
+ *    abilu_read_flags).
+ *  - Calls that share a workspace or a pattern's pinned buffer must not run concurrently.
+ */
+#ifndef ABILU_H
+#define ABILU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ABILU_OK = 0,
+    ABILU_WARN_MODIFIED = 1,   /* a singular diagonal block was replaced by I (modified iteration) */
+    ABILU_WARN_NOCONV = 2,     /* FGMRES stopped at maxit without reaching rtol */
+    ABILU_EINVAL = -1,         /* bad argument (null pointer, size, enum, workspace too small) */
+    ABILU_EPATTERN = -2,       /* unsorted columns, missing diagonal, index out of range */
+    ABILU_ENOMEM = -3,         /* device or pinned allocation failed (pattern build only) */
+    ABILU_EDEVICE = -4,        /* a HIP runtime call or kernel launch failed */
+    ABILU_ENONFINITE = -5      /* a non-finite value appeared (FGMRES result) */
+} abilu_status;
+
+typedef enum { ABILU_SYNC = 0, ABILU_ASYNC = 1 } abilu_mode;
+typedef enum { ABILU_F64 = 0, ABILU_F32 = 1 } abilu_prec;
+typedef enum { ABILU_INIT_FROM_A = 0, ABILU_INIT_FROM_LU = 1 } abilu_init;
+
+/* device flag word bits */
+#define ABILU_FLAG_MODIFIED 1u
+#define ABILU_FLAG_NONFINITE 2u
+
+typedef struct abilu_pattern abilu_pattern;
+
+/*
+ * Analyse a block pattern S_B (Section 4.2) on the device: validate it, locate the diagonal
+ * blocks, and build for every block (i,j) the update set of the block ILU equations (equation
+ * bilu), K(i,j) = { k < min(i,j) : (i,k) in S_B, (k,j) in S_B }, as a CSR list of position
+ * pairs (pos(i,k), pos(k,j)) ascending in k.
+ *   nbrows     N >= 0 block rows (cells)
+ *   d_rowptr   device int32[N+1]; d_colidx device int32[Z] (copied; caller keeps ownership)
+ *   bs         block size, must be 4
+ *   out        receives the pattern handle (release with abilu_pattern_destroy)
+ * Blocks on `stream`. Errors: ABILU_EINVAL (bs != 4, N < 0, null pointers), ABILU_EPATTERN
+ * (invalid pattern; *out is left NULL), ABILU_ENOMEM, ABILU_EDEVICE.
+ */
+abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_rowptr, const int32_t *d_colidx,
+                                 int32_t bs, void *stream, abilu_pattern **out);
+
+/* Free a pattern (NULL is accepted). Not ordered on any stream: the caller must have finished
+ * all work that uses it. */
+abilu_status abilu_pattern_destroy(abilu_pattern *p);
+
+/* Sizes of a pattern: block rows N, block nonzeros Z, total length of the update-set lists. */
+abilu_status abilu_pattern_info(const abilu_pattern *p, int32_t *nbrows, int64_t *nnzb,
+                                int64_t *npairs);
+
+/* Copy the pattern's analysis to caller device buffers (for verification): d_diag_pos int32[N],
+ * d_pair_ptr int32[Z+1], d_pik int32[npairs], d_pkj int32[npairs]. Any pointer may be NULL. */
+abilu_status abilu_pattern_export(const abilu_pattern *p, int32_t *d_diag_pos, int32_t *d_pair_ptr,
+                                  int32_t *d_pik, int32_t *d_pkj, void *stream);
+
+/* Workspace bytes needed by abilu_factor, abilu_apply, abilu_ilu_residual and, when
+ * fgmres_restart > 0, fgmres_solve with that restart length. */
+size_t abilu_workspace_bytes(const abilu_pattern *p, abilu_prec prec, int32_t fgmres_restart);
+
+/*
+ * Block ILU(0) factorisation by fixed-point sweeps (Section 4.2): every block of L and U is
+ * recomputed from equation bilu in each sweep, all blocks at once.
+ *   mode ABILU_SYNC : Jacobi-type iteration x^{p+1} = h(x^p) (deterministic; reads only the
+ *                     previous iterate, including its diagonal inverses).
+ *   mode ABILU_ASYNC: in-place asynchronous iteration (equation async_blockilu_fp): blocks are
+ *                     overwritten as soon as they are computed and later updates read whatever
+ *                     values are in memory; sums accumulate in registers only; no atomics on
+ *                     values. One kernel launch per sweep bounds the delay by one sweep.
+ *   init  ABILU_INIT_FROM_A : initial guess X0 = A (the paper's choice, Section 6 setup)
+ *         ABILU_INIT_FROM_LU: warm start from the values already in d_LU (Section 3.3 notes the
+ *                             previous time step's factors may serve as the initial guess)
+ *   d_A     double[Z][4][4] (read; rounded to float on load when prec = ABILU_F32)
+ *   d_LU    prec[Z][4][4]   (written; read first for INIT_FROM_LU)
+ *   d_Dinv  prec[N][4][4]   (written: inverses of the final diagonal blocks U_ii)
+ *   nsweeps >= 0 sweeps (0: d_LU = X0, d_Dinv = inverses of X0's diagonal blocks)
+ * A diagonal block that is singular (exact zero pivot in Gaussian elimination with partial
+ * pivoting) or has a non-finite inverse is replaced by I and ABILU_FLAG_MODIFIED is set in the
+ * workspace flag word (modified iteration, Theorem 8); non-finite factor values set
+ * ABILU_FLAG_NONFINITE. Non-blocking. Errors: ABILU_EINVAL, ABILU_EDEVICE.
+ */
+abilu_status abilu_factor(const abilu_pattern *p, const double *d_A, void *d_LU, void *d_Dinv,
+                          abilu_prec prec, int32_t nsweeps, abilu_mode mode, abilu_init init,
+                          void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * Preconditioner application z ~= (LU)^{-1} r by block Jacobi sweeps on the two triangular
+ * systems (Algorithm 5 and its backward analogue, Section 4.1), each from a zero initial guess:
+ *   forward  y_i <- r_i - sum_{j<i} L_ij y_j                  (L_ii = I)
+ *   backward z_i <- U_ii^{-1} (y_i - sum_{j>i} U_ij z_j)
+ * nsweeps forward sweeps then nsweeps backward sweeps (nsweeps = 0: z = r, no preconditioning).
+ * SYNC sweeps read the previous sweep's vector; ASYNC sweeps update the vector in place.
+ *   d_r double[4N] (read), d_z double[4N] (written; must not alias d_r)
+ *   intermediate vectors are stored in prec; d_r is rounded to prec on load.
+ * Non-blocking. Errors: ABILU_EINVAL, ABILU_EDEVICE.
+ */
+abilu_status abilu_apply(const abilu_pattern *p, const void *d_LU, const void *d_Dinv,
+                         abilu_prec prec, const double *d_r, double *d_z, int32_t nsweeps,
+                         abilu_mode mode, void *d_work, size_t work_bytes, void *stream);
+
+/* Block sparse matrix-vector product y = A x in double precision (the Krylov solver's operator,
+ * Section 6 setup). d_x and d_y double[4N] must not alias. Non-blocking. */
+abilu_status abilu_spmv(const abilu_pattern *p, const double *d_A, const double *d_x, double *d_y,
+                        void *stream);
+
+typedef struct {
+    int32_t iters;              /* FGMRES iterations (Arnoldi steps) performed */
+    int32_t restarts;           /* completed cycles (x updates) */
+    int32_t converged;          /* 1 if ||b - A x||_2 <= rtol ||b||_2 at exit */
+    uint32_t flags;             /* workspace flag word at exit (ABILU_FLAG_*) */
+    int32_t reorth;             /* iterations that needed the second Gram-Schmidt pass */
+    double rel_true_residual;   /* ||b - A x||_2 / ||b||_2 at exit (double precision) */
+    double rel_estimate;        /* last Givens residual estimate / ||b||_2 */
+} abilu_fgmres_result;
+
+/*
+ * Restarted flexible GMRES(restart), right-preconditioned by abilu_apply with the given factor
+ * (the outer solver of Sections 1 and 6; flexible because asynchronous application may differ
+ * between iterations). Arnoldi basis, orthogonalisation (classical Gram-Schmidt with a second
+ * pass when the norm drops below 1/sqrt(2) of its value before orthogonalisation), Givens
+ * rotations, least-squares update and true residual are all in double precision on the device.
+ * Iterations stop when the Givens estimate reaches rtol ||b||_2 or maxit; x is updated at each
+ * cycle end and convergence is decided on the true residual.
+ *   d_b double[4N]; d_x double[4N] holds x0 on entry and the solution on exit
+ *   restart >= 1, maxit >= 0, rtol >= 0; apply_sweeps / mode / prec as for abilu_apply
+ *   work_bytes >= abilu_workspace_bytes(p, prec, restart)
+ * Blocks (one host read of a few scalars per iteration). Returns ABILU_OK, ABILU_WARN_NOCONV,
+ * ABILU_WARN_MODIFIED (flag set and converged), ABILU_ENONFINITE, ABILU_EINVAL, ABILU_EDEVICE.
+ */
+abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, const double *d_b, double *d_x,
+                          int32_t restart, int32_t maxit, double rtol, const void *d_LU,
+                          const void *d_Dinv, abilu_prec prec, int32_t apply_sweeps, abilu_mode mode,
+                          void *d_work, size_t work_bytes, void *stream, abilu_fgmres_result *out);
+
+/*
+ * Nonlinear residual of the factor equations on the pattern, ||P_S(LU - A)||_F / ||P_S(A)||_F,
+ * with (LU)_ij = sum_{k in K(i,j)} L_ik U_kj + (i > j ? L_ij U_jj : U_ij) (equation bilu; the
+ * quality measure the paper reports for asynchronous factors, Section 6). Accumulated in
+ * double. Blocks; the result is written to *h_rel (host memory).
+ */
+abilu_status abilu_ilu_residual(const abilu_pattern *p, const double *d_A, const void *d_LU,
+                                abilu_prec prec, void *d_work, size_t work_bytes, double *h_rel,
+                                void *stream);
+
+/* Read (and if `clear`, reset) the workspace flag word. Blocks on `stream`. */
+abilu_status abilu_read_flags(void *d_work, int32_t clear, uint32_t *h_flags, void *stream);
+
+/* Zero the workspace flag word (ordered on `stream`, non-blocking). */
+abilu_status abilu_clear_flags(void *d_work, void *stream);
+
+/* STREAM-style copy d_dst[0:bytes) = d_src[0:bytes) with the same launch style as the library's
+ * kernels: the achievable-HBM-bandwidth reference the paper's STREAM comparison calls for
+ * (Section 6.1). bytes must be a multiple of 16 and both pointers 16-byte aligned. */
+abilu_status abilu_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *stream);
+
+/* Per-kernel timing with HIP events recorded on each launch's stream. enable != 0 starts
+ * recording (up to max_launches launches; later launches are not timed) and clears old records;
+ * enable = 0 stops. abilu_profile_report waits for the recorded events and writes a JSON object
+ * {"kernel": [launches, total_ms, algorithmic_bytes], ...} into buf (NUL-terminated, truncated
+ * to len). Algorithmic bytes count every array element a launch must read or write once
+ * (gathered blocks and vector entries once, as with perfect cache reuse). */
+abilu_status abilu_profile_enable(int32_t enable, int32_t max_launches);
+abilu_status abilu_profile_report(char *buf, size_t len);
+
+/* Text of the most recent failed HIP call in this thread (empty if none): the call and the
+ * runtime's error string. Copies at most len-1 characters and NUL-terminates. */
+abilu_status abilu_last_error(char *buf, size_t len);
+
+const char *abilu_status_string(abilu_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABILU_H */

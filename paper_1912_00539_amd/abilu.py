@@ -1,0 +1,213 @@
+"""Thin ctypes binding of libabilu.so (include/abilu.h): same entry-point names, argument
+marshalling only. Device buffers are torch tensors on the current HIP device; every call is
+ordered on torch's current stream unless a stream is given. Every computation runs in the HIP
+library: if the library is not built this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libabilu.so")
+
+ABILU_OK, ABILU_WARN_MODIFIED, ABILU_WARN_NOCONV = 0, 1, 2
+ABILU_EINVAL, ABILU_EPATTERN, ABILU_ENOMEM, ABILU_EDEVICE, ABILU_ENONFINITE = -1, -2, -3, -4, -5
+ABILU_SYNC, ABILU_ASYNC = 0, 1
+ABILU_F64, ABILU_F32 = 0, 1
+ABILU_INIT_FROM_A, ABILU_INIT_FROM_LU = 0, 1
+ABILU_FLAG_MODIFIED, ABILU_FLAG_NONFINITE = 1, 2
+
+MODES = {"sync": ABILU_SYNC, "async": ABILU_ASYNC}
+PRECS = {"f64": ABILU_F64, "f32": ABILU_F32}
+INITS = {"A": ABILU_INIT_FROM_A, "LU": ABILU_INIT_FROM_LU}
+
+
+class AbiluError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        detail = f" [{abilu_last_error()}]" if status == ABILU_EDEVICE else ""
+        super().__init__(f"{where}: {status_string(status)} ({status}){detail}")
+        self.status = status
+
+
+class FgmresResult(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("flags", C.c_uint32), ("reorth", C.c_int32), ("rel_true_residual", C.c_double),
+                ("rel_estimate", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libabilu.so; raise if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libabilu.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        # torch ships its own HIP runtime (soname libamdhip64.so.7). Loading torch first makes
+        # libabilu bind to that same runtime instance, which owns the tensors and streams we are
+        # handed; loaded first, libabilu would pull in a second runtime from the system path.
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz, st = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_int
+        sig = {
+            "abilu_build_pattern": ([i32, vp, vp, i32, vp, C.POINTER(vp)], st),
+            "abilu_pattern_destroy": ([vp], st),
+            "abilu_pattern_info": ([vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)], st),
+            "abilu_pattern_export": ([vp, vp, vp, vp, vp, vp], st),
+            "abilu_workspace_bytes": ([vp, st, i32], sz),
+            "abilu_factor": ([vp, vp, vp, vp, st, i32, st, st, vp, sz, vp], st),
+            "abilu_apply": ([vp, vp, vp, st, vp, vp, i32, st, vp, sz, vp], st),
+            "abilu_spmv": ([vp, vp, vp, vp, vp], st),
+            "fgmres_solve": ([vp, vp, vp, vp, i32, i32, C.c_double, vp, vp, st, i32, st, vp, sz, vp,
+                              C.POINTER(FgmresResult)], st),
+            "abilu_ilu_residual": ([vp, vp, vp, st, vp, sz, C.POINTER(C.c_double), vp], st),
+            "abilu_read_flags": ([vp, i32, C.POINTER(C.c_uint32), vp], st),
+            "abilu_clear_flags": ([vp, vp], st),
+            "abilu_stream_copy": ([vp, vp, sz, vp], st),
+            "abilu_profile_enable": ([i32, i32], st),
+            "abilu_profile_report": ([C.c_char_p, sz], st),
+            "abilu_status_string": ([st], C.c_char_p),
+            "abilu_last_error": ([C.c_char_p, sz], st),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def abilu_last_error() -> str:
+    buf = C.create_string_buffer(512)
+    lib().abilu_last_error(buf, len(buf))
+    return buf.value.decode(errors="replace")
+
+
+def status_string(status: int) -> str:
+    return lib().abilu_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str, ok=(ABILU_OK,)) -> int:
+    if status not in ok:
+        raise AbiluError(status, where)
+    return status
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Pattern:
+    """Owns an abilu_pattern handle."""
+
+    def __init__(self, handle: int):
+        self.handle = C.c_void_p(handle)
+
+    def info(self):
+        n = C.c_int32(); z = C.c_int64(); npairs = C.c_int64()
+        _check(lib().abilu_pattern_info(self.handle, C.byref(n), C.byref(z), C.byref(npairs)), "abilu_pattern_info")
+        return n.value, z.value, npairs.value
+
+    def destroy(self):
+        if self.handle is not None and self.handle.value:
+            lib().abilu_pattern_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def abilu_build_pattern(nbrows: int, rowptr, colidx, bs: int = 4, stream=None) -> Pattern:
+    out = C.c_void_p()
+    _check(lib().abilu_build_pattern(int(nbrows), _ptr(rowptr), _ptr(colidx), int(bs), _stream(stream),
+                                     C.byref(out)), "abilu_build_pattern")
+    return Pattern(out.value)
+
+
+def abilu_pattern_export(p: Pattern, diag_pos=None, pair_ptr=None, pik=None, pkj=None, stream=None):
+    _check(lib().abilu_pattern_export(p.handle, _ptr(diag_pos), _ptr(pair_ptr), _ptr(pik), _ptr(pkj),
+                                      _stream(stream)), "abilu_pattern_export")
+
+
+def abilu_workspace_bytes(p: Pattern, prec: str = "f32", fgmres_restart: int = 0) -> int:
+    return int(lib().abilu_workspace_bytes(p.handle, PRECS[prec], int(fgmres_restart)))
+
+
+def abilu_factor(p: Pattern, A, LU, Dinv, prec: str, nsweeps: int, mode: str, work, init: str = "A",
+                 stream=None) -> int:
+    return _check(lib().abilu_factor(p.handle, _ptr(A), _ptr(LU), _ptr(Dinv), PRECS[prec], int(nsweeps),
+                                     MODES[mode], INITS[init], _ptr(work), work.numel() * work.element_size(),
+                                     _stream(stream)), "abilu_factor")
+
+
+def abilu_apply(p: Pattern, LU, Dinv, prec: str, r, z, nsweeps: int, mode: str, work, stream=None) -> int:
+    return _check(lib().abilu_apply(p.handle, _ptr(LU), _ptr(Dinv), PRECS[prec], _ptr(r), _ptr(z), int(nsweeps),
+                                    MODES[mode], _ptr(work), work.numel() * work.element_size(), _stream(stream)),
+                  "abilu_apply")
+
+
+def abilu_spmv(p: Pattern, A, x, y, stream=None) -> int:
+    return _check(lib().abilu_spmv(p.handle, _ptr(A), _ptr(x), _ptr(y), _stream(stream)), "abilu_spmv")
+
+
+def fgmres_solve(p: Pattern, A, b, x, restart: int, maxit: int, rtol: float, LU, Dinv, prec: str,
+                 apply_sweeps: int, mode: str, work, stream=None):
+    """Returns (status, result dict). Warnings (no convergence, modified iteration) are returned,
+    errors raise."""
+    res = FgmresResult()
+    st = lib().fgmres_solve(p.handle, _ptr(A), _ptr(b), _ptr(x), int(restart), int(maxit), float(rtol), _ptr(LU),
+                            _ptr(Dinv), PRECS[prec], int(apply_sweeps), MODES[mode], _ptr(work),
+                            work.numel() * work.element_size(), _stream(stream), C.byref(res))
+    _check(st, "fgmres_solve", ok=(ABILU_OK, ABILU_WARN_MODIFIED, ABILU_WARN_NOCONV, ABILU_ENONFINITE))
+    return st, res.as_dict()
+
+
+def abilu_ilu_residual(p: Pattern, A, LU, prec: str, work, stream=None) -> float:
+    out = C.c_double()
+    _check(lib().abilu_ilu_residual(p.handle, _ptr(A), _ptr(LU), PRECS[prec], _ptr(work),
+                                    work.numel() * work.element_size(), C.byref(out), _stream(stream)),
+           "abilu_ilu_residual")
+    return out.value
+
+
+def abilu_read_flags(work, clear: bool = False, stream=None) -> int:
+    out = C.c_uint32()
+    _check(lib().abilu_read_flags(_ptr(work), int(bool(clear)), C.byref(out), _stream(stream)), "abilu_read_flags")
+    return out.value
+
+
+def abilu_clear_flags(work, stream=None) -> int:
+    return _check(lib().abilu_clear_flags(_ptr(work), _stream(stream)), "abilu_clear_flags")
+
+
+def abilu_stream_copy(dst, src, nbytes: int, stream=None) -> int:
+    return _check(lib().abilu_stream_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)), "abilu_stream_copy")
+
+
+def abilu_profile_enable(enable: bool, max_launches: int = 65536) -> int:
+    return _check(lib().abilu_profile_enable(int(bool(enable)), int(max_launches)), "abilu_profile_enable")
+
+
+def abilu_profile_report() -> dict:
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().abilu_profile_report(buf, len(buf)), "abilu_profile_report")
+    return json.loads(buf.value.decode())

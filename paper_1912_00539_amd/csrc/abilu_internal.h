@@ -1,0 +1,267 @@
+// Internal declarations of libabilu (gfx950). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "abilu.h"
+
+struct abilu_pattern {
+    int32_t n = 0;            // block rows
+    int64_t nnzb = 0;         // Z
+    int64_t npairs = 0;       // total length of the update-set lists
+    int64_t nnzb_lower = 0;   // strictly lower blocks
+    int64_t nnzb_upper = 0;   // strictly upper blocks
+    int32_t *rowptr = nullptr;    // device [n+1]
+    int32_t *colidx = nullptr;    // device [Z]
+    int32_t *diag_pos = nullptr;  // device [n]
+    int32_t *pair_ptr = nullptr;  // device [Z+1]
+    int32_t *pik = nullptr;       // device [npairs]
+    int32_t *pkj = nullptr;       // device [npairs]
+    double *pinned = nullptr;     // host pinned, 64 doubles, for blocking scalar reads
+    int device = 0;
+};
+
+namespace abilu {
+
+constexpr int BS = 4;
+constexpr int BB = 16;
+constexpr int WG = 256;                 // threads per workgroup (4 wavefronts of 64)
+constexpr int ROWS_PER_WG = WG / BS;    // one quad of 4 lanes per block row
+
+// vector kernels: elements per thread and workgroup tile
+constexpr int VEC_E = 8;
+constexpr int VEC_TILE = WG * VEC_E;    // 2048 doubles per workgroup
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ workspace layout
+struct Workspace {
+    size_t flags;      // uint32 flag word (in the 256-byte header)
+    size_t status;     // double[8] scalars read back by the host (header)
+    size_t x2, d2;     // SYNC factor ping-pong buffers (prec)
+    size_t ya, yb, za, zb;  // apply vectors (prec)
+    size_t partials;   // double[(restart+2) * nb_vec]
+    size_t hess;       // double[(restart+1) * restart], column-major, ld = restart+1
+    size_t cs, sn, g, coef, misc;  // double[restart+2] each; misc double[16]
+    size_t red;        // double[restart+4]: outputs of column reductions
+    size_t V, Z;       // double[(restart+1) * 4N], double[restart * 4N]
+    size_t total;
+    int nb_vec;        // workgroups of the vector kernels
+    int restart;
+};
+
+Workspace layout(const abilu_pattern *p, abilu_prec prec, int restart);
+
+// ------------------------------------------------------------------ launch helpers
+// Per-launch HIP-event timing (abilu_profile_enable). Records around every kernel launch,
+// together with the launch's algorithmic bytes (every array element the kernel must touch,
+// counted once).
+struct ProfScope {
+    ProfScope(const char *name, hipStream_t s, double bytes = 0.0);
+    ~ProfScope();
+    int slot;
+    hipStream_t stream;
+};
+int prof_mark();                          // index of the next profiled launch
+void prof_cancel_bytes(int from, int to); // zero the bytes of launches [from, to): skipped work
+
+abilu_status launch_status();   // hipGetLastError -> status (records the error text)
+
+// Record a failed HIP call (text returned by abilu_last_error); true if e == hipSuccess.
+bool hip_ok(hipError_t e, const char *what);
+
+// Algorithmic-byte model inputs of a pattern (doubles to avoid overflow in byte formulas).
+struct Sizes {
+    double N, Z, ZL, ZU, P;
+};
+inline Sizes sizes(const abilu_pattern *p) {
+    return Sizes{(double)p->n, (double)p->nnzb, (double)p->nnzb_lower, (double)p->nnzb_upper, (double)p->npairs};
+}
+
+// ------------------------------------------------------------------ entry points used across files
+abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv, abilu_prec prec,
+                        const double *r, double *z, int nsweeps, abilu_mode mode, char *work,
+                        const Workspace &W, hipStream_t s);
+abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x, double *y,
+                       const double *b, hipStream_t s);
+
+}  // namespace abilu
+
+// ------------------------------------------------------------------ device helpers
+namespace abilu_dev {
+
+// Workgroups are dispatched round-robin over the 8 XCDs. Remap so that each XCD walks one
+// contiguous range of block rows: neighbouring rows (whose blocks are gathered) then share
+// that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+    constexpr int NX = 8;
+    int q = nblocks / NX, rem = nblocks % NX;
+    int x = bid % NX, idx = bid / NX;
+    return (x < rem) ? x * (q + 1) + idx : rem * (q + 1) + (x - rem) * q + idx;
+}
+
+// Broadcast lane L of each quad (4 consecutive lanes) to the whole quad with one DPP
+// quad_perm move per 32-bit word. All four lanes of the quad must be active.
+template <int L>
+__device__ __forceinline__ float qb(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), L * 0x55, 0xF, 0xF, false));
+}
+template <int L>
+__device__ __forceinline__ double qb(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, L * 0x55, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, L * 0x55, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+
+// Row r (this lane's row) of a 4x4 block at `blk` (row-major), converted to T.
+template <typename T, typename S>
+__device__ __forceinline__ void load_row(const S *blk, int r, T (&v)[4]) {
+    const S *p = blk + r * 4;
+    if constexpr (sizeof(S) == 4) {
+        float4 q = *reinterpret_cast<const float4 *>(p);
+        v[0] = (T)q.x; v[1] = (T)q.y; v[2] = (T)q.z; v[3] = (T)q.w;
+    } else {
+        double2 a = *reinterpret_cast<const double2 *>(p);
+        double2 b = *reinterpret_cast<const double2 *>(p + 2);
+        v[0] = (T)a.x; v[1] = (T)a.y; v[2] = (T)b.x; v[3] = (T)b.y;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_row(T *blk, int r, const T (&v)[4]) {
+    T *p = blk + r * 4;
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+    }
+}
+
+// Full 4x4 block assembled in every lane of the quad from the lanes' rows.
+template <typename T>
+__device__ __forceinline__ void gather_block(const T (&row)[4], T (&M)[16]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        M[0 * 4 + c] = qb<0>(row[c]);
+        M[1 * 4 + c] = qb<1>(row[c]);
+        M[2 * 4 + c] = qb<2>(row[c]);
+        M[3 * 4 + c] = qb<3>(row[c]);
+    }
+}
+
+// out[c] = sum_m a[m] * B[m][c], where this lane holds row a of the left factor and row r of B;
+// rows m of B come from the quad's lanes by DPP broadcast.
+template <typename T>
+__device__ __forceinline__ void row_times_block(const T (&a)[4], const T (&brow)[4], T (&out)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        T b0 = qb<0>(brow[c]), b1 = qb<1>(brow[c]), b2 = qb<2>(brow[c]), b3 = qb<3>(brow[c]);
+        out[c] = a[0] * b0 + a[1] * b1 + a[2] * b2 + a[3] * b3;
+    }
+}
+
+// acc[c] -= sum_m a[m] * B[m][c]
+template <typename T>
+__device__ __forceinline__ void row_times_block_sub(const T (&a)[4], const T (&brow)[4], T (&acc)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        T b0 = qb<0>(brow[c]), b1 = qb<1>(brow[c]), b2 = qb<2>(brow[c]), b3 = qb<3>(brow[c]);
+        acc[c] -= a[0] * b0 + a[1] * b1 + a[2] * b2 + a[3] * b3;
+    }
+}
+
+// The 4-vector held one element per lane of the quad, broadcast to every lane.
+template <typename T>
+__device__ __forceinline__ void gather_vec(T v, T (&x)[4]) {
+    x[0] = qb<0>(v); x[1] = qb<1>(v); x[2] = qb<2>(v); x[3] = qb<3>(v);
+}
+
+// Inverse of a 4x4 block by Gaussian elimination with partial pivoting and back substitution,
+// all indices static (row exchanges are selects). Returns false, with R = I, if a pivot is
+// exactly zero or the inverse is not finite (the modified iteration's replacement).
+template <typename T>
+__device__ __forceinline__ bool inv4(T (&M)[16], T (&R)[16]) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) R[q] = (q % 5 == 0) ? T(1) : T(0);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int p = k;
+        T best = fabs(M[k * 4 + k]);
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            T a = fabs(M[r * 4 + k]);
+            bool gt = a > best;
+            best = gt ? a : best;
+            p = gt ? r : p;
+        }
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            bool s = (p == r);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                T a = M[k * 4 + c], b = M[r * 4 + c];
+                M[k * 4 + c] = s ? b : a;
+                M[r * 4 + c] = s ? a : b;
+                T x = R[k * 4 + c], y = R[r * 4 + c];
+                R[k * 4 + c] = s ? y : x;
+                R[r * 4 + c] = s ? x : y;
+            }
+        }
+        T piv = M[k * 4 + k];
+        ok = ok && (piv != T(0));
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            T f = M[r * 4 + k] / piv;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                M[r * 4 + c] -= f * M[k * 4 + c];
+                R[r * 4 + c] -= f * R[k * 4 + c];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            T s = R[k * 4 + c];
+#pragma unroll
+            for (int m = k + 1; m < 4; ++m) s -= M[k * 4 + m] * R[m * 4 + c];
+            R[k * 4 + c] = s / M[k * 4 + k];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ok = ok && isfinite(R[q]);
+    if (!ok) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) R[q] = (q % 5 == 0) ? T(1) : T(0);
+    }
+    return ok;
+}
+
+// Row r of a register-held 4x4 block (r = lane index within the quad, a runtime value). Two
+// levels of selects on the bits of r: a flat select chain is rewritten by the compiler into a
+// dynamically indexed stack array for 16 doubles.
+template <typename T>
+__device__ __forceinline__ void pick_row(const T (&M)[16], int r, T (&out)[4]) {
+    const bool b0 = (r & 1) != 0, b1 = (r & 2) != 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const T lo = b0 ? M[4 + c] : M[c];
+        const T hi = b0 ? M[12 + c] : M[8 + c];
+        out[c] = b1 ? hi : lo;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ unsigned nonfinite4(const T (&v)[4]) {
+    return (isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3])) ? 0u : ABILU_FLAG_NONFINITE;
+}
+
+}  // namespace abilu_dev

@@ -1,0 +1,283 @@
+// Preconditioner application by block Jacobi sweeps on the triangular factors (Algorithm 5 and
+// its backward analogue, Section 4.1), and the BSR matrix-vector product.
+//
+//   forward  y_i <- r_i - sum_{j<i} L_ij y_j          (unit block diagonal: no inverse)
+//   backward z_i <- U_ii^{-1} (y_i - sum_{j>i} U_ij z_j)
+//
+// Each sweep is one launch over all block rows; a quad of 4 lanes owns one block row, lane r
+// owns component r: it reads row r of each block (contiguous across the quad) and element r of
+// the gathered 4-vector, the other three elements coming from the quad by DPP broadcast.
+// SYNC sweeps read the previous sweep's vector (ping-pong); ASYNC sweeps update in place.
+// From the zero initial guess the first SYNC forward sweep is y = r, so it is not launched; the
+// last forward sweep also produces the first backward sweep z = Dinv y (its rows are at hand).
+#include "abilu_internal.h"
+
+using namespace abilu;
+using namespace abilu_dev;
+
+namespace {
+
+template <typename T, typename YI, bool EMIT_Z>
+__global__ __launch_bounds__(WG) void k_fwd(int n, const int32_t *__restrict__ rowptr,
+                                            const int32_t *__restrict__ colidx,
+                                            const int32_t *__restrict__ diag_pos, const T *__restrict__ LU,
+                                            const double *__restrict__ rhs, const YI *yin, T *yout,
+                                            const T *__restrict__ Dinv, T *__restrict__ zout) {
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = wg * ROWS_PER_WG + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (i >= n) return;
+    const int b0 = rowptr[i], d = diag_pos[i];
+    T acc = (T)rhs[(int64_t)i * 4 + r];
+    for (int e = b0; e < d; ++e) {
+        const int j = colidx[e];
+        T l[4], yj[4];
+        load_row(LU + (int64_t)e * BB, r, l);
+        gather_vec((T)yin[(int64_t)j * 4 + r], yj);
+        acc -= l[0] * yj[0] + l[1] * yj[1] + l[2] * yj[2] + l[3] * yj[3];
+    }
+    yout[(int64_t)i * 4 + r] = acc;
+    if constexpr (EMIT_Z) {
+        T dr[4], yi[4];
+        load_row(Dinv + (int64_t)i * BB, r, dr);
+        gather_vec(acc, yi);
+        zout[(int64_t)i * 4 + r] = dr[0] * yi[0] + dr[1] * yi[1] + dr[2] * yi[2] + dr[3] * yi[3];
+    }
+}
+
+// OFFDIAG = false: z = Dinv y only. DUAL: also store z (precision T) into zout2.
+template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
+__global__ __launch_bounds__(WG) void k_bwd(int n, const int32_t *__restrict__ rowptr,
+                                            const int32_t *__restrict__ colidx,
+                                            const int32_t *__restrict__ diag_pos, const T *__restrict__ LU,
+                                            const T *__restrict__ Dinv, const YI *__restrict__ y, const T *zin,
+                                            ZO *zout, T *zout2) {
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = wg * ROWS_PER_WG + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (i >= n) return;
+    T acc = (T)y[(int64_t)i * 4 + r];
+    if constexpr (OFFDIAG) {
+        const int d = diag_pos[i], b1 = rowptr[i + 1];
+        for (int e = d + 1; e < b1; ++e) {
+            const int j = colidx[e];
+            T u[4], zj[4];
+            load_row(LU + (int64_t)e * BB, r, u);
+            gather_vec(zin[(int64_t)j * 4 + r], zj);
+            acc -= u[0] * zj[0] + u[1] * zj[1] + u[2] * zj[2] + u[3] * zj[3];
+        }
+    }
+    T dr[4], a[4];
+    load_row(Dinv + (int64_t)i * BB, r, dr);
+    gather_vec(acc, a);
+    const T z = dr[0] * a[0] + dr[1] * a[1] + dr[2] * a[2] + dr[3] * a[3];
+    zout[(int64_t)i * 4 + r] = (ZO)z;
+    if constexpr (DUAL) zout2[(int64_t)i * 4 + r] = z;
+}
+
+template <typename T>
+__global__ void k_fill(int64_t len, T *v, T val) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < len) v[t] = val;
+}
+
+// y = A x  (RESID: y = b - A x), double precision
+template <bool RESID>
+__global__ __launch_bounds__(WG) void k_spmv(int n, const int32_t *__restrict__ rowptr,
+                                             const int32_t *__restrict__ colidx, const double *__restrict__ A,
+                                             const double *__restrict__ x, double *__restrict__ y,
+                                             const double *__restrict__ b) {
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = wg * ROWS_PER_WG + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (i >= n) return;
+    const int b0 = rowptr[i], b1 = rowptr[i + 1];
+    double acc = 0.0;
+    for (int e = b0; e < b1; ++e) {
+        const int j = colidx[e];
+        double a[4], xj[4];
+        load_row(A + (int64_t)e * BB, r, a);
+        gather_vec(x[(int64_t)j * 4 + r], xj);
+        acc += a[0] * xj[0] + a[1] * xj[1] + a[2] * xj[2] + a[3] * xj[3];
+    }
+    y[(int64_t)i * 4 + r] = RESID ? b[(int64_t)i * 4 + r] - acc : acc;
+}
+
+template <typename T>
+const char *tname();
+template <>
+const char *tname<float>() { return "f32"; }
+template <>
+const char *tname<double>() { return "f64"; }
+
+// Algorithmic bytes of one launch (every element touched once; gathered vector entries once).
+// forward: rowptr[i], diag_pos[i], colidx and blocks of the strict lower part, r (f64),
+// input vector (element size sY), output vector; EMIT_Z adds Dinv and the z output.
+double bytes_fwd(const Sizes &z, double sF, double sY, bool emit) {
+    double b = 8 * z.N + 4 * z.ZL + 16 * sF * z.ZL + 32 * z.N + 4 * z.N * sY + 4 * z.N * sF;
+    return emit ? b + 16 * sF * z.N + 4 * z.N * sF : b;
+}
+// backward: diag_pos[i], rowptr[i+1], colidx and blocks of the strict upper part, y, z input,
+// Dinv, output (element size sZ), optional second output in precision sF
+double bytes_bwd(const Sizes &z, double sF, double sZ, bool dual) {
+    double b = 8 * z.N + 4 * z.ZU + 16 * sF * z.ZU + 4 * z.N * sF + 4 * z.N * sF + 16 * sF * z.N + 4 * z.N * sZ;
+    return dual ? b + 4 * z.N * sF : b;
+}
+
+template <typename T>
+abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const double *r, double *z, int nsw,
+                     abilu_mode mode, char *work, const Workspace &W, hipStream_t s) {
+    const int n = p->n;
+    const int grid = div_up(n, ROWS_PER_WG);
+    const int64_t nv = 4 * (int64_t)n;
+    T *ya = (T *)(work + W.ya), *yb = (T *)(work + W.yb);
+    T *za = (T *)(work + W.za), *zb = (T *)(work + W.zb);
+    char name[64];
+    auto NAME = [&](const char *base) {
+        snprintf(name, sizeof name, "%s_%s_%s", base, tname<T>(), mode == ABILU_SYNC ? "sync" : "async");
+        return name;
+    };
+    const Sizes zz = sizes(p);
+    const double sF = sizeof(T);
+#define LAUNCHED() \
+    if (launch_status() != ABILU_OK) return ABILU_EDEVICE
+
+    if (mode == ABILU_SYNC) {
+        if (nsw == 1) {
+            ProfScope ps(NAME("apply_diag"), s, 32 * zz.N + 16 * sF * zz.N + 32 * zz.N);
+            k_bwd<T, double, double, false, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU,
+                                                                       Dinv, r, (const T *)nullptr, z, (T *)nullptr);
+            LAUNCHED();
+            return ABILU_OK;
+        }
+        // forward sweeps 2..nsw (sweep 1 is y = r)
+        const T *yprev = nullptr;
+        T *ycur = nullptr;
+        for (int q = 2; q <= nsw; ++q) {
+            ycur = (q % 2 == 0) ? ya : yb;
+            const bool last = (q == nsw);
+            ProfScope ps(NAME(last ? "apply_fwd_emitz" : "apply_fwd"), s, bytes_fwd(zz, sF, q == 2 ? 8 : sF, last));
+            if (q == 2) {
+                if (last)
+                    k_fwd<T, double, true><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, r, ycur,
+                                                               Dinv, za);
+                else
+                    k_fwd<T, double, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, r, ycur,
+                                                                Dinv, (T *)nullptr);
+            } else {
+                if (last)
+                    k_fwd<T, T, true><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, yprev, ycur,
+                                                          Dinv, za);
+                else
+                    k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, yprev, ycur,
+                                                           Dinv, (T *)nullptr);
+            }
+            LAUNCHED();
+            yprev = ycur;
+        }
+        const T *yfin = ycur;
+        // backward sweeps 2..nsw (sweep 1 produced za)
+        const T *zprev = za;
+        for (int q = 2; q <= nsw; ++q) {
+            ProfScope ps(NAME("apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, false));
+            if (q == nsw) {
+                k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, Dinv,
+                                                                     yfin, zprev, z, (T *)nullptr);
+            } else {
+                T *zcur = (zprev == za) ? zb : za;
+                k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, Dinv,
+                                                                yfin, zprev, zcur, (T *)nullptr);
+                zprev = zcur;
+            }
+            LAUNCHED();
+        }
+        return ABILU_OK;
+    }
+
+    // ASYNC: zero initial guesses, in-place sweeps
+    {
+        ProfScope ps("apply_fill", s, 2 * 4 * zz.N * sF);
+        k_fill<T><<<div_up(nv, 256), 256, 0, s>>>(nv, ya, T(0));
+        LAUNCHED();
+        k_fill<T><<<div_up(nv, 256), 256, 0, s>>>(nv, za, T(0));
+        LAUNCHED();
+    }
+    for (int q = 1; q <= nsw; ++q) {
+        ProfScope ps(NAME("apply_fwd"), s, bytes_fwd(zz, sF, sF, false));
+        k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, ya, ya, Dinv,
+                                               (T *)nullptr);
+        LAUNCHED();
+    }
+    for (int q = 1; q <= nsw; ++q) {
+        ProfScope ps(NAME("apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, q == nsw));
+        if (q == nsw)
+            k_bwd<T, T, double, true, true><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, Dinv, ya,
+                                                                za, z, za);
+        else
+            k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, Dinv, ya, za,
+                                                            za, (T *)nullptr);
+        LAUNCHED();
+    }
+    return ABILU_OK;
+#undef LAUNCHED
+}
+
+}  // namespace
+
+namespace abilu {
+
+abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv, abilu_prec prec, const double *r,
+                        double *z, int nsweeps, abilu_mode mode, char *work, const Workspace &W, hipStream_t s) {
+    if (p->n == 0) return ABILU_OK;
+    if (nsweeps == 0) {
+        return hip_ok(hipMemcpyAsync(z, r, sizeof(double) * 4 * (size_t)p->n, hipMemcpyDeviceToDevice, s),
+                      "apply identity copy")
+                   ? ABILU_OK
+                   : ABILU_EDEVICE;
+    }
+    if (prec == ABILU_F32)
+        return apply_t<float>(p, (const float *)LU, (const float *)Dinv, r, z, nsweeps, mode, work, W, s);
+    return apply_t<double>(p, (const double *)LU, (const double *)Dinv, r, z, nsweeps, mode, work, W, s);
+}
+
+abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x, double *y, const double *b,
+                       hipStream_t s) {
+    if (p->n == 0) return ABILU_OK;
+    const int grid = div_up(p->n, ROWS_PER_WG);
+    const Sizes z = sizes(p);
+    // rowptr, colidx, A (f64), x gathered once, y written (+ b read)
+    const double by = 4 * (z.N + 1) + 4 * z.Z + 128 * z.Z + 32 * z.N + 32 * z.N;
+    if (b) {
+        ProfScope ps("spmv_resid", s, by + 32 * z.N);
+        k_spmv<true><<<grid, WG, 0, s>>>(p->n, p->rowptr, p->colidx, A, x, y, b);
+    } else {
+        ProfScope ps("spmv", s, by);
+        k_spmv<false><<<grid, WG, 0, s>>>(p->n, p->rowptr, p->colidx, A, x, y, nullptr);
+    }
+    return launch_status();
+}
+
+}  // namespace abilu
+
+extern "C" abilu_status abilu_apply(const abilu_pattern *p, const void *d_LU, const void *d_Dinv, abilu_prec prec,
+                                    const double *d_r, double *d_z, int32_t nsweeps, abilu_mode mode, void *d_work,
+                                    size_t work_bytes, void *stream) {
+    if (!p || nsweeps < 0) return ABILU_EINVAL;
+    if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
+    if (mode != ABILU_SYNC && mode != ABILU_ASYNC) return ABILU_EINVAL;
+    if (!d_work) return ABILU_EINVAL;
+    const Workspace W = layout(p, prec, 0);
+    if (work_bytes < W.total) return ABILU_EINVAL;
+    if (p->n == 0) return ABILU_OK;
+    if (!d_r || !d_z || d_r == d_z) return ABILU_EINVAL;
+    if (nsweeps > 0 && (!d_LU || !d_Dinv)) return ABILU_EINVAL;
+    return apply_impl(p, d_LU, d_Dinv, prec, d_r, d_z, nsweeps, mode, (char *)d_work, W, (hipStream_t)stream);
+}
+
+extern "C" abilu_status abilu_spmv(const abilu_pattern *p, const double *d_A, const double *d_x, double *d_y,
+                                   void *stream) {
+    if (!p) return ABILU_EINVAL;
+    if (p->n == 0) return ABILU_OK;
+    if (!d_A || !d_x || !d_y || d_x == d_y) return ABILU_EINVAL;
+    return spmv_impl(p, d_A, d_x, d_y, nullptr, (hipStream_t)stream);
+}

@@ -1,0 +1,525 @@
+// Restarted flexible GMRES (the Krylov solver of Sections 1 and 6), right-preconditioned by the
+// sweep apply, entirely in double precision on the device: Arnoldi basis V and preconditioned
+// basis Z in the workspace, classical Gram-Schmidt with a second pass when the norm falls below
+// 1/sqrt(2) of its value before orthogonalisation ("twice is enough"), Givens rotations on the
+// Hessenberg matrix by a single-lane kernel, x update and true residual at each cycle end.
+// The host loop reads back a few scalars per iteration to decide when to stop.
+//
+// All reductions are fixed-order (per-workgroup partials, then one workgroup per column in
+// index order), so results do not depend on scheduling.
+#include <cmath>
+
+#include "abilu_internal.h"
+
+using namespace abilu;
+using namespace abilu_dev;
+
+namespace {
+
+constexpr int MAX_RESTART = 256;
+
+// status slots (double[8] in the workspace header, copied to the host)
+enum { ST_EST = 0, ST_HN = 1, ST_BETA = 2, ST_NUM = 3, ST_GUARD = 4 };
+// misc slots (double[16])
+enum { MI_NRM0 = 0, MI_NRM1 = 1, MI_HN = 2, MI_BETA = 3, MI_GUARD = 15 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ bool skipped(const int *guard) { return guard && *guard == 0; }
+
+// partial[k*nb + b] = sum_{t in tile b} V_k[t] w[t] for k < q;  partial[q*nb + b] = sum w[t]^2
+__global__ __launch_bounds__(WG) void k_mdot(int64_t len, const double *__restrict__ V, int64_t ldv, int q,
+                                             const double *__restrict__ w, double *__restrict__ partial, int nb,
+                                             const int *guard) {
+    if (skipped(guard)) return;
+    __shared__ double sh[MAX_RESTART + 2][WG / 64];
+    const int64_t base = (int64_t)blockIdx.x * VEC_TILE + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double wv[VEC_E];
+    const bool full = base + (int64_t)(VEC_E - 1) * WG < len;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        wv[e] = (full || t < len) ? w[t] : 0.0;
+    }
+    for (int k = 0; k < q; ++k) {
+        const double *vk = V + (int64_t)k * ldv;
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < VEC_E; ++e) {
+            const int64_t t = base + (int64_t)e * WG;
+            s += ((full || t < len) ? vk[t] : 0.0) * wv[e];
+        }
+        s = wave_sum(s);
+        if (lane == 0) sh[k][wave] = s;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) s += wv[e] * wv[e];
+    s = wave_sum(s);
+    if (lane == 0) sh[q][wave] = s;
+    __syncthreads();
+    for (int k = threadIdx.x; k <= q; k += WG)
+        partial[(int64_t)k * nb + blockIdx.x] = ((sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]));
+}
+
+// w[t] += alpha * sum_k c[k] V_k[t]; if partial: partial[b] = sum over tile of new w[t]^2
+__global__ __launch_bounds__(WG) void k_update(int64_t len, const double *__restrict__ V, int64_t ldv, int q,
+                                               const double *__restrict__ c, double alpha, double *__restrict__ w,
+                                               double *__restrict__ partial, const int *guard) {
+    if (skipped(guard)) return;
+    __shared__ double sh[WG / 64];
+    const int64_t base = (int64_t)blockIdx.x * VEC_TILE + threadIdx.x;
+    const bool full = base + (int64_t)(VEC_E - 1) * WG < len;
+    double acc[VEC_E];
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        acc[e] = (full || t < len) ? w[t] : 0.0;
+    }
+    for (int k = 0; k < q; ++k) {
+        const double ck = alpha * c[k];
+        const double *vk = V + (int64_t)k * ldv;
+#pragma unroll
+        for (int e = 0; e < VEC_E; ++e) {
+            const int64_t t = base + (int64_t)e * WG;
+            acc[e] += ck * ((full || t < len) ? vk[t] : 0.0);
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        if (full || t < len) w[t] = acc[e];
+        s += acc[e] * acc[e];
+    }
+    if (partial) {
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    }
+}
+
+// out[col] = sum_b partial[col*nb + b], one workgroup per column, fixed order
+__global__ __launch_bounds__(WG) void k_reduce_cols(const double *__restrict__ partial, int nb,
+                                                    double *__restrict__ out, const int *guard) {
+    if (skipped(guard)) return;
+    __shared__ double sh[WG / 64];
+    const double *pc = partial + (int64_t)blockIdx.x * nb;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += WG) s += pc[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// v = w / h (h read from device memory; left unchanged if h == 0)
+__global__ __launch_bounds__(WG) void k_scale(int64_t len, const double *w, double *v, const double *h) {
+    const double hv = *h;
+    const int64_t base = (int64_t)blockIdx.x * VEC_TILE + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        if (t < len) v[t] = (hv != 0.0) ? w[t] / hv : w[t];
+    }
+}
+
+// ---- single-lane kernels on the small dense Hessenberg problem (column-major, ld = m+1)
+
+// After the first Gram-Schmidt pass: H(0:k,k) = dots, coef = dots, nrm0 = ||w|| before.
+__global__ void k_gs1(int k, int m, const double *__restrict__ red, double *H, double *coef, double *misc) {
+    for (int q = 0; q <= k; ++q) {
+        H[(int64_t)k * (m + 1) + q] = red[q];
+        coef[q] = red[q];
+    }
+    misc[MI_NRM0] = sqrt(red[k + 1]);
+}
+
+// After the first update: decide on a second pass (guard = 1) if ||w'|| < ||w|| / sqrt(2).
+__global__ void k_gs1_done(const double *__restrict__ nrm2, double *misc, int *guard) {
+    const double n1 = sqrt(nrm2[0]);
+    misc[MI_NRM1] = n1;
+    *guard = (n1 < 0.70710678118654752440 * misc[MI_NRM0]) ? 1 : 0;
+}
+
+// After the second dot pass (only if guard): H(0:k,k) += dots2, coef = dots2.
+__global__ void k_gs2(int k, int m, const double *__restrict__ red, double *H, double *coef, const int *guard) {
+    if (*guard == 0) return;
+    for (int q = 0; q <= k; ++q) {
+        H[(int64_t)k * (m + 1) + q] += red[q];
+        coef[q] = red[q];
+    }
+}
+
+// Final norm, Givens rotations, residual estimate.
+__global__ void k_givens(int k, int m, const double *__restrict__ nrm2_pass2, const int *guard, double *H,
+                         double *cs, double *sn, double *g, double *misc, double *status) {
+    const double hn = (*guard) ? sqrt(nrm2_pass2[0]) : misc[MI_NRM1];
+    double *h = H + (int64_t)k * (m + 1);
+    h[k + 1] = hn;
+    for (int q = 0; q < k; ++q) {
+        const double a = h[q], b = h[q + 1];
+        h[q] = cs[q] * a + sn[q] * b;
+        h[q + 1] = -sn[q] * a + cs[q] * b;
+    }
+    const double a = h[k], b = h[k + 1];
+    const double rho = sqrt(a * a + b * b);
+    cs[k] = rho > 0 ? a / rho : 1.0;
+    sn[k] = rho > 0 ? b / rho : 0.0;
+    h[k] = rho;
+    h[k + 1] = 0.0;
+    g[k + 1] = -sn[k] * g[k];
+    g[k] = cs[k] * g[k];
+    misc[MI_HN] = hn;
+    status[ST_EST] = fabs(g[k + 1]);
+    status[ST_HN] = hn;
+    status[ST_GUARD] = (double)(*guard);
+}
+
+// Back substitution on the k x k upper triangle: coef = y.
+__global__ void k_solve(int k, int m, const double *__restrict__ H, const double *__restrict__ g, double *coef) {
+    for (int q = k - 1; q >= 0; --q) {
+        double s = g[q];
+        for (int t = q + 1; t < k; ++t) s -= H[(int64_t)t * (m + 1) + q] * coef[t];
+        coef[q] = s / H[(int64_t)q * (m + 1) + q];
+    }
+}
+
+// beta = sqrt(red[0]); g = [beta, 0, ...]; status[slot] = beta
+__global__ void k_beta(int m, const double *__restrict__ red, double *g, double *misc, double *status, int slot) {
+    const double beta = sqrt(red[0]);
+    status[slot] = beta;
+    misc[MI_BETA] = beta;
+    if (g) {
+        g[0] = beta;
+        for (int q = 1; q <= m + 1; ++q) g[q] = 0.0;
+    }
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+// ---- ILU residual: sums of ||(LU - A)_ij||^2 and ||A_ij||^2 over the pattern
+template <typename T>
+__global__ __launch_bounds__(WG) void k_ilu_residual(int n, const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ colidx,
+                                                     const int32_t *__restrict__ diag_pos,
+                                                     const int32_t *__restrict__ pair_ptr,
+                                                     const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
+                                                     const double *__restrict__ A, const T *__restrict__ X,
+                                                     double *__restrict__ partial, int nb) {
+    __shared__ double shn[WG / 64], shd[WG / 64];
+    const int r = threadIdx.x & 3;
+    double num = 0.0, den = 0.0;
+    for (int pass = 0; pass < VEC_TILE / 4 / ROWS_PER_WG; ++pass) {
+        const int i = (blockIdx.x * (VEC_TILE / 4 / ROWS_PER_WG) + pass) * ROWS_PER_WG + (threadIdx.x >> 2);
+        if (i < n) {
+            const int b0 = rowptr[i], b1 = rowptr[i + 1];
+            for (int e = b0; e < b1; ++e) {
+                const int j = colidx[e];
+                double x[4], P[4];
+                load_row(X + (int64_t)e * BB, r, x);
+                if (i > j) {
+                    double u[4];
+                    load_row(X + (int64_t)diag_pos[j] * BB, r, u);
+                    row_times_block(x, u, P);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) P[c] = x[c];
+                }
+                for (int q = pair_ptr[e]; q < pair_ptr[e + 1]; ++q) {
+                    double l[4], u[4], t[4];
+                    load_row(X + (int64_t)pik[q] * BB, r, l);
+                    load_row(X + (int64_t)pkj[q] * BB, r, u);
+                    row_times_block(l, u, t);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) P[c] += t[c];
+                }
+                double a[4];
+                load_row(A + (int64_t)e * BB, r, a);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    num += (P[c] - a[c]) * (P[c] - a[c]);
+                    den += a[c] * a[c];
+                }
+            }
+        }
+    }
+    num = wave_sum(num);
+    den = wave_sum(den);
+    if ((threadIdx.x & 63) == 0) {
+        shn[threadIdx.x >> 6] = num;
+        shd[threadIdx.x >> 6] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = (shn[0] + shn[1]) + (shn[2] + shn[3]);
+        partial[nb + blockIdx.x] = (shd[0] + shd[1]) + (shd[2] + shd[3]);
+    }
+}
+
+struct Ctx {
+    const abilu_pattern *p;
+    Workspace W;
+    char *work;
+    hipStream_t s;
+    int64_t nv;
+    double *partials, *H, *cs, *sn, *g, *coef, *misc, *status, *red, *V, *Zb;
+    int *guard;
+};
+
+#define CKL()                                                     \
+    do {                                                          \
+        if (launch_status() != ABILU_OK) return ABILU_EDEVICE;    \
+    } while (0)
+
+// c.red[0..q] <- dots of w with V_0..V_{q-1}, then ||w||^2
+abilu_status mdot_reduce(Ctx &c, const double *Vb, int q, const double *w, const int *guard) {
+    const int nb = c.W.nb_vec;
+    const double n8 = 8.0 * (double)c.nv;
+    {
+        ProfScope ps("fgmres_mdot", c.s, (q + 1) * n8);
+        k_mdot<<<nb, WG, 0, c.s>>>(c.nv, Vb, c.nv, q, w, c.partials, nb, guard);
+    }
+    CKL();
+    {
+        ProfScope ps("fgmres_reduce", c.s, 8.0 * (q + 1) * nb);
+        k_reduce_cols<<<q + 1, WG, 0, c.s>>>(c.partials, nb, c.red, guard);
+    }
+    CKL();
+    return ABILU_OK;
+}
+
+// w += alpha * sum_k coef[k] Vb_k; with_norm: c.red[0] <- ||w||^2 afterwards
+abilu_status update_reduce(Ctx &c, const double *Vb, int q, double alpha, double *w, bool with_norm,
+                           const int *guard) {
+    const int nb = c.W.nb_vec;
+    const double n8 = 8.0 * (double)c.nv;
+    {
+        ProfScope ps("fgmres_update", c.s, (q + 2) * n8);
+        k_update<<<nb, WG, 0, c.s>>>(c.nv, Vb, c.nv, q, c.coef, alpha, w, with_norm ? c.partials : nullptr, guard);
+    }
+    CKL();
+    if (with_norm) {
+        ProfScope ps("fgmres_reduce", c.s, 8.0 * nb);
+        k_reduce_cols<<<1, WG, 0, c.s>>>(c.partials, nb, c.red, guard);
+        CKL();
+    }
+    return ABILU_OK;
+}
+
+// copies the flag word and the status scalars to the host
+abilu_status readback(Ctx &c, double *h, uint32_t *flags) {
+    if (!hip_ok(hipMemcpyAsync(c.p->pinned, c.work, 128, hipMemcpyDeviceToHost, c.s), "fgmres readback"))
+        return ABILU_EDEVICE;
+    if (!hip_ok(hipStreamSynchronize(c.s), "fgmres readback sync")) return ABILU_EDEVICE;
+    *flags = *(const uint32_t *)c.p->pinned;
+    for (int q = 0; q < 8; ++q) h[q] = c.p->pinned[8 + q];
+    return ABILU_OK;
+}
+
+// r = b - A x into V_0, beta = ||r|| into g[0], misc[MI_BETA] and status[ST_BETA]
+abilu_status true_residual(Ctx &c, const double *A, const double *b, const double *x, int m) {
+    abilu_status st = spmv_impl(c.p, A, x, c.V, b, c.s);
+    if (st != ABILU_OK) return st;
+    if ((st = mdot_reduce(c, c.V, 0, c.V, nullptr)) != ABILU_OK) return st;
+    {
+        ProfScope ps("fgmres_small", c.s);
+        k_beta<<<1, 1, 0, c.s>>>(m, c.red, c.g, c.misc, c.status, ST_BETA);
+    }
+    CKL();
+    return ABILU_OK;
+}
+
+}  // namespace
+
+extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, const double *d_b, double *d_x,
+                                     int32_t restart, int32_t maxit, double rtol, const void *d_LU,
+                                     const void *d_Dinv, abilu_prec prec, int32_t apply_sweeps, abilu_mode mode,
+                                     void *d_work, size_t work_bytes, void *stream, abilu_fgmres_result *out) {
+    if (!p || !out || !d_work) return ABILU_EINVAL;
+    if (restart < 1 || restart > MAX_RESTART || maxit < 0 || !(rtol >= 0.0) || apply_sweeps < 0) return ABILU_EINVAL;
+    if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
+    if (mode != ABILU_SYNC && mode != ABILU_ASYNC) return ABILU_EINVAL;
+    *out = abilu_fgmres_result{0, 0, 0, 0u, 0, 0.0, 0.0};
+    Ctx c;
+    c.p = p;
+    c.W = layout(p, prec, restart);
+    if (work_bytes < c.W.total) return ABILU_EINVAL;
+    if (p->n == 0) {
+        out->converged = 1;
+        return ABILU_OK;
+    }
+    if (!d_A || !d_b || !d_x) return ABILU_EINVAL;
+    if (apply_sweeps > 0 && (!d_LU || !d_Dinv)) return ABILU_EINVAL;
+    c.work = (char *)d_work;
+    c.s = (hipStream_t)stream;
+    c.nv = 4 * (int64_t)p->n;
+    const int m = restart;
+    c.partials = (double *)(c.work + c.W.partials);
+    c.H = (double *)(c.work + c.W.hess);
+    c.cs = (double *)(c.work + c.W.cs);
+    c.sn = (double *)(c.work + c.W.sn);
+    c.g = (double *)(c.work + c.W.g);
+    c.coef = (double *)(c.work + c.W.coef);
+    c.misc = (double *)(c.work + c.W.misc);
+    c.status = (double *)(c.work + c.W.status);
+    c.red = (double *)(c.work + c.W.red);
+    c.V = (double *)(c.work + c.W.V);
+    c.Zb = (double *)(c.work + c.W.Z);
+    c.guard = (int *)(c.misc + MI_GUARD);
+    double h[8];
+    uint32_t flags = 0;
+    abilu_status st;
+
+    // ||b|| and the initial residual
+    if ((st = mdot_reduce(c, c.V, 0, d_b, nullptr)) != ABILU_OK) return st;
+    {
+        ProfScope ps("fgmres_small", c.s);
+        k_beta<<<1, 1, 0, c.s>>>(m, c.red, nullptr, c.misc, c.status, ST_NUM);
+    }
+    CKL();
+    if ((st = true_residual(c, d_A, d_b, d_x, m)) != ABILU_OK) return st;
+    if ((st = readback(c, h, &flags)) != ABILU_OK) return st;
+    const double bnorm = h[ST_NUM];
+    const double bn = bnorm > 0 ? bnorm : 1.0;
+    const double tol = rtol * bn;
+    double beta = h[ST_BETA], est = beta;
+    int iters = 0, restarts = 0, reorth = 0;
+    bool converged = beta <= tol;
+    bool nonfinite = !std::isfinite(beta) || !std::isfinite(bnorm);
+
+    while (!converged && !nonfinite && iters < maxit && beta > 0.0) {
+        {
+            ProfScope ps("fgmres_scale", c.s, 16.0 * (double)c.nv);
+            k_scale<<<c.W.nb_vec, WG, 0, c.s>>>(c.nv, c.V, c.V, c.misc + MI_BETA);
+        }
+        CKL();
+        int k = 0;
+        while (k < m && iters < maxit) {
+            const double *vk = c.V + (int64_t)k * c.nv;
+            double *zk = c.Zb + (int64_t)k * c.nv;
+            double *w = c.V + (int64_t)(k + 1) * c.nv;
+            if ((st = apply_impl(p, d_LU, d_Dinv, prec, vk, zk, apply_sweeps, mode, c.work, c.W, c.s)) != ABILU_OK)
+                return st;
+            if ((st = spmv_impl(p, d_A, zk, w, nullptr, c.s)) != ABILU_OK) return st;
+            // Gram-Schmidt pass 1
+            if ((st = mdot_reduce(c, c.V, k + 1, w, nullptr)) != ABILU_OK) return st;
+            {
+                ProfScope ps("fgmres_small", c.s);
+                k_gs1<<<1, 1, 0, c.s>>>(k, m, c.red, c.H, c.coef, c.misc);
+            }
+            CKL();
+            if ((st = update_reduce(c, c.V, k + 1, -1.0, w, true, nullptr)) != ABILU_OK) return st;
+            {
+                ProfScope ps("fgmres_small", c.s);
+                k_gs1_done<<<1, 1, 0, c.s>>>(c.red, c.misc, c.guard);
+            }
+            CKL();
+            // pass 2, executed by the device only when the guard is set
+            const int pass2_begin = prof_mark();
+            if ((st = mdot_reduce(c, c.V, k + 1, w, c.guard)) != ABILU_OK) return st;
+            {
+                ProfScope ps("fgmres_small", c.s);
+                k_gs2<<<1, 1, 0, c.s>>>(k, m, c.red, c.H, c.coef, c.guard);
+            }
+            CKL();
+            if ((st = update_reduce(c, c.V, k + 1, -1.0, w, true, c.guard)) != ABILU_OK) return st;
+            const int pass2_end = prof_mark();
+            {
+                ProfScope ps("fgmres_small", c.s);
+                k_givens<<<1, 1, 0, c.s>>>(k, m, c.red, c.guard, c.H, c.cs, c.sn, c.g, c.misc, c.status);
+            }
+            CKL();
+            {
+                ProfScope ps("fgmres_scale", c.s, 16.0 * (double)c.nv);
+                k_scale<<<c.W.nb_vec, WG, 0, c.s>>>(c.nv, w, w, c.misc + MI_HN);
+            }
+            CKL();
+            if ((st = readback(c, h, &flags)) != ABILU_OK) return st;
+            if (h[ST_GUARD] != 0.0)
+                ++reorth;
+            else
+                prof_cancel_bytes(pass2_begin, pass2_end);   // the second pass exited at once
+            ++iters;
+            ++k;
+            est = h[ST_EST];
+            if (!std::isfinite(est) || !std::isfinite(h[ST_HN])) {
+                nonfinite = true;
+                break;
+            }
+            if (est <= tol || h[ST_HN] == 0.0) break;
+        }
+        if (nonfinite) break;
+        // least squares and x += Z y
+        {
+            ProfScope ps("fgmres_small", c.s);
+            k_solve<<<1, 1, 0, c.s>>>(k, m, c.H, c.g, c.coef);
+        }
+        CKL();
+        if ((st = update_reduce(c, c.Zb, k, 1.0, d_x, false, nullptr)) != ABILU_OK) return st;
+        if ((st = true_residual(c, d_A, d_b, d_x, m)) != ABILU_OK) return st;
+        if ((st = readback(c, h, &flags)) != ABILU_OK) return st;
+        ++restarts;
+        beta = h[ST_BETA];
+        if (!std::isfinite(beta)) nonfinite = true;
+        converged = beta <= tol;
+    }
+    out->iters = iters;
+    out->restarts = restarts;
+    out->converged = converged ? 1 : 0;
+    out->flags = flags;
+    out->reorth = reorth;
+    out->rel_true_residual = beta / bn;
+    out->rel_estimate = est / bn;
+    if (nonfinite) return ABILU_ENONFINITE;
+    if (!converged) return ABILU_WARN_NOCONV;
+    if (flags & ABILU_FLAG_MODIFIED) return ABILU_WARN_MODIFIED;
+    return ABILU_OK;
+}
+
+template <typename T>
+static abilu_status ilu_residual_t(const abilu_pattern *p, const double *A, const T *X, char *work,
+                                   const Workspace &W, double *h_rel, hipStream_t s) {
+    const int nb = W.nb_vec;
+    double *partial = (double *)(work + W.partials);
+    double *red = (double *)(work + W.red);
+    {
+        ProfScope ps("ilu_residual", s);
+        k_ilu_residual<T><<<nb, WG, 0, s>>>(p->n, p->rowptr, p->colidx, p->diag_pos, p->pair_ptr, p->pik, p->pkj, A,
+                                            X, partial, nb);
+    }
+    if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+    k_reduce_cols<<<2, WG, 0, s>>>(partial, nb, red, nullptr);
+    if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+    double v[2];
+    if (!hip_ok(hipMemcpyAsync(p->pinned, red, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "residual readback"))
+        return ABILU_EDEVICE;
+    if (!hip_ok(hipStreamSynchronize(s), "residual readback sync")) return ABILU_EDEVICE;
+    v[0] = p->pinned[0];
+    v[1] = p->pinned[1];
+    *h_rel = v[1] > 0 ? std::sqrt(v[0] / v[1]) : std::sqrt(v[0]);
+    return ABILU_OK;
+}
+
+extern "C" abilu_status abilu_ilu_residual(const abilu_pattern *p, const double *d_A, const void *d_LU,
+                                           abilu_prec prec, void *d_work, size_t work_bytes, double *h_rel,
+                                           void *stream) {
+    if (!p || !h_rel || !d_work) return ABILU_EINVAL;
+    if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
+    const Workspace W = layout(p, prec, 0);
+    if (work_bytes < W.total) return ABILU_EINVAL;
+    if (p->n == 0) {
+        *h_rel = 0.0;
+        return ABILU_OK;
+    }
+    if (!d_A || !d_LU) return ABILU_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == ABILU_F32) return ilu_residual_t<float>(p, d_A, (const float *)d_LU, (char *)d_work, W, h_rel, s);
+    return ilu_residual_t<double>(p, d_A, (const double *)d_LU, (char *)d_work, W, h_rel, s);
+}

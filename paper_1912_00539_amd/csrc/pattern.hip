@@ -1,0 +1,315 @@
+// Pattern analysis on the device: validation, diagonal positions and the update sets
+// K(i,j) = { k < min(i,j) : (i,k), (k,j) in S_B } of the block ILU(0) equations (Section 4.2,
+// equation bilu), stored as CSR lists of block-position pairs ascending in k.
+#include <climits>
+#include <cstring>
+#include <vector>
+
+#include "abilu_internal.h"
+
+namespace {
+
+// position of column j in row k, or -1 (binary search over the sorted row)
+__device__ __forceinline__ int find_col(const int32_t *rowptr, const int32_t *colidx, int k, int j) {
+    int lo = rowptr[k], hi = rowptr[k + 1] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int c = colidx[mid];
+        if (c == j) return mid;
+        if (c < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+__global__ void k_pat_rows(int n, int64_t Z, const int32_t *__restrict__ rowptr,
+                           const int32_t *__restrict__ colidx, int32_t *__restrict__ diag_pos,
+                           unsigned *__restrict__ err) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b0 = rowptr[i], b1 = rowptr[i + 1];
+    bool bad = (b0 < 0) || (b1 < b0) || ((int64_t)b1 > Z);
+    int d = -1;
+    if (!bad) {
+        int prev = -1;
+        for (int e = b0; e < b1; ++e) {
+            int j = colidx[e];
+            if (j < 0 || j >= n || j <= prev) { bad = true; break; }
+            prev = j;
+            if (j == i) d = e;
+        }
+    }
+    if (d < 0) bad = true;
+    diag_pos[i] = d;
+    if (bad) atomicOr(err, 1u);
+}
+
+// one thread per block row; counts |K(i,j)| for every block of the row
+__global__ void k_pat_count(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                            int64_t *__restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b0 = rowptr[i], b1 = rowptr[i + 1];
+    for (int e = b0; e < b1; ++e) {
+        int j = colidx[e];
+        int lim = i < j ? i : j;
+        int c = 0;
+        for (int f = b0; f < b1; ++f) {
+            int k = colidx[f];
+            if (k >= lim) break;
+            c += (find_col(rowptr, colidx, k, j) >= 0);
+        }
+        cnt[e] = c;
+    }
+}
+
+__global__ void k_pat_fill(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                           const int64_t *__restrict__ ptr, int32_t *__restrict__ pik,
+                           int32_t *__restrict__ pkj) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b0 = rowptr[i], b1 = rowptr[i + 1];
+    for (int e = b0; e < b1; ++e) {
+        int j = colidx[e];
+        int lim = i < j ? i : j;
+        int64_t o = ptr[e];
+        for (int f = b0; f < b1; ++f) {
+            int k = colidx[f];
+            if (k >= lim) break;
+            int g = find_col(rowptr, colidx, k, j);
+            if (g >= 0) {
+                pik[o] = f;
+                pkj[o] = g;
+                ++o;
+            }
+        }
+    }
+}
+
+// ---- exclusive scan of int64 counts (3 phases: tile scan, scan of tile totals, add)
+constexpr int SCAN_T = 256, SCAN_E = 8, SCAN_TILE = SCAN_T * SCAN_E;
+
+__device__ long long block_exclusive(long long v, long long *sh, long long *total) {
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        long long a = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    long long inc = sh[t];
+    *total = sh[SCAN_T - 1];
+    __syncthreads();
+    return inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tiles(int64_t len, const int64_t *__restrict__ in,
+                                                       int64_t *__restrict__ out, int64_t *__restrict__ tot) {
+    __shared__ long long sh[SCAN_T];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_E;
+    long long v[SCAN_E], s = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_E; ++q) {
+        v[q] = (base + q < len) ? in[base + q] : 0;
+        s += v[q];
+    }
+    long long total;
+    long long pre = block_exclusive(s, sh, &total);
+#pragma unroll
+    for (int q = 0; q < SCAN_E; ++q) {
+        if (base + q < len) out[base + q] = pre;
+        pre += v[q];
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_totals(int ntiles, int64_t *__restrict__ tot,
+                                                        int64_t *__restrict__ grand) {
+    __shared__ long long sh[SCAN_T];
+    long long carry = 0;
+    for (int base = 0; base < ntiles; base += SCAN_T) {
+        int q = base + threadIdx.x;
+        long long v = (q < ntiles) ? tot[q] : 0;
+        long long total;
+        long long pre = block_exclusive(v, sh, &total);
+        if (q < ntiles) tot[q] = carry + pre;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ void k_scan_finish(int64_t len, const int64_t *__restrict__ scan, const int64_t *__restrict__ tot,
+                              const int64_t *__restrict__ grand, int64_t *__restrict__ ptr64,
+                              int32_t *__restrict__ ptr32) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < len) {
+        int64_t v = scan[e] + tot[e / SCAN_TILE];
+        ptr64[e] = v;
+        ptr32[e] = (int32_t)v;
+    } else if (e == len) {
+        ptr64[len] = *grand;
+        ptr32[len] = (int32_t)*grand;
+    }
+}
+
+void free_pattern(abilu_pattern *p) {
+    if (!p) return;
+    (void)hipFree(p->rowptr);
+    (void)hipFree(p->colidx);
+    (void)hipFree(p->diag_pos);
+    (void)hipFree(p->pair_ptr);
+    (void)hipFree(p->pik);
+    (void)hipFree(p->pkj);
+    if (p->pinned) (void)hipHostFree(p->pinned);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_rowptr,
+                                            const int32_t *d_colidx, int32_t bs, void *stream,
+                                            abilu_pattern **out) {
+    using namespace abilu;
+    if (!out) return ABILU_EINVAL;
+    *out = nullptr;
+    if (bs != 4 || nbrows < 0 || !d_rowptr) return ABILU_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = nbrows;
+
+    abilu_pattern *p = new abilu_pattern();
+    int64_t *cnt = nullptr, *scan = nullptr, *tot = nullptr, *ptr64 = nullptr;
+    unsigned *err = nullptr;
+    abilu_status st = ABILU_OK;
+    int32_t ends[2] = {0, 0};
+#define CK(x)                                  \
+    do {                                       \
+        if (!hip_ok((x), #x)) {                \
+            st = ABILU_EDEVICE;                \
+            goto fail;                         \
+        }                                      \
+    } while (0)
+#define CKA(x)                                 \
+    do {                                       \
+        if (!hip_ok((x), #x)) {                \
+            st = ABILU_ENOMEM;                 \
+            goto fail;                         \
+        }                                      \
+    } while (0)
+    {
+        CK(hipGetDevice(&p->device));
+        p->n = n;
+        CK(hipMemcpyAsync(&ends[0], d_rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(&ends[1], d_rowptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        if (ends[0] != 0 || ends[1] < n) { st = ABILU_EPATTERN; goto fail; }
+        const int64_t Z = ends[1];
+        if (Z > 0 && !d_colidx) { st = ABILU_EINVAL; goto fail; }
+        p->nnzb = Z;
+        CKA(hipHostMalloc((void **)&p->pinned, 64 * sizeof(double), hipHostMallocDefault));
+        CKA(hipMalloc(&p->rowptr, sizeof(int32_t) * (n + 1)));
+        CKA(hipMalloc(&p->colidx, sizeof(int32_t) * (Z + 1)));
+        CKA(hipMalloc(&p->diag_pos, sizeof(int32_t) * (n + 1)));
+        CKA(hipMalloc(&p->pair_ptr, sizeof(int32_t) * (Z + 1)));
+        CKA(hipMalloc(&err, sizeof(unsigned)));
+        CK(hipMemcpyAsync(p->rowptr, d_rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+        if (Z > 0) CK(hipMemcpyAsync(p->colidx, d_colidx, sizeof(int32_t) * Z, hipMemcpyDeviceToDevice, s));
+        CK(hipMemsetAsync(err, 0, sizeof(unsigned), s));
+        if (n > 0) {
+            k_pat_rows<<<div_up(n, 256), 256, 0, s>>>(n, Z, p->rowptr, p->colidx, p->diag_pos, err);
+            CK(hipGetLastError());
+        }
+        unsigned herr = 0;
+        CK(hipMemcpyAsync(&herr, err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        if (herr) { st = ABILU_EPATTERN; goto fail; }
+        if (n > 0) {
+            // block counts of the strict triangles (for the byte model)
+            std::vector<int32_t> hrp(n + 1), hdp(n);
+            CK(hipMemcpyAsync(hrp.data(), p->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+            CK(hipMemcpyAsync(hdp.data(), p->diag_pos, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+            CK(hipStreamSynchronize(s));
+            int64_t zl = 0;
+            for (int i = 0; i < n; ++i) zl += hdp[i] - hrp[i];
+            p->nnzb_lower = zl;
+            p->nnzb_upper = Z - n - zl;
+        }
+
+        const int ntiles = div_up(Z > 0 ? Z : 1, SCAN_TILE);
+        CKA(hipMalloc(&cnt, sizeof(int64_t) * (Z + 1)));
+        CKA(hipMalloc(&scan, sizeof(int64_t) * (Z + 1)));
+        CKA(hipMalloc(&ptr64, sizeof(int64_t) * (Z + 1)));
+        CKA(hipMalloc(&tot, sizeof(int64_t) * (ntiles + 1)));
+        if (n > 0) {
+            k_pat_count<<<div_up(n, 128), 128, 0, s>>>(n, p->rowptr, p->colidx, cnt);
+            CK(hipGetLastError());
+        }
+        k_scan_tiles<<<ntiles, SCAN_T, 0, s>>>(Z, cnt, scan, tot);
+        CK(hipGetLastError());
+        k_scan_totals<<<1, SCAN_T, 0, s>>>(ntiles, tot, tot + ntiles);
+        CK(hipGetLastError());
+        k_scan_finish<<<div_up(Z + 1, 256), 256, 0, s>>>(Z, scan, tot, tot + ntiles, ptr64, p->pair_ptr);
+        CK(hipGetLastError());
+        int64_t npairs = 0;
+        CK(hipMemcpyAsync(&npairs, ptr64 + Z, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        if (npairs < 0 || npairs > (int64_t)INT_MAX) { st = ABILU_EPATTERN; goto fail; }
+        p->npairs = npairs;
+        CKA(hipMalloc(&p->pik, sizeof(int32_t) * (npairs + 1)));
+        CKA(hipMalloc(&p->pkj, sizeof(int32_t) * (npairs + 1)));
+        if (n > 0 && npairs > 0) {
+            k_pat_fill<<<div_up(n, 128), 128, 0, s>>>(n, p->rowptr, p->colidx, ptr64, p->pik, p->pkj);
+            CK(hipGetLastError());
+        }
+        CK(hipStreamSynchronize(s));
+    }
+    (void)hipFree(cnt);
+    (void)hipFree(scan);
+    (void)hipFree(ptr64);
+    (void)hipFree(tot);
+    (void)hipFree(err);
+    *out = p;
+    return ABILU_OK;
+fail:
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(cnt);
+    (void)hipFree(scan);
+    (void)hipFree(ptr64);
+    (void)hipFree(tot);
+    (void)hipFree(err);
+    free_pattern(p);
+    return st;
+#undef CK
+#undef CKA
+}
+
+extern "C" abilu_status abilu_pattern_destroy(abilu_pattern *p) {
+    free_pattern(p);
+    return ABILU_OK;
+}
+
+extern "C" abilu_status abilu_pattern_info(const abilu_pattern *p, int32_t *nbrows, int64_t *nnzb,
+                                           int64_t *npairs) {
+    if (!p) return ABILU_EINVAL;
+    if (nbrows) *nbrows = p->n;
+    if (nnzb) *nnzb = p->nnzb;
+    if (npairs) *npairs = p->npairs;
+    return ABILU_OK;
+}
+
+extern "C" abilu_status abilu_pattern_export(const abilu_pattern *p, int32_t *d_diag_pos,
+                                             int32_t *d_pair_ptr, int32_t *d_pik, int32_t *d_pkj,
+                                             void *stream) {
+    if (!p) return ABILU_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (d_diag_pos && p->n > 0)
+        e = hipMemcpyAsync(d_diag_pos, p->diag_pos, sizeof(int32_t) * p->n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && d_pair_ptr)
+        e = hipMemcpyAsync(d_pair_ptr, p->pair_ptr, sizeof(int32_t) * (p->nnzb + 1), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && d_pik && p->npairs > 0)
+        e = hipMemcpyAsync(d_pik, p->pik, sizeof(int32_t) * p->npairs, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && d_pkj && p->npairs > 0)
+        e = hipMemcpyAsync(d_pkj, p->pkj, sizeof(int32_t) * p->npairs, hipMemcpyDeviceToDevice, s);
+    return abilu::hip_ok(e, "pattern export copy") ? ABILU_OK : ABILU_EDEVICE;
+}

@@ -1,0 +1,451 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances (relative Frobenius / 2-norms):
+  * pattern analysis (integers): bit-exact;
+  * double-precision sweeps and SpMV: 1e-12 (rounding-order differences only: the oracle sums
+    in ascending order without fused multiply-add, the GPU uses FMA and quad-wise products);
+  * single-precision factor/sweeps vs the double oracle: 1e-5, or 8x the input-rounding
+    sensitivity when that is larger: the oracle run on A rounded to float (what the FP32 path
+    reads) already differs from the oracle on A by that much on ill-conditioned cases (the
+    anisotropic aspect-ratio-1000 case cancels large products in U_ii = A_ii - sum A_ik A_ki);
+  * FGMRES: iteration counts within 1, true residual below rtol on both sides.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_00539_amd import workloads as W
+from tests.dense_ref import rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1912_00539_amd import abilu
+    abilu.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def DS(case, prec="f64", restart=30):
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    return DeviceSystem(case, prec=prec, restart=restart)
+
+
+def parity_cases():
+    return {
+        "quad32": lambda: W.case("quad32"),
+        "tri40x30_rcm": lambda: W.case("tri", seed=3, nx=40, ny=30, order="rcm", shift="cfl", cfl=100.0),
+        "nine23x17": lambda: W.case("nine", seed=4, nx=23, ny=17),
+        "random1000": lambda: W.case("random", seed=5, n=1000, deg=5.0, order="random"),
+        "aniso50x20_line": lambda: W.case("aniso", seed=6, nx=50, ny=20, order="line", shift="cfl", cfl=100.0),
+        "chain7": lambda: W.case("chain", seed=7, n=7),
+        "single": lambda: W.case("chain", seed=8, n=1),
+    }
+
+
+CASES = list(parity_cases().keys())
+
+
+def get(name):
+    return parity_cases()[name]()
+
+
+# ------------------------------------------------------------------ pattern analysis (a1)
+@pytest.mark.parametrize("name", CASES)
+def test_pattern_bit_exact(name):
+    from paper_1912_00539_amd import abilu as L
+    c = get(name)
+    s = DS(c)
+    n, z, npairs = s.pattern.info()
+    ptr, pik, pkj = oracle.pairs(c.n, c.rowptr, c.colidx)
+    assert (n, z, npairs) == (c.n, c.nnzb, int(ptr[-1]))
+    dp = torch.zeros(max(c.n, 1), dtype=torch.int32, device="cuda")
+    pp = torch.zeros(z + 1, dtype=torch.int32, device="cuda")
+    a = torch.zeros(max(npairs, 1), dtype=torch.int32, device="cuda")
+    b = torch.zeros(max(npairs, 1), dtype=torch.int32, device="cuda")
+    L.abilu_pattern_export(s.pattern, dp, pp, a, b)
+    torch.cuda.synchronize()
+    diag = np.array([c.rowptr[i] + np.nonzero(c.colidx[c.rowptr[i]:c.rowptr[i + 1]] == i)[0][0] for i in range(c.n)])
+    np.testing.assert_array_equal(dp.cpu().numpy()[: c.n], diag)
+    np.testing.assert_array_equal(pp.cpu().numpy(), ptr)
+    np.testing.assert_array_equal(a.cpu().numpy()[:npairs], pik)
+    np.testing.assert_array_equal(b.cpu().numpy()[:npairs], pkj)
+
+
+def test_pattern_invalid_rejected():
+    from paper_1912_00539_amd import abilu as L
+    c = W.case("quad", nx=5, ny=4)
+    for mutate in ("unsorted", "range", "nodiag", "rowptr"):
+        rp = c.rowptr.copy(); ci = c.colidx.copy()
+        if mutate == "unsorted":
+            ci[[0, 1]] = ci[[1, 0]]
+        elif mutate == "range":
+            ci[5] = c.n + 3
+        elif mutate == "nodiag":
+            d = int(np.nonzero(ci[rp[2]:rp[3]] == 2)[0][0]) + rp[2]
+            ci = np.delete(ci, d)                 # row 2 loses its diagonal block
+            rp = rp.copy(); rp[3:] -= 1
+        elif mutate == "rowptr":
+            rp[3], rp[4] = rp[4], rp[3]
+        with pytest.raises(L.AbiluError) as ei:
+            L.abilu_build_pattern(c.n, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda())
+        assert ei.value.status == L.ABILU_EPATTERN, mutate
+
+
+def test_empty_matrix():
+    from paper_1912_00539_amd import abilu as L
+    rp = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ci = torch.zeros(1, dtype=torch.int32, device="cuda")
+    p = L.abilu_build_pattern(0, rp, ci)
+    assert p.info() == (0, 0, 0)
+    work = torch.zeros(L.abilu_workspace_bytes(p, "f64", 5), dtype=torch.uint8, device="cuda")
+    e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    assert L.abilu_factor(p, e, e, e, "f64", 3, "sync", work) == 0
+    assert L.abilu_apply(p, e, e, "f64", e, e.clone(), 3, "sync", work) == 0
+    st, res = L.fgmres_solve(p, e, e, e.clone(), 5, 10, 1e-2, e, e, "f64", 3, "sync", work)
+    assert st == 0 and res["converged"] == 1
+
+
+# ------------------------------------------------------------------ factor sweeps (a2-a4)
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("nsw", [0, 1, 2, 3])
+def test_factor_sync_f64(name, nsw):
+    c = get(name)
+    s = DS(c, "f64")
+    s.factor(nsw, "sync")
+    X, D = s.factor_host()
+    Xo, Do, fo = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, nsw)
+    assert rel(X, Xo) <= 1e-12 and rel(D, Do) <= 1e-12
+    assert s.flags() == fo == 0
+
+
+def f32_tolerance(c, nsw):
+    """max(1e-5, 8 x sensitivity of the oracle's factor to rounding A to float)."""
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, nsw)
+    A32 = c.vals.astype(np.float32).astype(np.float64)
+    Xr, Dr, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, A32, nsw)
+    return Xo, Do, max(1e-5, 8 * rel(Xr, Xo)), max(1e-5, 8 * rel(Dr, Do))
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("nsw", [1, 3])
+def test_factor_sync_f32(name, nsw):
+    c = get(name)
+    s = DS(c, "f32")
+    s.factor(nsw, "sync")
+    X, D = s.factor_host()
+    Xo, Do, tx, td = f32_tolerance(c, nsw)
+    print(f"f32 vs f64 oracle: X {rel(X, Xo):.2e} (tol {tx:.1e}), Dinv {rel(D, Do):.2e} (tol {td:.1e})")
+    assert rel(X, Xo) <= tx and rel(D, Do) <= td
+
+
+@pytest.mark.parametrize("name", ["quad32", "nine23x17", "random1000", "chain7"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_factor_exact_at_depth(name, prec):
+    """Sync sweeps reach the sequential block ILU(0) at the dependency depth D (Lemma 2,
+    Theorem 8); in-place asynchronous sweeps (one launch per sweep, so every read sees at least
+    the previous sweep) reach the same floating-point fixed point bit for bit."""
+    c = get(name)
+    D, _ = oracle.depth(c.n, c.rowptr, c.colidx)
+    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    s = DS(c, prec)
+    s.factor(D, "sync")
+    Xg, Dg = s.factor_host()
+    assert rel(Xg, Xs) <= tol and rel(Dg, Ds) <= tol
+    a = DS(c, prec)
+    a.factor(D + 2, "async")
+    Xa, Da = a.factor_host()
+    np.testing.assert_array_equal(Xa, Xg)
+    np.testing.assert_array_equal(Da, Dg)
+    assert s.ilu_residual() <= (1e-13 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("name", ["tri40x30_rcm", "nine23x17"])
+def test_factor_async_residual_reported(name):
+    """ASYNC is nondeterministic: its ILU residual is reported (beside the Jacobi-type
+    iteration's at the same sweep count), is finite and decreases with the sweep count."""
+    c = get(name)
+    out = []
+    r0 = oracle.ilu_residual(c.n, c.rowptr, c.colidx, c.vals, c.vals)
+    for nsw in (1, 2, 3):
+        a = DS(c, "f64")
+        a.factor(nsw, "async")
+        ra = a.ilu_residual()
+        Xo, _, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, nsw)
+        rs = oracle.ilu_residual(c.n, c.rowptr, c.colidx, c.vals, Xo)
+        assert np.isfinite(ra)
+        out.append((nsw, ra, rs))
+    print("nsw, async residual, sync residual:", out)
+    assert out[0][1] < r0 and out[-1][1] < out[0][1]
+
+
+@pytest.mark.parametrize("name", ["tri40x30_rcm", "nine23x17"])
+def test_ilu_residual_matches_oracle(name):
+    c = get(name)
+    s = DS(c, "f64")
+    s.factor(1, "sync")
+    X, _ = s.factor_host()
+    ref = oracle.ilu_residual(c.n, c.rowptr, c.colidx, c.vals, X)
+    assert abs(s.ilu_residual() - ref) <= 1e-12 * ref
+
+
+def test_factor_warm_start():
+    """INIT_FROM_LU: sweeps continue from the factor in d_LU (x^{p+q} from x^p)."""
+    c = get("nine23x17")
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        for first, second in ((1, 2), (2, 1), (1, 0)):
+            s = DS(c, prec)
+            s.factor(first, "sync")
+            s.factor(second, "sync", init="LU")
+            X, D = s.factor_host()
+            Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, first + second)
+            assert rel(X, Xo) <= tol and rel(D, Do) <= tol, (prec, first, second)
+
+
+def test_factor_singular_and_nonfinite_flags():
+    c = W.case("quad", seed=3, nx=9, ny=8)
+    A = c.vals.copy()
+    d0 = int(np.nonzero(c.colidx[c.rowptr[0]:c.rowptr[1]] == 0)[0][0])
+    A[d0] = 0.0
+    c0 = W.BSRCase(c.n, c.rowptr, c.colidx, A, c.b, c.meta)
+    for prec in ("f64", "f32"):
+        s = DS(c0, prec)
+        s.factor(3, "sync")
+        X, D = s.factor_host()
+        Xo, Do, fo = oracle.factor_sync(c.n, c.rowptr, c.colidx, A, 3)
+        assert fo & oracle.FLAG_MODIFIED
+        assert s.flags() & 1
+        np.testing.assert_array_equal(D[0], np.eye(4))
+        assert rel(X, Xo) <= (1e-12 if prec == "f64" else 1e-5)
+    A2 = c.vals.copy()
+    A2[d0, 1, 2] = np.nan
+    s = DS(W.BSRCase(c.n, c.rowptr, c.colidx, A2, c.b, c.meta), "f64")
+    s.factor(2, "sync")
+    assert s.flags() & 2
+
+
+# ------------------------------------------------------------------ apply sweeps (a5, a6)
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("nsw", [0, 1, 2, 3, 5])
+def test_apply_sync_f64(name, nsw):
+    c = get(name)
+    s = DS(c, "f64")
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 2)
+    s.set_factor(Xo, Do)
+    r = np.random.default_rng(nsw).uniform(-1, 1, 4 * c.n)
+    rt = torch.from_numpy(r).cuda()
+    zt = torch.zeros_like(rt)
+    s.apply(rt, zt, nsw, "sync")
+    ref = oracle.apply_sync(c.n, c.rowptr, c.colidx, Xo, Do, r, nsw)
+    assert rel(zt.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("nsw", [1, 2, 3])
+def test_apply_sync_f32(name, nsw):
+    c = get(name)
+    s = DS(c, "f32")
+    s.factor(1, "sync")
+    X, D = s.factor_host()                  # the f32 factor, exactly representable in f64
+    r = np.random.default_rng(10 + nsw).uniform(-1, 1, 4 * c.n)
+    rt = torch.from_numpy(r).cuda()
+    zt = torch.zeros_like(rt)
+    s.apply(rt, zt, nsw, "sync")
+    ref = oracle.apply_sync(c.n, c.rowptr, c.colidx, X, D, r, nsw)
+    assert rel(zt.cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["quad32", "tri40x30_rcm", "aniso50x20_line", "chain7"])
+def test_apply_exact_at_levels(name):
+    """Theorem 3 (tight form): once the sweep count reaches the number of levels, sync and
+    async sweeps return the exact triangular solves (Algorithm 1)."""
+    c = get(name)
+    nl, nu, _, _ = oracle.levels(c.n, c.rowptr, c.colidx)
+    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    r = np.random.default_rng(2).uniform(-1, 1, 4 * c.n)
+    ref = oracle.trisolve_exact(c.n, c.rowptr, c.colidx, Xs, Ds, r)
+    s = DS(c, "f64")
+    s.set_factor(Xs, Ds)
+    rt = torch.from_numpy(r).cuda()
+    for mode in ("sync", "async"):
+        zt = torch.zeros_like(rt)
+        s.apply(rt, zt, max(nl, nu), mode)
+        assert rel(zt.cpu().numpy(), ref) <= 1e-12, mode
+
+
+def test_apply_async_converges_to_exact():
+    c = get("tri40x30_rcm")
+    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    r = np.random.default_rng(3).uniform(-1, 1, 4 * c.n)
+    ref = oracle.trisolve_exact(c.n, c.rowptr, c.colidx, Xs, Ds, r)
+    s = DS(c, "f64")
+    s.set_factor(Xs, Ds)
+    rt = torch.from_numpy(r).cuda()
+    errs = []
+    for nsw in (1, 2, 4, 8):
+        zt = torch.zeros_like(rt)
+        s.apply(rt, zt, nsw, "async")
+        e_async = rel(zt.cpu().numpy(), ref)
+        e_sync = rel(oracle.apply_sync(c.n, c.rowptr, c.colidx, Xs, Ds, r, nsw), ref)
+        assert np.isfinite(e_async)
+        errs.append((nsw, e_async, e_sync))
+    print("nsw, async error, sync error:", errs)
+    assert errs[-1][1] < errs[0][1]
+
+
+# ------------------------------------------------------------------ SpMV (a7)
+@pytest.mark.parametrize("name", CASES)
+def test_spmv(name):
+    c = get(name)
+    s = DS(c, "f64")
+    x = np.random.default_rng(4).uniform(-1, 1, 4 * c.n)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    s.spmv(xt, yt)
+    ref = oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)
+    assert rel(yt.cpu().numpy(), ref) <= 1e-13
+
+
+# ------------------------------------------------------------------ FGMRES (a8, a9)
+@pytest.mark.parametrize("name", ["quad32", "tri40x30_rcm", "nine23x17", "aniso50x20_line"])
+def test_fgmres_f64_matches_oracle(name):
+    c = get(name)
+    s = DS(c, "f64", restart=30)
+    s.factor(3, "sync")
+    X, D = s.factor_host()
+    st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-6, maxit=300)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, X, D, restart=30, maxit=300, rtol=1e-6, apply_nsw=3)
+    assert st == 0 and res["converged"] and ref["converged"]
+    assert abs(res["iters"] - ref["iters"]) <= 1
+    assert res["rel_true_residual"] <= 1e-6 and ref["rel_true_residual"] <= 1e-6
+    x = s.x.cpu().numpy()
+    true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
+    assert abs(true - res["rel_true_residual"]) <= 1e-10
+    if res["iters"] == ref["iters"]:
+        assert rel(x, ref["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["quad32", "tri40x30_rcm", "aniso50x20_line"])
+def test_fgmres_f32_sync_preconditioner(name):
+    """FP32 factor and sweeps, FP64 Krylov, synchronous sweeps: same outcome as the FP64 oracle
+    (both converge within one iteration of each other, or both fail to converge), and the
+    double-precision true residual matches an oracle SpMV on the returned x."""
+    from paper_1912_00539_amd import abilu as L
+    c = get(name)
+    s = DS(c, "f32", restart=30)
+    s.factor(1, "sync")
+    st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-2, maxit=300)
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, Xo, Do, restart=30, maxit=300, rtol=1e-2, apply_nsw=3)
+    print(f"iters gpu {res['iters']} oracle {ref['iters']}, converged {res['converged']} / {ref['converged']}")
+    assert bool(res["converged"]) == ref["converged"]
+    if ref["converged"]:
+        assert st == 0 and abs(res["iters"] - ref["iters"]) <= 1
+    else:
+        assert st == L.ABILU_WARN_NOCONV
+    x = s.x.cpu().numpy()
+    true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
+    assert abs(true - res["rel_true_residual"]) <= 1e-10 * max(1.0, true)
+    if res["converged"]:
+        assert true <= 1e-2
+
+
+@pytest.mark.parametrize("name", ["quad32", "tri40x30_rcm", "aniso50x20_line"])
+def test_fgmres_f32_async_preconditioner(name):
+    """Asynchronous factor and sweeps (nondeterministic): the solve converges, its true residual
+    is confirmed by an oracle SpMV, and the iteration count is reported beside the oracle's with
+    the one-worker (Gauss-Seidel) factor, which is the sequential ILU(0) after one sweep, and with
+    the Jacobi-type factor."""
+    c = get(name)
+    s = DS(c, "f32", restart=30)
+    s.factor(1, "async")
+    st, res = s.solve(apply_sweeps=3, mode="async", rtol=1e-2, maxit=300)
+    Xg, Dg, _ = oracle.factor_gs(c.n, c.rowptr, c.colidx, c.vals, 1)
+    gs = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, Xg, Dg, restart=30, maxit=300, rtol=1e-2, apply_nsw=3)
+    print(f"iters gpu async {res['iters']}, oracle one-worker {gs['iters']}")
+    assert st == 0 and res["converged"]
+    x = s.x.cpu().numpy()
+    true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
+    assert true <= 1e-2 and abs(true - res["rel_true_residual"]) <= 1e-10
+
+
+def test_fgmres_restarts_and_noconv():
+    c = W.case("quad", seed=6, nx=30, ny=30, s=0.05)
+    s = DS(c, "f64", restart=4)
+    s.factor(1, "sync")
+    X, D = s.factor_host()
+    st, res = s.solve(apply_sweeps=1, mode="sync", rtol=1e-8, maxit=400)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, X, D, restart=4, maxit=400, rtol=1e-8, apply_nsw=1)
+    assert res["converged"] and ref["converged"] and res["restarts"] >= 2
+    assert abs(res["iters"] - ref["iters"]) <= 1
+    from paper_1912_00539_amd import abilu as L
+    st, res = s.solve(apply_sweeps=0, mode="sync", rtol=1e-12, maxit=3)
+    assert st == L.ABILU_WARN_NOCONV and not res["converged"] and res["iters"] == 3
+
+
+def test_fgmres_unpreconditioned_matches_oracle():
+    c = W.case("quad", seed=5, nx=12, ny=11, s=0.5)
+    s = DS(c, "f64", restart=10)
+    st, res = s.solve(apply_sweeps=0, rtol=1e-9, maxit=200)
+    Z = np.zeros_like(c.vals); D0 = np.zeros((c.n, 4, 4))
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, Z, D0, restart=10, maxit=200, rtol=1e-9, apply_nsw=0)
+    assert res["converged"] and abs(res["iters"] - ref["iters"]) <= 1
+
+
+def test_stream_copy():
+    from paper_1912_00539_amd import abilu as L
+    src = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    L.abilu_stream_copy(dst, src, src.numel() * 8)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+
+
+def test_profile_records_launches():
+    from paper_1912_00539_amd import abilu as L
+    c = get("quad32")
+    s = DS(c, "f32")
+    L.abilu_profile_enable(True, 1024)
+    s.factor(2, "sync")
+    rep = L.abilu_profile_report()
+    L.abilu_profile_enable(False)
+    assert rep["factor_sweep_f32_sync_fromA"][0] == 1 and rep["factor_sweep_f32_sync"][0] == 1
+
+
+# ------------------------------------------------------------------ full size (4M cells)
+@pytest.mark.slow
+def test_full_size_tri2000_f32():
+    """The benchmark workload at full size, in the benchmark's launch configuration: 1 sync FP32
+    factor sweep vs the FP64 oracle over every block; 3 apply sweeps vs the oracle on the GPU's own
+    factor; SpMV; FGMRES(50) true residual checked by an oracle SpMV on the returned x."""
+    c = W.case("tri2000")
+    s = DS(c, "f32", restart=50)
+    s.factor(1, "sync")
+    X, D = s.factor_host()
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    print(f"full size f32 factor vs oracle: X {rel(X, Xo):.2e} Dinv {rel(D, Do):.2e}")
+    assert rel(X, Xo) <= 1e-5 and rel(D, Do) <= 1e-5
+    del Xo, Do
+    r = np.random.default_rng(0).uniform(-1, 1, 4 * c.n)
+    rt = torch.from_numpy(r).cuda()
+    zt = torch.zeros_like(rt)
+    s.apply(rt, zt, 3, "sync")
+    ref = oracle.apply_sync(c.n, c.rowptr, c.colidx, X, D, r, 3)
+    assert rel(zt.cpu().numpy(), ref) <= 1e-5
+    s.spmv(rt, zt)
+    assert rel(zt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r)) <= 1e-13
+    for mode in ("sync", "async"):
+        s.factor(1, mode)
+        st, res = s.solve(apply_sweeps=3, mode=mode, rtol=1e-2, maxit=500, restart=50)
+        print(mode, res)
+        assert st == 0 and res["converged"]
+    x = s.x.cpu().numpy()
+    true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
+    assert true <= 1e-2 and abs(true - res["rel_true_residual"]) <= 1e-10

@@ -1,0 +1,58 @@
+"""The C-ABI library loads and exports every entry point include/abilu.h declares; argument
+checks that run before any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1912_00539_amd import abilu as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "abilu.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if not n.startswith("ABILU")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("abilu_build_pattern", "abilu_factor", "abilu_apply", "abilu_spmv", "fgmres_solve",
+                     "abilu_ilu_residual", "abilu_workspace_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(L.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for st in (0, 1, 2, -1, -2, -3, -4, -5):
+        s = L.status_string(st)
+        assert isinstance(s, str) and len(s) > 0
+    assert "invalid argument" in L.status_string(L.ABILU_EINVAL)
+
+
+def test_argument_checks_without_device():
+    lib = L.lib()
+    out = C.c_void_p()
+    # bad block size / negative size / null output are rejected before any HIP call
+    assert lib.abilu_build_pattern(4, None, None, 3, None, C.byref(out)) == L.ABILU_EINVAL
+    assert lib.abilu_build_pattern(-1, None, None, 4, None, C.byref(out)) == L.ABILU_EINVAL
+    assert lib.abilu_build_pattern(4, None, None, 4, None, None) == L.ABILU_EINVAL
+    assert lib.abilu_workspace_bytes(None, L.ABILU_F32, 30) == 0
+    assert lib.abilu_factor(None, None, None, None, L.ABILU_F32, 1, 0, 0, None, 0, None) == L.ABILU_EINVAL
+    assert lib.abilu_apply(None, None, None, L.ABILU_F32, None, None, 1, 0, None, 0, None) == L.ABILU_EINVAL
+    assert lib.abilu_spmv(None, None, None, None, None) == L.ABILU_EINVAL
+    res = L.FgmresResult()
+    assert lib.fgmres_solve(None, None, None, None, 30, 10, 1e-2, None, None, 0, 3, 0, None, 0, None,
+                            C.byref(res)) == L.ABILU_EINVAL
+    assert lib.abilu_stream_copy(None, None, 7, None) == L.ABILU_EINVAL
+    assert lib.abilu_profile_enable(1, 0) == L.ABILU_EINVAL
