@@ -37,18 +37,19 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def run_steps(sysm, args, mode, steps, profile):
+def run_steps(sysm, args, mode, steps, profile, build_sweeps=None, maxit=None):
     import torch
     from paper_1912_00539_amd import abilu as L
     results = []
+    nb = args.build_sweeps if build_sweeps is None else build_sweeps
     if profile:
         L.abilu_profile_enable(True, 200000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        sysm.factor(args.build_sweeps, mode)
-        st, res = sysm.solve(apply_sweeps=args.apply_sweeps, mode=mode, rtol=args.rtol, maxit=args.maxit,
-                             restart=args.restart)
+        sysm.factor(nb, mode)
+        st, res = sysm.solve(apply_sweeps=args.apply_sweeps, mode=mode, rtol=args.rtol,
+                             maxit=args.maxit if maxit is None else maxit, restart=args.restart)
         results.append((st, res))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -99,12 +100,13 @@ def cpu_baseline(case, args):
     rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
     ZL = int(np.count_nonzero(ci < rows))
     ZU = Z - n - ZL
-    reps = 3
+    reps = 0
     t0 = time.perf_counter()
-    for _ in range(reps):
+    while reps < 50 and (reps == 0 or time.perf_counter() - t0 < 10.0):
         X, D, _ = oracle.factor_sync(n, rp, ci, A, 1)
         z = oracle.apply_sync(n, rp, ci, X, D, case.b, args.apply_sweeps)
         oracle.spmv(n, rp, ci, A, z)
+        reps += 1
     t1 = time.perf_counter()
     by = reps * oracle_bytes_f64(n, Z, ZL, ZU, P, args.apply_sweeps)
     return {"value": round(by / (t1 - t0) / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
@@ -134,7 +136,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="async", choices=["sync", "async"])
-    ap.add_argument("--compare-mode", default="sync", choices=["sync", "async", "none"])
+    ap.add_argument("--compare", default="sync:1:100,sync:2:500",
+                    help="comma list of mode:build_sweeps:maxit runs reported beside the headline ('none' to skip)")
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default="tri2000")
     ap.add_argument("--build-sweeps", type=int, default=1)
@@ -175,6 +178,7 @@ def main():
     secs, results, rep = run_steps(sysm, args, args.mode, args.steps, profile=True)
     log(f"timed {args.steps} steps: {secs * 1e3 / args.steps:.3f} ms/step")
     secs_np, _, _ = run_steps(sysm, args, args.mode, args.steps, profile=False)
+    ilu_res = sysm.ilu_residual()
 
     kernels = {k: v for k, v in rep.items() if not k.startswith("_")}
     total_bytes = sum(v[2] for v in kernels.values())
@@ -194,15 +198,21 @@ def main():
     conv = all(r["converged"] for _, r in results)
     resid = max(r["rel_true_residual"] for _, r in results)
 
-    compare = None
-    if args.compare_mode != "none" and args.compare_mode != args.mode:
-        run_steps(sysm, args, args.compare_mode, 1, profile=False)
-        csecs, cres, crep = run_steps(sysm, args, args.compare_mode, max(2, args.steps // 2), profile=True)
-        cb = sum(v[2] for k, v in crep.items() if not k.startswith("_"))
-        compare = {"mode": args.compare_mode, "ms_per_step": round(csecs * 1e3 / max(2, args.steps // 2), 3),
-                   "GBps": round(cb / csecs / 1e9, 1),
-                   "fgmres_iters": [r["iters"] for _, r in cres],
-                   "converged": all(r["converged"] for _, r in cres)}
+    compare = []
+    if args.compare != "none":
+        for spec in args.compare.split(","):
+            cmode, cnb, cmaxit = spec.split(":")
+            cnb, cmaxit = int(cnb), int(cmaxit)
+            run_steps(sysm, args, cmode, 1, profile=False, build_sweeps=cnb, maxit=cmaxit)
+            nst = 3
+            csecs, cres, crep = run_steps(sysm, args, cmode, nst, profile=True, build_sweeps=cnb, maxit=cmaxit)
+            cb = sum(v[2] for k, v in crep.items() if not k.startswith("_"))
+            compare.append({"mode": cmode, "build_sweeps": cnb, "maxit": cmaxit,
+                            "ms_per_step": round(csecs * 1e3 / nst, 3), "GBps": round(cb / csecs / 1e9, 1),
+                            "fgmres_iters": [r["iters"] for _, r in cres],
+                            "converged": all(r["converged"] for _, r in cres),
+                            "ilu_residual": sysm.ilu_residual()})
+        log("compare:", compare)
 
     out = {
         "metric": METRIC,
@@ -236,6 +246,7 @@ def main():
         "ms_per_step_unprofiled": round(secs_np * 1e3 / args.steps, 3),
         "kernel_time_frac_of_step": round(total_kernel_ms / (secs * 1e3), 3),
         "fgmres_iters": iters,
+        "ilu_residual": ilu_res,
         "converged": conv,
         "max_rel_true_residual": resid,
         "kernels": {k: {"launches": v[0], "ms": round(v[1], 4), "GBps": round(v[2] / (v[1] / 1e3) / 1e9, 1) if v[1] else None}

@@ -155,15 +155,20 @@ typedef struct {
  * Iterations stop when the Givens estimate reaches rtol ||b||_2 or maxit; x is updated at each
  * cycle end and convergence is decided on the true residual.
  *   d_b double[4N]; d_x double[4N] holds x0 on entry and the solution on exit
+ *   options  bit ABILU_FGMRES_ZERO_GUESS: x0 = 0 (d_x is not read; the first residual is b, so
+ *            no SpMV is spent on it)
  *   restart >= 1, maxit >= 0, rtol >= 0; apply_sweeps / mode / prec as for abilu_apply
  *   work_bytes >= abilu_workspace_bytes(p, prec, restart)
  * Blocks (one host read of a few scalars per iteration). Returns ABILU_OK, ABILU_WARN_NOCONV,
  * ABILU_WARN_MODIFIED (flag set and converged), ABILU_ENONFINITE, ABILU_EINVAL, ABILU_EDEVICE.
  */
+#define ABILU_FGMRES_ZERO_GUESS 1u
+
 abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, const double *d_b, double *d_x,
                           int32_t restart, int32_t maxit, double rtol, const void *d_LU,
                           const void *d_Dinv, abilu_prec prec, int32_t apply_sweeps, abilu_mode mode,
-                          void *d_work, size_t work_bytes, void *stream, abilu_fgmres_result *out);
+                          uint32_t options, void *d_work, size_t work_bytes, void *stream,
+                          abilu_fgmres_result *out);
 
 /*
  * Nonlinear residual of the factor equations on the pattern, ||P_S(LU - A)||_F / ||P_S(A)||_F,

@@ -19,6 +19,7 @@ ABILU_SYNC, ABILU_ASYNC = 0, 1
 ABILU_F64, ABILU_F32 = 0, 1
 ABILU_INIT_FROM_A, ABILU_INIT_FROM_LU = 0, 1
 ABILU_FLAG_MODIFIED, ABILU_FLAG_NONFINITE = 1, 2
+ABILU_FGMRES_ZERO_GUESS = 1
 
 MODES = {"sync": ABILU_SYNC, "async": ABILU_ASYNC}
 PRECS = {"f64": ABILU_F64, "f32": ABILU_F32}
@@ -65,7 +66,7 @@ def lib():
             "abilu_factor": ([vp, vp, vp, vp, st, i32, st, st, vp, sz, vp], st),
             "abilu_apply": ([vp, vp, vp, st, vp, vp, i32, st, vp, sz, vp], st),
             "abilu_spmv": ([vp, vp, vp, vp, vp], st),
-            "fgmres_solve": ([vp, vp, vp, vp, i32, i32, C.c_double, vp, vp, st, i32, st, vp, sz, vp,
+            "fgmres_solve": ([vp, vp, vp, vp, i32, i32, C.c_double, vp, vp, st, i32, st, C.c_uint32, vp, sz, vp,
                               C.POINTER(FgmresResult)], st),
             "abilu_ilu_residual": ([vp, vp, vp, st, vp, sz, C.POINTER(C.c_double), vp], st),
             "abilu_read_flags": ([vp, i32, C.POINTER(C.c_uint32), vp], st),
@@ -170,12 +171,13 @@ def abilu_spmv(p: Pattern, A, x, y, stream=None) -> int:
 
 
 def fgmres_solve(p: Pattern, A, b, x, restart: int, maxit: int, rtol: float, LU, Dinv, prec: str,
-                 apply_sweeps: int, mode: str, work, stream=None):
+                 apply_sweeps: int, mode: str, work, zero_guess: bool = False, stream=None):
     """Returns (status, result dict). Warnings (no convergence, modified iteration) are returned,
     errors raise."""
     res = FgmresResult()
+    opts = ABILU_FGMRES_ZERO_GUESS if zero_guess else 0
     st = lib().fgmres_solve(p.handle, _ptr(A), _ptr(b), _ptr(x), int(restart), int(maxit), float(rtol), _ptr(LU),
-                            _ptr(Dinv), PRECS[prec], int(apply_sweeps), MODES[mode], _ptr(work),
+                            _ptr(Dinv), PRECS[prec], int(apply_sweeps), MODES[mode], opts, _ptr(work),
                             work.numel() * work.element_size(), _stream(stream), C.byref(res))
     _check(st, "fgmres_solve", ok=(ABILU_OK, ABILU_WARN_MODIFIED, ABILU_WARN_NOCONV, ABILU_ENONFINITE))
     return st, res.as_dict()

@@ -204,6 +204,15 @@ __global__ void k_beta(int m, const double *__restrict__ red, double *g, double 
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
+__global__ __launch_bounds__(WG) void k_zero(int64_t len, double *v) {
+    const int64_t base = (int64_t)blockIdx.x * VEC_TILE + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        if (t < len) v[t] = 0.0;
+    }
+}
+
 // ---- ILU residual: sums of ||(LU - A)_ij||^2 and ||A_ij||^2 over the pattern
 template <typename T>
 __global__ __launch_bounds__(WG) void k_ilu_residual(int n, const int32_t *__restrict__ rowptr,
@@ -341,7 +350,8 @@ abilu_status true_residual(Ctx &c, const double *A, const double *b, const doubl
 extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, const double *d_b, double *d_x,
                                      int32_t restart, int32_t maxit, double rtol, const void *d_LU,
                                      const void *d_Dinv, abilu_prec prec, int32_t apply_sweeps, abilu_mode mode,
-                                     void *d_work, size_t work_bytes, void *stream, abilu_fgmres_result *out) {
+                                     uint32_t options, void *d_work, size_t work_bytes, void *stream,
+                                     abilu_fgmres_result *out) {
     if (!p || !out || !d_work) return ABILU_EINVAL;
     if (restart < 1 || restart > MAX_RESTART || maxit < 0 || !(rtol >= 0.0) || apply_sweeps < 0) return ABILU_EINVAL;
     if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
@@ -377,14 +387,26 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
     uint32_t flags = 0;
     abilu_status st;
 
-    // ||b|| and the initial residual
+    // ||b|| and the initial residual (b itself for a zero initial guess)
+    const bool zero_guess = (options & ABILU_FGMRES_ZERO_GUESS) != 0;
     if ((st = mdot_reduce(c, c.V, 0, d_b, nullptr)) != ABILU_OK) return st;
     {
         ProfScope ps("fgmres_small", c.s);
-        k_beta<<<1, 1, 0, c.s>>>(m, c.red, nullptr, c.misc, c.status, ST_NUM);
+        k_beta<<<1, 1, 0, c.s>>>(m, c.red, zero_guess ? c.g : nullptr, c.misc, c.status, ST_NUM);
+        if (zero_guess) k_beta<<<1, 1, 0, c.s>>>(m, c.red, nullptr, c.misc, c.status, ST_BETA);
     }
     CKL();
-    if ((st = true_residual(c, d_A, d_b, d_x, m)) != ABILU_OK) return st;
+    const double *first_v0 = c.V;   // the vector the first cycle normalises into V_0
+    if (zero_guess) {
+        {
+            ProfScope ps("fgmres_scale", c.s, 8.0 * (double)c.nv);
+            k_zero<<<c.W.nb_vec, WG, 0, c.s>>>(c.nv, d_x);
+        }
+        CKL();
+        first_v0 = d_b;
+    } else if ((st = true_residual(c, d_A, d_b, d_x, m)) != ABILU_OK) {
+        return st;
+    }
     if ((st = readback(c, h, &flags)) != ABILU_OK) return st;
     const double bnorm = h[ST_NUM];
     const double bn = bnorm > 0 ? bnorm : 1.0;
@@ -397,9 +419,10 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
     while (!converged && !nonfinite && iters < maxit && beta > 0.0) {
         {
             ProfScope ps("fgmres_scale", c.s, 16.0 * (double)c.nv);
-            k_scale<<<c.W.nb_vec, WG, 0, c.s>>>(c.nv, c.V, c.V, c.misc + MI_BETA);
+            k_scale<<<c.W.nb_vec, WG, 0, c.s>>>(c.nv, first_v0, c.V, c.misc + MI_BETA);
         }
         CKL();
+        first_v0 = c.V;
         int k = 0;
         while (k < m && iters < maxit) {
             const double *vk = c.V + (int64_t)k * c.nv;

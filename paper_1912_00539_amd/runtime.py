@@ -43,12 +43,12 @@ class DeviceSystem:
 
     def solve(self, apply_sweeps: int = 3, mode: str = "sync", rtol: float = 1e-2, maxit: int = 2500,
               x0=None, restart: int = None, stream=None):
-        if x0 is None:
-            self.x.zero_()
-        else:
+        """FGMRES from x0 (None: zero initial guess, no initial SpMV)."""
+        if x0 is not None:
             self.x.copy_(x0)
         return L.fgmres_solve(self.pattern, self.A, self.b, self.x, restart or self.restart, maxit, rtol, self.LU,
-                              self.Dinv, self.prec, apply_sweeps, mode, self.work, stream=stream)
+                              self.Dinv, self.prec, apply_sweeps, mode, self.work, zero_guess=x0 is None,
+                              stream=stream)
 
     def ilu_residual(self, stream=None) -> float:
         return L.abilu_ilu_residual(self.pattern, self.A, self.LU, self.prec, self.work, stream=stream)

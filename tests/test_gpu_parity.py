@@ -108,7 +108,7 @@ def test_empty_matrix():
     e = torch.zeros(1, dtype=torch.float64, device="cuda")
     assert L.abilu_factor(p, e, e, e, "f64", 3, "sync", work) == 0
     assert L.abilu_apply(p, e, e, "f64", e, e.clone(), 3, "sync", work) == 0
-    st, res = L.fgmres_solve(p, e, e, e.clone(), 5, 10, 1e-2, e, e, "f64", 3, "sync", work)
+    st, res = L.fgmres_solve(p, e, e, e.clone(), 5, 10, 1e-2, e, e, "f64", 3, "sync", work, zero_guess=True)
     assert st == 0 and res["converged"] == 1
 
 
@@ -390,6 +390,21 @@ def test_fgmres_restarts_and_noconv():
     assert st == L.ABILU_WARN_NOCONV and not res["converged"] and res["iters"] == 3
 
 
+def test_fgmres_nonzero_initial_guess():
+    """x0 given: the solve starts from r0 = b - A x0 (oracle FGMRES from the same x0)."""
+    c = get("tri40x30_rcm")
+    s = DS(c, "f64", restart=30)
+    s.factor(2, "sync")
+    X, D = s.factor_host()
+    x0 = np.random.default_rng(9).uniform(-1, 1, 4 * c.n)
+    st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-6, maxit=300, x0=torch.from_numpy(x0).cuda())
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, X, D, restart=30, maxit=300, rtol=1e-6, apply_nsw=3,
+                        x0=x0)
+    assert st == 0 and res["converged"] and abs(res["iters"] - ref["iters"]) <= 1
+    if res["iters"] == ref["iters"]:
+        assert rel(s.x.cpu().numpy(), ref["x"]) <= 1e-10
+
+
 def test_fgmres_unpreconditioned_matches_oracle():
     c = W.case("quad", seed=5, nx=12, ny=11, s=0.5)
     s = DS(c, "f64", restart=10)
@@ -429,9 +444,9 @@ def test_full_size_tri2000_f32():
     s = DS(c, "f32", restart=50)
     s.factor(1, "sync")
     X, D = s.factor_host()
-    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
-    print(f"full size f32 factor vs oracle: X {rel(X, Xo):.2e} Dinv {rel(D, Do):.2e}")
-    assert rel(X, Xo) <= 1e-5 and rel(D, Do) <= 1e-5
+    Xo, Do, tx, td = f32_tolerance(c, 1)
+    print(f"full size f32 factor vs oracle: X {rel(X, Xo):.2e} (tol {tx:.1e}) Dinv {rel(D, Do):.2e} (tol {td:.1e})")
+    assert rel(X, Xo) <= tx and rel(D, Do) <= td
     del Xo, Do
     r = np.random.default_rng(0).uniform(-1, 1, 4 * c.n)
     rt = torch.from_numpy(r).cuda()
@@ -441,10 +456,10 @@ def test_full_size_tri2000_f32():
     assert rel(zt.cpu().numpy(), ref) <= 1e-5
     s.spmv(rt, zt)
     assert rel(zt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r)) <= 1e-13
-    for mode in ("sync", "async"):
-        s.factor(1, mode)
+    for mode, nsw in (("async", 1), ("sync", 2)):
+        s.factor(nsw, mode)
         st, res = s.solve(apply_sweeps=3, mode=mode, rtol=1e-2, maxit=500, restart=50)
-        print(mode, res)
+        print(mode, nsw, res)
         assert st == 0 and res["converged"]
     x = s.x.cpu().numpy()
     true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
