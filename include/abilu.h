@@ -11,9 +11,13 @@
  *    rowptr int32[N+1] (rowptr[0] = 0), colidx int32[Z] strictly ascending within each row,
  *    every diagonal block present. Values double[Z][4][4], each block contiguous and row-major.
  *    Vectors double[4N], the 4 unknowns of a cell consecutive.
- *  - Factor: the combined array LU[Z][4][4] shares A's pattern (ILU(0), Section 6): for i > j the
- *    block is L_ij (L has an implicit identity block diagonal), for i <= j it is U_ij.
- *    Dinv[N][4][4] holds U_ii^{-1}. Element type double (ABILU_F64) or float (ABILU_F32).
+ *  - Factor: LU[Z][4][4] holds one block per block of A's pattern (ILU(0), Section 6): L_ij for
+ *    i > j (L has an implicit identity block diagonal) and U_ij for i <= j, stored in the factor
+ *    layout [strictly lower blocks (Z_L) | diagonal blocks U_ii (N) | strictly upper blocks (Z_U)],
+ *    each part in row order (columns ascending within a row). The forward and backward sweeps
+ *    then read one contiguous part each. abilu_factor_to_csr / abilu_factor_from_csr convert to
+ *    and from A's CSR order. Dinv[N][4][4] holds U_ii^{-1}. Element type double (ABILU_F64) or
+ *    float (ABILU_F32).
  *  - Memory: every pointer named d_* is device memory on the current HIP device, allocated and
  *    owned by the caller. The library owns only the pattern object (device arrays plus a small
  *    pinned host buffer); the compute entry points allocate nothing. Scratch space is a
@@ -130,6 +134,14 @@ abilu_status abilu_factor(const abilu_pattern *p, const double *d_A, void *d_LU,
 abilu_status abilu_apply(const abilu_pattern *p, const void *d_LU, const void *d_Dinv,
                          abilu_prec prec, const double *d_r, double *d_z, int32_t nsweeps,
                          abilu_mode mode, void *d_work, size_t work_bytes, void *stream);
+
+/* Permute a factor between the factor layout and A's CSR block order (for inspection, warm
+ * starts from external factors, and verification). d_LU and d_csr: prec[Z][4][4], distinct
+ * buffers. Non-blocking. */
+abilu_status abilu_factor_to_csr(const abilu_pattern *p, abilu_prec prec, const void *d_LU, void *d_csr,
+                                 void *stream);
+abilu_status abilu_factor_from_csr(const abilu_pattern *p, abilu_prec prec, const void *d_csr, void *d_LU,
+                                   void *stream);
 
 /* Block sparse matrix-vector product y = A x in double precision (the Krylov solver's operator,
  * Section 6 setup). d_x and d_y double[4N] must not alias. Non-blocking. */

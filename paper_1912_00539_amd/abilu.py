@@ -66,6 +66,8 @@ def lib():
             "abilu_factor": ([vp, vp, vp, vp, st, i32, st, st, vp, sz, vp], st),
             "abilu_apply": ([vp, vp, vp, st, vp, vp, i32, st, vp, sz, vp], st),
             "abilu_spmv": ([vp, vp, vp, vp, vp], st),
+            "abilu_factor_to_csr": ([vp, st, vp, vp, vp], st),
+            "abilu_factor_from_csr": ([vp, st, vp, vp, vp], st),
             "fgmres_solve": ([vp, vp, vp, vp, i32, i32, C.c_double, vp, vp, st, i32, st, C.c_uint32, vp, sz, vp,
                               C.POINTER(FgmresResult)], st),
             "abilu_ilu_residual": ([vp, vp, vp, st, vp, sz, C.POINTER(C.c_double), vp], st),
@@ -164,6 +166,16 @@ def abilu_apply(p: Pattern, LU, Dinv, prec: str, r, z, nsweeps: int, mode: str, 
     return _check(lib().abilu_apply(p.handle, _ptr(LU), _ptr(Dinv), PRECS[prec], _ptr(r), _ptr(z), int(nsweeps),
                                     MODES[mode], _ptr(work), work.numel() * work.element_size(), _stream(stream)),
                   "abilu_apply")
+
+
+def abilu_factor_to_csr(p: Pattern, prec: str, LU, csr, stream=None) -> int:
+    return _check(lib().abilu_factor_to_csr(p.handle, PRECS[prec], _ptr(LU), _ptr(csr), _stream(stream)),
+                  "abilu_factor_to_csr")
+
+
+def abilu_factor_from_csr(p: Pattern, prec: str, csr, LU, stream=None) -> int:
+    return _check(lib().abilu_factor_from_csr(p.handle, PRECS[prec], _ptr(csr), _ptr(LU), _stream(stream)),
+                  "abilu_factor_from_csr")
 
 
 def abilu_spmv(p: Pattern, A, x, y, stream=None) -> int:

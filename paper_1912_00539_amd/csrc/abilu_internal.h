@@ -17,9 +17,17 @@ struct abilu_pattern {
     int32_t *rowptr = nullptr;    // device [n+1]
     int32_t *colidx = nullptr;    // device [Z]
     int32_t *diag_pos = nullptr;  // device [n]
-    int32_t *pair_ptr = nullptr;  // device [Z+1]
-    int32_t *pik = nullptr;       // device [npairs]
-    int32_t *pkj = nullptr;       // device [npairs]
+    int32_t *pair_ptr = nullptr;  // device [Z+1], indexed by CSR position
+    int32_t *pik = nullptr;       // device [npairs] CSR position of (i,k)
+    int32_t *pkj = nullptr;       // device [npairs] CSR position of (k,j)
+    int32_t *sik = nullptr;       // device [npairs] factor-layout position of (i,k)
+    int32_t *skj = nullptr;       // device [npairs] factor-layout position of (k,j)
+    // factor layout: [strictly lower blocks | diagonal blocks | strictly upper blocks], each part
+    // in row order; lrow/urow are the row offsets inside the lower/upper parts
+    int32_t *lrow = nullptr;      // device [n+1]
+    int32_t *urow = nullptr;      // device [n+1]
+    int32_t *lcol = nullptr;      // device [ZL+1] columns of the lower part (one padding entry)
+    int32_t *ucol = nullptr;      // device [ZU+1] columns of the upper part
     double *pinned = nullptr;     // host pinned, 64 doubles, for blocking scalar reads
     int device = 0;
 };
@@ -92,6 +100,11 @@ abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x,
 
 // ------------------------------------------------------------------ device helpers
 namespace abilu_dev {
+
+// Position in the factor layout of CSR position e of row i (d = diag_pos[i]).
+__device__ __forceinline__ int split_pos(int e, int i, int b0, int d, int lbase, int ubase, int ZL, int n) {
+    return e < d ? lbase + (e - b0) : (e == d ? ZL + i : ZL + n + ubase + (e - d - 1));
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs. Remap so that each XCD walks one
 // contiguous range of block rows: neighbouring rows (whose blocks are gathered) then share

@@ -17,62 +17,134 @@ using namespace abilu_dev;
 
 namespace {
 
+constexpr int RPQ = 2;                       // block rows per quad
+constexpr int ROWS_PER_WG2 = RPQ * ROWS_PER_WG;
+
+// Forward sweep over the strictly lower part of the factor layout (lrow/lcol/Lb).
+// Each quad owns rows ib and ib + 64 and loads two blocks of each per step (clamped, so the
+// loads are branch-free); a row with fewer blocks reads index 0 of the part, which exists
+// whenever the loop runs, and discards the product.
 template <typename T, typename YI, bool EMIT_Z>
-__global__ __launch_bounds__(WG) void k_fwd(int n, const int32_t *__restrict__ rowptr,
-                                            const int32_t *__restrict__ colidx,
-                                            const int32_t *__restrict__ diag_pos, const T *__restrict__ LU,
-                                            const double *__restrict__ rhs, const YI *yin, T *yout,
-                                            const T *__restrict__ Dinv, T *__restrict__ zout) {
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int i = wg * ROWS_PER_WG + (threadIdx.x >> 2);
+__global__ __launch_bounds__(WG) void k_fwd(int n, const int32_t *__restrict__ lrow, const int32_t *__restrict__ lcol,
+                                            const T *__restrict__ Lb, const double *__restrict__ rhs, const YI *yin,
+                                            T *yout, const T *__restrict__ Dinv, T *__restrict__ zout) {
+    const int ib = blockIdx.x * ROWS_PER_WG2 + (threadIdx.x >> 2);
     const int r = threadIdx.x & 3;
-    if (i >= n) return;
-    const int b0 = rowptr[i], d = diag_pos[i];
-    T acc = (T)rhs[(int64_t)i * 4 + r];
-    for (int e = b0; e < d; ++e) {
-        const int j = colidx[e];
-        T l[4], yj[4];
-        load_row(LU + (int64_t)e * BB, r, l);
-        gather_vec((T)yin[(int64_t)j * 4 + r], yj);
-        acc -= l[0] * yj[0] + l[1] * yj[1] + l[2] * yj[2] + l[3] * yj[3];
+    if (ib >= n) return;
+    int ii[RPQ], b0[RPQ], b1[RPQ];
+    T acc[RPQ];
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        ii[h] = ib + h * ROWS_PER_WG;
+        const int i = min(ii[h], n - 1);
+        b0[h] = lrow[i];
+        b1[h] = (ii[h] < n) ? lrow[i + 1] : b0[h];
+        acc[h] = (T)rhs[(int64_t)i * 4 + r];
     }
-    yout[(int64_t)i * 4 + r] = acc;
-    if constexpr (EMIT_Z) {
-        T dr[4], yi[4];
-        load_row(Dinv + (int64_t)i * BB, r, dr);
-        gather_vec(acc, yi);
-        zout[(int64_t)i * 4 + r] = dr[0] * yi[0] + dr[1] * yi[1] + dr[2] * yi[2] + dr[3] * yi[3];
+    int cnt = 0;
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) cnt = max(cnt, b1[h] - b0[h]);
+    for (int t0 = 0; t0 < cnt; t0 += 2) {
+        int j[RPQ][2];
+        T l[RPQ][2][4], yv[RPQ][2];
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = (b1[h] > b0[h]) ? min(b0[h] + t0 + u, b1[h] - 1) : 0;
+                j[h][u] = lcol[e];
+                load_row(Lb + (int64_t)e * BB, r, l[h][u]);
+            }
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) yv[h][u] = (T)yin[(int64_t)j[h][u] * 4 + r];
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                T yj[4];
+                gather_vec(yv[h][u], yj);
+                const T c = l[h][u][0] * yj[0] + l[h][u][1] * yj[1] + l[h][u][2] * yj[2] + l[h][u][3] * yj[3];
+                acc[h] -= (b0[h] + t0 + u < b1[h]) ? c : T(0);
+            }
+    }
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        if (ii[h] < n) {
+            yout[(int64_t)ii[h] * 4 + r] = acc[h];
+            if constexpr (EMIT_Z) {
+                T dr[4], yi[4];
+                load_row(Dinv + (int64_t)ii[h] * BB, r, dr);
+                gather_vec(acc[h], yi);
+                zout[(int64_t)ii[h] * 4 + r] = dr[0] * yi[0] + dr[1] * yi[1] + dr[2] * yi[2] + dr[3] * yi[3];
+            }
+        }
     }
 }
 
+// Backward sweep over the strictly upper part (urow/ucol/Ub), then z_i = Dinv_i (y_i - sum).
 // OFFDIAG = false: z = Dinv y only. DUAL: also store z (precision T) into zout2.
 template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
-__global__ __launch_bounds__(WG) void k_bwd(int n, const int32_t *__restrict__ rowptr,
-                                            const int32_t *__restrict__ colidx,
-                                            const int32_t *__restrict__ diag_pos, const T *__restrict__ LU,
-                                            const T *__restrict__ Dinv, const YI *__restrict__ y, const T *zin,
-                                            ZO *zout, T *zout2) {
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int i = wg * ROWS_PER_WG + (threadIdx.x >> 2);
+__global__ __launch_bounds__(WG) void k_bwd(int n, const int32_t *__restrict__ urow, const int32_t *__restrict__ ucol,
+                                            const T *__restrict__ Ub, const T *__restrict__ Dinv,
+                                            const YI *__restrict__ y, const T *zin, ZO *zout, T *zout2) {
+    const int ib = blockIdx.x * ROWS_PER_WG2 + (threadIdx.x >> 2);
     const int r = threadIdx.x & 3;
-    if (i >= n) return;
-    T acc = (T)y[(int64_t)i * 4 + r];
-    if constexpr (OFFDIAG) {
-        const int d = diag_pos[i], b1 = rowptr[i + 1];
-        for (int e = d + 1; e < b1; ++e) {
-            const int j = colidx[e];
-            T u[4], zj[4];
-            load_row(LU + (int64_t)e * BB, r, u);
-            gather_vec(zin[(int64_t)j * 4 + r], zj);
-            acc -= u[0] * zj[0] + u[1] * zj[1] + u[2] * zj[2] + u[3] * zj[3];
+    if (ib >= n) return;
+    int ii[RPQ], b0[RPQ], b1[RPQ];
+    T acc[RPQ];
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        ii[h] = ib + h * ROWS_PER_WG;
+        const int i = min(ii[h], n - 1);
+        acc[h] = (T)y[(int64_t)i * 4 + r];
+        if constexpr (OFFDIAG) {
+            b0[h] = urow[i];
+            b1[h] = (ii[h] < n) ? urow[i + 1] : b0[h];
         }
     }
-    T dr[4], a[4];
-    load_row(Dinv + (int64_t)i * BB, r, dr);
-    gather_vec(acc, a);
-    const T z = dr[0] * a[0] + dr[1] * a[1] + dr[2] * a[2] + dr[3] * a[3];
-    zout[(int64_t)i * 4 + r] = (ZO)z;
-    if constexpr (DUAL) zout2[(int64_t)i * 4 + r] = z;
+    if constexpr (OFFDIAG) {
+        int cnt = 0;
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h) cnt = max(cnt, b1[h] - b0[h]);
+        for (int t0 = 0; t0 < cnt; t0 += 2) {
+            int j[RPQ][2];
+            T u4[RPQ][2][4], zv[RPQ][2];
+#pragma unroll
+            for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int e = (b1[h] > b0[h]) ? min(b0[h] + t0 + u, b1[h] - 1) : 0;
+                    j[h][u] = ucol[e];
+                    load_row(Ub + (int64_t)e * BB, r, u4[h][u]);
+                }
+#pragma unroll
+            for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) zv[h][u] = zin[(int64_t)j[h][u] * 4 + r];
+#pragma unroll
+            for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    T zj[4];
+                    gather_vec(zv[h][u], zj);
+                    const T c = u4[h][u][0] * zj[0] + u4[h][u][1] * zj[1] + u4[h][u][2] * zj[2] + u4[h][u][3] * zj[3];
+                    acc[h] -= (b0[h] + t0 + u < b1[h]) ? c : T(0);
+                }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        if (ii[h] < n) {
+            T dr[4], a[4];
+            load_row(Dinv + (int64_t)ii[h] * BB, r, dr);
+            gather_vec(acc[h], a);
+            const T z = dr[0] * a[0] + dr[1] * a[1] + dr[2] * a[2] + dr[3] * a[3];
+            zout[(int64_t)ii[h] * 4 + r] = (ZO)z;
+            if constexpr (DUAL) zout2[(int64_t)ii[h] * 4 + r] = z;
+        }
+    }
 }
 
 template <typename T>
@@ -81,26 +153,56 @@ __global__ void k_fill(int64_t len, T *v, T val) {
     if (t < len) v[t] = val;
 }
 
-// y = A x  (RESID: y = b - A x), double precision
+// y = A x  (RESID: y = b - A x), double precision, CSR; two rows per quad, two blocks per step
 template <bool RESID>
 __global__ __launch_bounds__(WG) void k_spmv(int n, const int32_t *__restrict__ rowptr,
                                              const int32_t *__restrict__ colidx, const double *__restrict__ A,
                                              const double *__restrict__ x, double *__restrict__ y,
                                              const double *__restrict__ b) {
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int i = wg * ROWS_PER_WG + (threadIdx.x >> 2);
+    const int ib = blockIdx.x * ROWS_PER_WG2 + (threadIdx.x >> 2);
     const int r = threadIdx.x & 3;
-    if (i >= n) return;
-    const int b0 = rowptr[i], b1 = rowptr[i + 1];
-    double acc = 0.0;
-    for (int e = b0; e < b1; ++e) {
-        const int j = colidx[e];
-        double a[4], xj[4];
-        load_row(A + (int64_t)e * BB, r, a);
-        gather_vec(x[(int64_t)j * 4 + r], xj);
-        acc += a[0] * xj[0] + a[1] * xj[1] + a[2] * xj[2] + a[3] * xj[3];
+    if (ib >= n) return;
+    int ii[RPQ], b0[RPQ], b1[RPQ];
+    double acc[RPQ];
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        ii[h] = ib + h * ROWS_PER_WG;
+        const int i = min(ii[h], n - 1);
+        b0[h] = rowptr[i];
+        b1[h] = (ii[h] < n) ? rowptr[i + 1] : b0[h];
+        acc[h] = 0.0;
     }
-    y[(int64_t)i * 4 + r] = RESID ? b[(int64_t)i * 4 + r] - acc : acc;
+    int cnt = 0;
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) cnt = max(cnt, b1[h] - b0[h]);
+    for (int t0 = 0; t0 < cnt; t0 += 2) {
+        int j[RPQ][2];
+        double a[RPQ][2][4], xv[RPQ][2];
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = (b1[h] > b0[h]) ? min(b0[h] + t0 + u, b1[h] - 1) : 0;
+                j[h][u] = colidx[e];
+                load_row(A + (int64_t)e * BB, r, a[h][u]);
+            }
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) xv[h][u] = x[(int64_t)j[h][u] * 4 + r];
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                double xj[4];
+                gather_vec(xv[h][u], xj);
+                const double c = a[h][u][0] * xj[0] + a[h][u][1] * xj[1] + a[h][u][2] * xj[2] + a[h][u][3] * xj[3];
+                acc[h] += (b0[h] + t0 + u < b1[h]) ? c : 0.0;
+            }
+    }
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h)
+        if (ii[h] < n) y[(int64_t)ii[h] * 4 + r] = RESID ? b[(int64_t)ii[h] * 4 + r] - acc[h] : acc[h];
 }
 
 template <typename T>
@@ -111,16 +213,16 @@ template <>
 const char *tname<double>() { return "f64"; }
 
 // Algorithmic bytes of one launch (every element touched once; gathered vector entries once).
-// forward: rowptr[i], diag_pos[i], colidx and blocks of the strict lower part, r (f64),
+// forward: lrow, columns and blocks of the strictly lower part, r (f64),
 // input vector (element size sY), output vector; EMIT_Z adds Dinv and the z output.
 double bytes_fwd(const Sizes &z, double sF, double sY, bool emit) {
-    double b = 8 * z.N + 4 * z.ZL + 16 * sF * z.ZL + 32 * z.N + 4 * z.N * sY + 4 * z.N * sF;
+    double b = 4 * (z.N + 1) + 4 * z.ZL + 16 * sF * z.ZL + 32 * z.N + 4 * z.N * sY + 4 * z.N * sF;
     return emit ? b + 16 * sF * z.N + 4 * z.N * sF : b;
 }
-// backward: diag_pos[i], rowptr[i+1], colidx and blocks of the strict upper part, y, z input,
+// backward: urow, columns and blocks of the strictly upper part, y, z input,
 // Dinv, output (element size sZ), optional second output in precision sF
 double bytes_bwd(const Sizes &z, double sF, double sZ, bool dual) {
-    double b = 8 * z.N + 4 * z.ZU + 16 * sF * z.ZU + 4 * z.N * sF + 4 * z.N * sF + 16 * sF * z.N + 4 * z.N * sZ;
+    double b = 4 * (z.N + 1) + 4 * z.ZU + 16 * sF * z.ZU + 4 * z.N * sF + 4 * z.N * sF + 16 * sF * z.N + 4 * z.N * sZ;
     return dual ? b + 4 * z.N * sF : b;
 }
 
@@ -128,8 +230,11 @@ template <typename T>
 abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const double *r, double *z, int nsw,
                      abilu_mode mode, char *work, const Workspace &W, hipStream_t s) {
     const int n = p->n;
-    const int grid = div_up(n, ROWS_PER_WG);
+    const int grid = div_up(n, ROWS_PER_WG2);
     const int64_t nv = 4 * (int64_t)n;
+    const T *Lb = LU;                                              // strictly lower part
+    const T *Ub = LU + ((int64_t)p->nnzb_lower + n) * BB;          // strictly upper part
+    const int32_t *lrow = p->lrow, *lcol = p->lcol, *urow = p->urow, *ucol = p->ucol;
     T *ya = (T *)(work + W.ya), *yb = (T *)(work + W.yb);
     T *za = (T *)(work + W.za), *zb = (T *)(work + W.zb);
     char name[64];
@@ -145,8 +250,8 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
     if (mode == ABILU_SYNC) {
         if (nsw == 1) {
             ProfScope ps(NAME("apply_diag"), s, 32 * zz.N + 16 * sF * zz.N + 32 * zz.N);
-            k_bwd<T, double, double, false, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU,
-                                                                       Dinv, r, (const T *)nullptr, z, (T *)nullptr);
+            k_bwd<T, double, double, false, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, r, (const T *)nullptr, z,
+                                                                       (T *)nullptr);
             LAUNCHED();
             return ABILU_OK;
         }
@@ -159,18 +264,14 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
             ProfScope ps(NAME(last ? "apply_fwd_emitz" : "apply_fwd"), s, bytes_fwd(zz, sF, q == 2 ? 8 : sF, last));
             if (q == 2) {
                 if (last)
-                    k_fwd<T, double, true><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, r, ycur,
-                                                               Dinv, za);
+                    k_fwd<T, double, true><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, r, ycur, Dinv, za);
                 else
-                    k_fwd<T, double, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, r, ycur,
-                                                                Dinv, (T *)nullptr);
+                    k_fwd<T, double, false><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, r, ycur, Dinv, (T *)nullptr);
             } else {
                 if (last)
-                    k_fwd<T, T, true><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, yprev, ycur,
-                                                          Dinv, za);
+                    k_fwd<T, T, true><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, yprev, ycur, Dinv, za);
                 else
-                    k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, yprev, ycur,
-                                                           Dinv, (T *)nullptr);
+                    k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, yprev, ycur, Dinv, (T *)nullptr);
             }
             LAUNCHED();
             yprev = ycur;
@@ -181,12 +282,10 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
         for (int q = 2; q <= nsw; ++q) {
             ProfScope ps(NAME("apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, false));
             if (q == nsw) {
-                k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, Dinv,
-                                                                     yfin, zprev, z, (T *)nullptr);
+                k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, (T *)nullptr);
             } else {
                 T *zcur = (zprev == za) ? zb : za;
-                k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, Dinv,
-                                                                yfin, zprev, zcur, (T *)nullptr);
+                k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, zcur, (T *)nullptr);
                 zprev = zcur;
             }
             LAUNCHED();
@@ -204,18 +303,15 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
     }
     for (int q = 1; q <= nsw; ++q) {
         ProfScope ps(NAME("apply_fwd"), s, bytes_fwd(zz, sF, sF, false));
-        k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, r, ya, ya, Dinv,
-                                               (T *)nullptr);
+        k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, ya, ya, Dinv, (T *)nullptr);
         LAUNCHED();
     }
     for (int q = 1; q <= nsw; ++q) {
         ProfScope ps(NAME("apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, q == nsw));
         if (q == nsw)
-            k_bwd<T, T, double, true, true><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, Dinv, ya,
-                                                                za, z, za);
+            k_bwd<T, T, double, true, true><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, z, za);
         else
-            k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, LU, Dinv, ya, za,
-                                                            za, (T *)nullptr);
+            k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, za, (T *)nullptr);
         LAUNCHED();
     }
     return ABILU_OK;
@@ -243,7 +339,7 @@ abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv
 abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x, double *y, const double *b,
                        hipStream_t s) {
     if (p->n == 0) return ABILU_OK;
-    const int grid = div_up(p->n, ROWS_PER_WG);
+    const int grid = div_up(p->n, ROWS_PER_WG2);
     const Sizes z = sizes(p);
     // rowptr, colidx, A (f64), x gathered once, y written (+ b read)
     const double by = 4 * (z.N + 1) + 4 * z.Z + 128 * z.Z + 32 * z.N + 32 * z.N;

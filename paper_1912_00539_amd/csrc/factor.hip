@@ -4,21 +4,26 @@
 //   H_ij(X) = (A_ij - sum_{k in K(i,j)} X_ik X_kj) X_jj^{-1}   for i > j
 //   H_ij(X) =  A_ij - sum_{k in K(i,j)} X_ik X_kj              for i <= j
 // One sweep evaluates H for every block at once. The diagonal inverses are carried as a second
-// array Dinv (the exact 4x4 inversion of each diagonal block, fused into the sweep: the quad
-// that produces U_ii inverts it on the spot).
+// array Dinv (the exact 4x4 inversion of each diagonal block, fused into the sweep: the quad that
+// produces U_ii inverts it on the spot).
+//
+// Factor layout: [strictly lower blocks | diagonal blocks | strictly upper blocks], each part in
+// row order, so the forward and backward apply sweeps stream one contiguous part each. A stays in
+// CSR order. X_ik is always a strictly lower block of row i; X_kj lies in row k < i.
 //
 // Mapping: one quad of 4 lanes per block row i; lane r owns row r of every 4x4 block of the row
-// (so a block is one contiguous 64/128-byte access by the quad) and rows of other blocks are
-// exchanged inside the quad by DPP broadcasts. 64 block rows per 256-thread workgroup; the
-// workgroup index is remapped so each XCD sweeps one contiguous range of rows.
+// (a block is one contiguous 64/128-byte access by the quad) and rows of other blocks come from
+// the quad by DPP broadcasts. A row's blocks are processed in chunks of CH with branch-free
+// (clamped) loads so that several block loads are in flight per lane.
 //
-// SYNC: reads only X^p, Dinv^p and writes X^{p+1}, Dinv^{p+1} (ping-pong buffers): the
-//       Jacobi-type iteration x^{p+1} = h(x^p). Deterministic.
-// ASYNC: X and Dinv are updated in place; reads see whatever value is in memory (possibly a
-//       block that another quad is writing: torn reads are allowed because each scalar has its
-//       own delay in the block-asynchronous model). Within a row the blocks are visited in
-//       ascending column order, so U_ii uses the L_ik just computed by the same quad. Sums are
-//       accumulated in registers and stored once; no atomics on factor values.
+// SYNC : reads only X^p, Dinv^p and writes X^{p+1}, Dinv^{p+1} (ping-pong buffers): the
+//        Jacobi-type iteration x^{p+1} = h(x^p). Deterministic.
+// ASYNC: X and Dinv are updated in place; reads see whatever value is in memory (possibly a block
+//        another quad is writing: torn reads are allowed since every scalar has its own delay in
+//        the block-asynchronous model). Blocks of a row are updated in ascending column order, so
+//        U_ii uses the L_ik this quad has just written. The first sweep from A reads the X_kj of
+//        other rows from A itself (the initial guess, the oldest admissible value) and so needs no
+//        copy of A into X. Sums are accumulated in registers and stored once; no atomics on values.
 #include "abilu_internal.h"
 
 using namespace abilu;
@@ -26,26 +31,55 @@ using namespace abilu_dev;
 
 namespace {
 
-// X0 -> (optional) copy into Xout in precision T, and D0 = inverses of X0's diagonal blocks.
-template <typename T, typename S, bool COPY>
-__global__ __launch_bounds__(WG) void k_factor_init(int n, const int32_t *__restrict__ rowptr,
+constexpr int CH = 2;   // blocks of a row loaded together
+
+template <typename T, typename S>
+__device__ __forceinline__ void load_block_row(const S *base, int64_t pos, int r, T (&v)[4]) {
+    load_row(base + pos * BB, r, v);
+}
+
+// t -= sum over the update set [p0, p1) of X_ik X_kj (this lane's row of the products).
+// L_ik from XL at factor-layout positions (or from A at CSR positions when L_FROM_A),
+// X_kj from XU likewise (or A when U_FROM_A).
+template <typename T, bool L_FROM_A, bool U_FROM_A>
+__device__ __forceinline__ void update_terms(int p0, int p1, int r, const int32_t *__restrict__ pik,
+                                             const int32_t *__restrict__ pkj, const int32_t *__restrict__ sik,
+                                             const int32_t *__restrict__ skj, const double *__restrict__ A,
+                                             const T *XL, const T *XU, T (&t)[4]) {
+    for (int q = p0; q < p1; ++q) {
+        T l[4], u[4];
+        if constexpr (L_FROM_A) load_block_row(A, pik[q], r, l);
+        else load_block_row(XL, sik[q], r, l);
+        if constexpr (U_FROM_A) load_block_row(A, pkj[q], r, u);
+        else load_block_row(XU, skj[q], r, u);
+        row_times_block_sub(l, u, t);
+    }
+}
+
+// X0 -> (optional) copy into Xout in factor layout, and D0 = inverses of X0's diagonal blocks.
+// SRC_CSR: X0 is A (CSR order, double); otherwise X0 is a factor-layout array of T.
+template <typename T, typename S, bool SRC_CSR, bool COPY>
+__global__ __launch_bounds__(WG) void k_factor_init(int n, int ZL, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ diag_pos,
-                                                    const S *X0, T *Xout, T *D0, unsigned *flags) {
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int i = wg * ROWS_PER_WG + (threadIdx.x >> 2);
+                                                    const int32_t *__restrict__ lrow,
+                                                    const int32_t *__restrict__ urow, const S *X0, T *Xout, T *D0,
+                                                    unsigned *flags) {
+    const int i = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
     const int r = threadIdx.x & 3;
     if (i >= n) return;
-    const int d = diag_pos[i];
     if constexpr (COPY) {
-        const int b0 = rowptr[i], b1 = rowptr[i + 1];
+        static_assert(SRC_CSR, "copy reads A");
+        const int b0 = rowptr[i], d = diag_pos[i], b1 = rowptr[i + 1];
+        const int lb = lrow[i], ub = urow[i];
         for (int e = b0; e < b1; ++e) {
             T v[4];
             load_row(X0 + (int64_t)e * BB, r, v);
-            store_row(Xout + (int64_t)e * BB, r, v);
+            store_row(Xout + (int64_t)split_pos(e, i, b0, d, lb, ub, ZL, n) * BB, r, v);
         }
     }
+    const int64_t dpos = SRC_CSR ? (int64_t)diag_pos[i] : (int64_t)ZL + i;
     T u[4], M[16], R[16], out[4];
-    load_row(X0 + (int64_t)d * BB, r, u);
+    load_row(X0 + dpos * BB, r, u);
     gather_block(u, M);
     bool ok = inv4(M, R);
     pick_row(R, r, out);
@@ -53,53 +87,61 @@ __global__ __launch_bounds__(WG) void k_factor_init(int n, const int32_t *__rest
     if (!ok && r == 0) atomicOr(flags, ABILU_FLAG_MODIFIED);
 }
 
-// t -= sum over the update set of block e of X_ik X_kj (this lane's row of the product)
-template <typename T, typename S>
-__device__ __forceinline__ void update_terms(int e, int r, const int32_t *__restrict__ pair_ptr,
-                                             const int32_t *__restrict__ pik,
-                                             const int32_t *__restrict__ pkj, const S *Xp, T (&t)[4]) {
-    const int p0 = pair_ptr[e], p1 = pair_ptr[e + 1];
-    for (int p = p0; p < p1; ++p) {
-        const int ik = pik[p], kj = pkj[p];
-        T l[4], u[4];
-        load_row(Xp + (int64_t)ik * BB, r, l);
-        load_row(Xp + (int64_t)kj * BB, r, u);
-        row_times_block_sub(l, u, t);
-    }
-}
-
-// One sweep. S = element type of the iterate read (double when the iterate is A itself).
-template <typename T, typename S>
+// One sweep.
+template <typename T, bool L_FROM_A, bool U_FROM_A>
 __global__ __launch_bounds__(WG) void k_factor_sweep(
-    int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ pair_ptr,
-    const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj, const double *__restrict__ A,
-    const S *Xp, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int i = wg * ROWS_PER_WG + (threadIdx.x >> 2);
+    int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+    const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
+    const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
+    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
+    const int i = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
     const int r = threadIdx.x & 3;
     if (i >= n) return;
     const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
+    const int lbase = lrow[i], ubase = urow[i];
+    // update-set extents: lower blocks [pb0, pd), diagonal [pd, pd1), upper [pd1, pb1)
+    const int pb0 = pair_ptr[b0], pd = pair_ptr[d], pd1 = pair_ptr[d + 1], pb1 = pair_ptr[b1];
+    T *XnL = Xn + (int64_t)lbase * BB;
+    T *XnU = Xn + ((int64_t)ZL + n + ubase) * BB;
     unsigned fl = 0;
+
     // strictly lower blocks: L_ij = (A_ij - sum) U_jj^{-1}
-    for (int e = b0; e < d; ++e) {
-        T t[4];
-        load_row(A + (int64_t)e * BB, r, t);
-        update_terms(e, r, pair_ptr, pik, pkj, Xp, t);
-        const int j = colidx[e];
-        T dr[4], x[4];
-        load_row(Dp + (int64_t)j * BB, r, dr);
-        row_times_block(t, dr, x);
-        fl |= nonfinite4(x);
-        store_row(Xn + (int64_t)e * BB, r, x);
+    for (int e0 = b0; e0 < d; e0 += CH) {
+        T t[CH][4], dr[CH][4];
+        int j[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = min(e0 + u, d - 1);
+            load_row(A + (int64_t)e * BB, r, t[u]);
+            j[u] = colidx[e];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) load_row(Dp + (int64_t)j[u] * BB, r, dr[u]);
+        if (pd > pb0) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (e0 + u < d)
+                    update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
+                                                        skj, A, XL, XU, t[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            T x[4];
+            row_times_block(t[u], dr[u], x);
+            if (e0 + u < d) {
+                fl |= nonfinite4(x);
+                store_row(XnL + (int64_t)(e0 + u - b0) * BB, r, x);
+            }
+        }
     }
     // diagonal block U_ii = A_ii - sum, and its inverse
     {
         T t[4];
         load_row(A + (int64_t)d * BB, r, t);
-        update_terms(d, r, pair_ptr, pik, pkj, Xp, t);
+        update_terms<T, L_FROM_A, U_FROM_A>(pd, pd1, r, pik, pkj, sik, skj, A, XL, XU, t);
         fl |= nonfinite4(t);
-        store_row(Xn + (int64_t)d * BB, r, t);
+        store_row(Xn + ((int64_t)ZL + i) * BB, r, t);
         T M[16], R[16], out[4];
         gather_block(t, M);
         if (!inv4(M, R)) fl |= ABILU_FLAG_MODIFIED;
@@ -107,14 +149,45 @@ __global__ __launch_bounds__(WG) void k_factor_sweep(
         store_row(Dn + (int64_t)i * BB, r, out);
     }
     // strictly upper blocks: U_ij = A_ij - sum
-    for (int e = d + 1; e < b1; ++e) {
-        T t[4];
-        load_row(A + (int64_t)e * BB, r, t);
-        update_terms(e, r, pair_ptr, pik, pkj, Xp, t);
-        fl |= nonfinite4(t);
-        store_row(Xn + (int64_t)e * BB, r, t);
+    for (int e0 = d + 1; e0 < b1; e0 += CH) {
+        T t[CH][4];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) load_row(A + (int64_t)min(e0 + u, b1 - 1) * BB, r, t[u]);
+        if (pb1 > pd1) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (e0 + u < b1)
+                    update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
+                                                        skj, A, XL, XU, t[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (e0 + u < b1) {
+                fl |= nonfinite4(t[u]);
+                store_row(XnU + (int64_t)(e0 + u - d - 1) * BB, r, t[u]);
+            }
+        }
     }
     if (fl) atomicOr(flags, fl);
+}
+
+// Conversions between the factor layout and CSR order (one quad per block row).
+template <typename T, bool TO_CSR>
+__global__ __launch_bounds__(WG) void k_factor_permute(int n, int ZL, const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ diag_pos,
+                                                       const int32_t *__restrict__ lrow,
+                                                       const int32_t *__restrict__ urow, const T *__restrict__ src,
+                                                       T *__restrict__ dst) {
+    const int i = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (i >= n) return;
+    const int b0 = rowptr[i], d = diag_pos[i], b1 = rowptr[i + 1];
+    for (int e = b0; e < b1; ++e) {
+        const int64_t sp = split_pos(e, i, b0, d, lrow[i], urow[i], ZL, n);
+        T v[4];
+        load_row(src + (TO_CSR ? sp : (int64_t)e) * BB, r, v);
+        store_row(dst + (TO_CSR ? (int64_t)e : sp) * BB, r, v);
+    }
 }
 
 template <typename T>
@@ -125,25 +198,35 @@ template <>
 const char *tname<double>() { return "f64"; }
 
 // Algorithmic bytes of one launch: every array element touched once.
-// init with copy: rowptr, diag_pos, A (f64), X0 written, Dinv written
+// init with copy: rowptr, diag_pos, lrow, urow, A (f64), X0 written, Dinv written
 // init without copy: diag_pos, diagonal blocks of the source, Dinv written
 double bytes_init(const Sizes &z, double sS, double sF, bool copy) {
-    if (copy) return 4 * (z.N + 1) + 4 * z.N + 128 * z.Z + 16 * sF * z.Z + 16 * sF * z.N;
+    if (copy) return 4 * (z.N + 1) + 12 * z.N + 128 * z.Z + 16 * sF * z.Z + 16 * sF * z.N;
     return 4 * z.N + 16 * sS * z.N + 16 * sF * z.N;
 }
-// sweep: rowptr, diag_pos, colidx of strictly lower blocks, pair_ptr, pair lists, A (f64),
-// the blocks the update sets read (min(2P, Z) of them; none extra when they are A's own),
-// Dinv read, X written, Dinv written
-double bytes_sweep(const Sizes &z, double sF, bool fromA) {
-    const double xr = fromA ? 0.0 : 16 * sF * (2 * z.P < z.Z ? 2 * z.P : z.Z);
-    return 4 * (z.N + 1) + 4 * z.N + 4 * z.ZL + 4 * (z.Z + 1) + 8 * z.P + 128 * z.Z + xr + 16 * sF * z.N +
+// sweep: rowptr, diag_pos, lrow, urow, colidx of strictly lower blocks, pair_ptr at 4 places per
+// row, the pair lists, A (f64), the blocks the update sets read from X (min(2P, Z) of them, half
+// on each side; none when a side comes from A), Dinv read, X written, Dinv written
+double bytes_sweep(const Sizes &z, double sF, bool l_from_a, bool u_from_a) {
+    const double m = (2 * z.P < z.Z ? 2 * z.P : z.Z) / 2;
+    const double xr = (l_from_a ? 0.0 : 16 * sF * m) + (u_from_a ? 0.0 : 16 * sF * m);
+    return 4 * (z.N + 1) + 12 * z.N + 4 * z.ZL + 16 * z.N + 8 * z.P + 128 * z.Z + xr + 16 * sF * z.N +
            16 * sF * z.Z + 16 * sF * z.N;
+}
+
+template <typename T, bool LA, bool UA>
+void launch_sweep(const abilu_pattern *p, int grid, hipStream_t s, const double *A, const T *XL, const T *XU,
+                  const T *Dp, T *Xn, T *Dn, unsigned *flags) {
+    k_factor_sweep<T, LA, UA><<<grid, WG, 0, s>>>(p->n, (int)p->nnzb_lower, p->rowptr, p->colidx, p->diag_pos,
+                                                   p->lrow, p->urow, p->pair_ptr, p->pik, p->pkj, p->sik, p->skj, A,
+                                                   XL, XU, Dp, Xn, Dn, flags);
 }
 
 template <typename T>
 abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, int nsw, abilu_mode mode,
                       abilu_init init, char *work, const Workspace &W, hipStream_t s) {
     const int n = p->n;
+    const int ZL = (int)p->nnzb_lower;
     const int grid = div_up(n, ROWS_PER_WG);
     unsigned *flags = (unsigned *)(work + W.flags);
     T *X1 = (T *)(work + W.x2);
@@ -155,22 +238,51 @@ abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, i
     };
     const Sizes z = sizes(p);
     const double sF = sizeof(T);
+#define LAUNCHED() \
+    if (launch_status() != ABILU_OK) return ABILU_EDEVICE
 
-    if (mode == ABILU_ASYNC || nsw == 0) {
-        // X0 in d_LU, D0 in d_Dinv, then in-place sweeps
+    auto init_dinv_A = [&](T *D0) -> abilu_status {
+        ProfScope ps(NAME("factor_init", ""), s, bytes_init(z, 8, sF, false));
+        k_factor_init<T, double, true, false><<<grid, WG, 0, s>>>(n, ZL, p->rowptr, p->diag_pos, p->lrow, p->urow, A,
+                                                                  (T *)nullptr, D0, flags);
+        LAUNCHED();
+        return ABILU_OK;
+    };
+    auto init_dinv_X = [&](const T *X0, T *D0) -> abilu_status {
+        ProfScope ps(NAME("factor_init", ""), s, bytes_init(z, sF, sF, false));
+        k_factor_init<T, T, false, false><<<grid, WG, 0, s>>>(n, ZL, p->rowptr, p->diag_pos, p->lrow, p->urow, X0,
+                                                              (T *)nullptr, D0, flags);
+        LAUNCHED();
+        return ABILU_OK;
+    };
+    abilu_status st;
+
+    if (nsw == 0) {
         if (init == ABILU_INIT_FROM_A) {
             ProfScope ps(NAME("factor_init", "_copy"), s, bytes_init(z, 8, sF, true));
-            k_factor_init<T, double, true><<<grid, WG, 0, s>>>(n, p->rowptr, p->diag_pos, A, LU, Dinv, flags);
-        } else {
-            ProfScope ps(NAME("factor_init", ""), s, bytes_init(z, sF, sF, false));
-            k_factor_init<T, T, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->diag_pos, LU, (T *)nullptr, Dinv, flags);
+            k_factor_init<T, double, true, true><<<grid, WG, 0, s>>>(n, ZL, p->rowptr, p->diag_pos, p->lrow, p->urow,
+                                                                     A, LU, Dinv, flags);
+            LAUNCHED();
+            return ABILU_OK;
         }
-        if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
-        for (int q = 0; q < nsw; ++q) {
-            ProfScope ps(NAME("factor_sweep", "_async"), s, bytes_sweep(z, sF, false));
-            k_factor_sweep<T, T><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, p->pair_ptr, p->pik,
-                                                     p->pkj, A, LU, Dinv, LU, Dinv, flags);
-            if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+        return init_dinv_X(LU, Dinv);
+    }
+
+    if (mode == ABILU_ASYNC) {
+        int q0 = 0;
+        if (init == ABILU_INIT_FROM_A) {
+            if ((st = init_dinv_A(Dinv)) != ABILU_OK) return st;
+            ProfScope ps(NAME("factor_sweep", "_async_fromA"), s, bytes_sweep(z, sF, false, true));
+            launch_sweep<T, false, true>(p, grid, s, A, LU, (const T *)nullptr, Dinv, LU, Dinv, flags);
+            LAUNCHED();
+            q0 = 1;
+        } else if ((st = init_dinv_X(LU, Dinv)) != ABILU_OK) {
+            return st;
+        }
+        for (int q = q0; q < nsw; ++q) {
+            ProfScope ps(NAME("factor_sweep", "_async"), s, bytes_sweep(z, sF, false, false));
+            launch_sweep<T, false, false>(p, grid, s, A, LU, LU, Dinv, LU, Dinv, flags);
+            LAUNCHED();
         }
         return ABILU_OK;
     }
@@ -180,16 +292,11 @@ abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, i
     auto outD = [&](int q) { return ((nsw - q) % 2 == 0) ? Dinv : D1; };
     T *D0 = outD(0);
     if (init == ABILU_INIT_FROM_A) {
-        {
-            ProfScope ps(NAME("factor_init", ""), s, bytes_init(z, 8, sF, false));
-            k_factor_init<T, double, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->diag_pos, A, (T *)nullptr, D0, flags);
-        }
-        if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
-        {
-            ProfScope ps(NAME("factor_sweep", "_sync_fromA"), s, bytes_sweep(z, sF, true));
-            k_factor_sweep<T, double><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, p->pair_ptr,
-                                                          p->pik, p->pkj, A, A, D0, outX(1), outD(1), flags);
-        }
+        if ((st = init_dinv_A(D0)) != ABILU_OK) return st;
+        ProfScope ps(NAME("factor_sweep", "_sync_fromA"), s, bytes_sweep(z, sF, true, true));
+        launch_sweep<T, true, true>(p, grid, s, A, (const T *)nullptr, (const T *)nullptr, D0, outX(1), outD(1),
+                                    flags);
+        LAUNCHED();
     } else {
         // warm start: X0 = d_LU. Sweep 1 must not write where it reads.
         T *X0 = LU;
@@ -199,25 +306,30 @@ abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, i
                 return ABILU_EDEVICE;
             X0 = X1;
         }
-        {
-            ProfScope ps(NAME("factor_init", ""), s, bytes_init(z, sF, sF, false));
-            k_factor_init<T, T, false><<<grid, WG, 0, s>>>(n, p->rowptr, p->diag_pos, X0, (T *)nullptr, D0, flags);
-        }
-        if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
-        {
-            ProfScope ps(NAME("factor_sweep", "_sync"), s, bytes_sweep(z, sF, false));
-            k_factor_sweep<T, T><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, p->pair_ptr, p->pik,
-                                                     p->pkj, A, X0, D0, outX(1), outD(1), flags);
-        }
+        if ((st = init_dinv_X(X0, D0)) != ABILU_OK) return st;
+        ProfScope ps(NAME("factor_sweep", "_sync"), s, bytes_sweep(z, sF, false, false));
+        launch_sweep<T, false, false>(p, grid, s, A, X0, X0, D0, outX(1), outD(1), flags);
+        LAUNCHED();
     }
-    if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
     for (int q = 2; q <= nsw; ++q) {
-        ProfScope ps(NAME("factor_sweep", "_sync"), s, bytes_sweep(z, sF, false));
-        k_factor_sweep<T, T><<<grid, WG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, p->pair_ptr, p->pik, p->pkj,
-                                                 A, outX(q - 1), outD(q - 1), outX(q), outD(q), flags);
-        if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+        ProfScope ps(NAME("factor_sweep", "_sync"), s, bytes_sweep(z, sF, false, false));
+        launch_sweep<T, false, false>(p, grid, s, A, outX(q - 1), outX(q - 1), outD(q - 1), outX(q), outD(q), flags);
+        LAUNCHED();
     }
     return ABILU_OK;
+#undef LAUNCHED
+}
+
+template <typename T>
+abilu_status permute_t(const abilu_pattern *p, const T *src, T *dst, bool to_csr, hipStream_t s) {
+    const int grid = div_up(p->n, ROWS_PER_WG);
+    const int ZL = (int)p->nnzb_lower;
+    ProfScope ps(to_csr ? "factor_to_csr" : "factor_from_csr", s, 2.0 * 16 * sizeof(T) * (double)p->nnzb);
+    if (to_csr)
+        k_factor_permute<T, true><<<grid, WG, 0, s>>>(p->n, ZL, p->rowptr, p->diag_pos, p->lrow, p->urow, src, dst);
+    else
+        k_factor_permute<T, false><<<grid, WG, 0, s>>>(p->n, ZL, p->rowptr, p->diag_pos, p->lrow, p->urow, src, dst);
+    return launch_status();
 }
 
 }  // namespace
@@ -238,4 +350,24 @@ extern "C" abilu_status abilu_factor(const abilu_pattern *p, const double *d_A, 
     if (prec == ABILU_F32)
         return factor_t<float>(p, d_A, (float *)d_LU, (float *)d_Dinv, nsweeps, mode, init, (char *)d_work, W, s);
     return factor_t<double>(p, d_A, (double *)d_LU, (double *)d_Dinv, nsweeps, mode, init, (char *)d_work, W, s);
+}
+
+extern "C" abilu_status abilu_factor_to_csr(const abilu_pattern *p, abilu_prec prec, const void *d_LU,
+                                            void *d_csr, void *stream) {
+    if (!p || (prec != ABILU_F32 && prec != ABILU_F64)) return ABILU_EINVAL;
+    if (p->n == 0) return ABILU_OK;
+    if (!d_LU || !d_csr || d_LU == d_csr) return ABILU_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == ABILU_F32) return permute_t<float>(p, (const float *)d_LU, (float *)d_csr, true, s);
+    return permute_t<double>(p, (const double *)d_LU, (double *)d_csr, true, s);
+}
+
+extern "C" abilu_status abilu_factor_from_csr(const abilu_pattern *p, abilu_prec prec, const void *d_csr,
+                                              void *d_LU, void *stream) {
+    if (!p || (prec != ABILU_F32 && prec != ABILU_F64)) return ABILU_EINVAL;
+    if (p->n == 0) return ABILU_OK;
+    if (!d_LU || !d_csr || d_LU == d_csr) return ABILU_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == ABILU_F32) return permute_t<float>(p, (const float *)d_csr, (float *)d_LU, false, s);
+    return permute_t<double>(p, (const double *)d_csr, (double *)d_LU, false, s);
 }

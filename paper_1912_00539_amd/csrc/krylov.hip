@@ -213,13 +213,14 @@ __global__ __launch_bounds__(WG) void k_zero(int64_t len, double *v) {
     }
 }
 
-// ---- ILU residual: sums of ||(LU - A)_ij||^2 and ||A_ij||^2 over the pattern
+// ---- ILU residual: sums of ||(LU - A)_ij||^2 and ||A_ij||^2 over the pattern (factor layout)
 template <typename T>
-__global__ __launch_bounds__(WG) void k_ilu_residual(int n, const int32_t *__restrict__ rowptr,
+__global__ __launch_bounds__(WG) void k_ilu_residual(int n, int ZL, const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ colidx,
                                                      const int32_t *__restrict__ diag_pos,
+                                                     const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
                                                      const int32_t *__restrict__ pair_ptr,
-                                                     const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
+                                                     const int32_t *__restrict__ sik, const int32_t *__restrict__ skj,
                                                      const double *__restrict__ A, const T *__restrict__ X,
                                                      double *__restrict__ partial, int nb) {
     __shared__ double shn[WG / 64], shd[WG / 64];
@@ -228,14 +229,14 @@ __global__ __launch_bounds__(WG) void k_ilu_residual(int n, const int32_t *__res
     for (int pass = 0; pass < VEC_TILE / 4 / ROWS_PER_WG; ++pass) {
         const int i = (blockIdx.x * (VEC_TILE / 4 / ROWS_PER_WG) + pass) * ROWS_PER_WG + (threadIdx.x >> 2);
         if (i < n) {
-            const int b0 = rowptr[i], b1 = rowptr[i + 1];
+            const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
             for (int e = b0; e < b1; ++e) {
                 const int j = colidx[e];
                 double x[4], P[4];
-                load_row(X + (int64_t)e * BB, r, x);
+                load_row(X + (int64_t)split_pos(e, i, b0, d, lrow[i], urow[i], ZL, n) * BB, r, x);
                 if (i > j) {
                     double u[4];
-                    load_row(X + (int64_t)diag_pos[j] * BB, r, u);
+                    load_row(X + ((int64_t)ZL + j) * BB, r, u);
                     row_times_block(x, u, P);
                 } else {
 #pragma unroll
@@ -243,8 +244,8 @@ __global__ __launch_bounds__(WG) void k_ilu_residual(int n, const int32_t *__res
                 }
                 for (int q = pair_ptr[e]; q < pair_ptr[e + 1]; ++q) {
                     double l[4], u[4], t[4];
-                    load_row(X + (int64_t)pik[q] * BB, r, l);
-                    load_row(X + (int64_t)pkj[q] * BB, r, u);
+                    load_row(X + (int64_t)sik[q] * BB, r, l);
+                    load_row(X + (int64_t)skj[q] * BB, r, u);
                     row_times_block(l, u, t);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) P[c] += t[c];
@@ -514,8 +515,8 @@ static abilu_status ilu_residual_t(const abilu_pattern *p, const double *A, cons
     double *red = (double *)(work + W.red);
     {
         ProfScope ps("ilu_residual", s);
-        k_ilu_residual<T><<<nb, WG, 0, s>>>(p->n, p->rowptr, p->colidx, p->diag_pos, p->pair_ptr, p->pik, p->pkj, A,
-                                            X, partial, nb);
+        k_ilu_residual<T><<<nb, WG, 0, s>>>(p->n, (int)p->nnzb_lower, p->rowptr, p->colidx, p->diag_pos, p->lrow,
+                                            p->urow, p->pair_ptr, p->sik, p->skj, A, X, partial, nb);
     }
     if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
     k_reduce_cols<<<2, WG, 0, s>>>(partial, nb, red, nullptr);

@@ -3,7 +3,6 @@
 // equation bilu), stored as CSR lists of block-position pairs ascending in k.
 #include <climits>
 #include <cstring>
-#include <vector>
 
 #include "abilu_internal.h"
 
@@ -62,9 +61,12 @@ __global__ void k_pat_count(int n, const int32_t *__restrict__ rowptr, const int
     }
 }
 
-__global__ void k_pat_fill(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                           const int64_t *__restrict__ ptr, int32_t *__restrict__ pik,
-                           int32_t *__restrict__ pkj) {
+__global__ void k_pat_fill(int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                           const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow,
+                           const int32_t *__restrict__ urow, const int64_t *__restrict__ ptr,
+                           int32_t *__restrict__ pik, int32_t *__restrict__ pkj, int32_t *__restrict__ sik,
+                           int32_t *__restrict__ skj) {
+    using abilu_dev::split_pos;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int b0 = rowptr[i], b1 = rowptr[i + 1];
@@ -79,10 +81,33 @@ __global__ void k_pat_fill(int n, const int32_t *__restrict__ rowptr, const int3
             if (g >= 0) {
                 pik[o] = f;
                 pkj[o] = g;
+                sik[o] = split_pos(f, i, b0, diag_pos[i], lrow[i], urow[i], ZL, n);
+                skj[o] = split_pos(g, k, rowptr[k], diag_pos[k], lrow[k], urow[k], ZL, n);
                 ++o;
             }
         }
     }
+}
+
+// per-row counts of strictly lower / upper blocks
+__global__ void k_pat_tri_counts(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ diag_pos,
+                                 int64_t *__restrict__ nl, int64_t *__restrict__ nu) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    nl[i] = diag_pos[i] - rowptr[i];
+    nu[i] = rowptr[i + 1] - diag_pos[i] - 1;
+}
+
+// columns of the lower and upper parts in factor-layout order
+__global__ void k_pat_tri_cols(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                               const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow,
+                               const int32_t *__restrict__ urow, int32_t *__restrict__ lcol,
+                               int32_t *__restrict__ ucol) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b0 = rowptr[i], d = diag_pos[i], b1 = rowptr[i + 1];
+    for (int e = b0; e < d; ++e) lcol[lrow[i] + (e - b0)] = colidx[e];
+    for (int e = d + 1; e < b1; ++e) ucol[urow[i] + (e - d - 1)] = colidx[e];
 }
 
 // ---- exclusive scan of int64 counts (3 phases: tile scan, scan of tile totals, add)
@@ -161,6 +186,12 @@ void free_pattern(abilu_pattern *p) {
     (void)hipFree(p->pair_ptr);
     (void)hipFree(p->pik);
     (void)hipFree(p->pkj);
+    (void)hipFree(p->sik);
+    (void)hipFree(p->skj);
+    (void)hipFree(p->lrow);
+    (void)hipFree(p->urow);
+    (void)hipFree(p->lcol);
+    (void)hipFree(p->ucol);
     if (p->pinned) (void)hipHostFree(p->pinned);
     delete p;
 }
@@ -223,23 +254,47 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
         CK(hipMemcpyAsync(&herr, err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         if (herr) { st = ABILU_EPATTERN; goto fail; }
+        const int ntiles = div_up(Z > 0 ? Z : 1, SCAN_TILE);
+        const int ntiles_n = div_up(n > 0 ? n : 1, SCAN_TILE);
+        const int ntmax = ntiles > ntiles_n ? ntiles : ntiles_n;
+        CKA(hipMalloc(&cnt, sizeof(int64_t) * (Z + n + 2)));
+        CKA(hipMalloc(&scan, sizeof(int64_t) * (Z + n + 2)));
+        CKA(hipMalloc(&ptr64, sizeof(int64_t) * (Z + n + 2)));
+        CKA(hipMalloc(&tot, sizeof(int64_t) * (ntmax + 1)));
+        CKA(hipMalloc(&p->lrow, sizeof(int32_t) * (n + 1)));
+        CKA(hipMalloc(&p->urow, sizeof(int32_t) * (n + 1)));
+        // row offsets of the strictly lower / upper parts of the factor layout
+        int64_t tri[2] = {0, 0};
         if (n > 0) {
-            // block counts of the strict triangles (for the byte model)
-            std::vector<int32_t> hrp(n + 1), hdp(n);
-            CK(hipMemcpyAsync(hrp.data(), p->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
-            CK(hipMemcpyAsync(hdp.data(), p->diag_pos, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+            k_pat_tri_counts<<<div_up(n, 256), 256, 0, s>>>(n, p->rowptr, p->diag_pos, cnt, cnt + (n + 1));
+            CK(hipGetLastError());
+        }
+        for (int part = 0; part < 2; ++part) {
+            const int64_t *counts = cnt + (part == 0 ? 0 : (n + 1));
+            k_scan_tiles<<<ntiles_n, SCAN_T, 0, s>>>(n, counts, scan, tot);
+            CK(hipGetLastError());
+            k_scan_totals<<<1, SCAN_T, 0, s>>>(ntiles_n, tot, tot + ntiles_n);
+            CK(hipGetLastError());
+            k_scan_finish<<<div_up(n + 1, 256), 256, 0, s>>>(n, scan, tot, tot + ntiles_n, ptr64,
+                                                             part == 0 ? p->lrow : p->urow);
+            CK(hipGetLastError());
+            CK(hipMemcpyAsync(&tri[part], ptr64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
             CK(hipStreamSynchronize(s));
-            int64_t zl = 0;
-            for (int i = 0; i < n; ++i) zl += hdp[i] - hrp[i];
-            p->nnzb_lower = zl;
-            p->nnzb_upper = Z - n - zl;
+        }
+        p->nnzb_lower = tri[0];
+        p->nnzb_upper = tri[1];
+        if (tri[0] + tri[1] + n != Z) { st = ABILU_EPATTERN; goto fail; }
+        CKA(hipMalloc(&p->lcol, sizeof(int32_t) * (tri[0] + 1)));
+        CKA(hipMalloc(&p->ucol, sizeof(int32_t) * (tri[1] + 1)));
+        CK(hipMemsetAsync(p->lcol, 0, sizeof(int32_t) * (tri[0] + 1), s));
+        CK(hipMemsetAsync(p->ucol, 0, sizeof(int32_t) * (tri[1] + 1), s));
+        if (n > 0) {
+            k_pat_tri_cols<<<div_up(n, 256), 256, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow,
+                                                           p->lcol, p->ucol);
+            CK(hipGetLastError());
         }
 
-        const int ntiles = div_up(Z > 0 ? Z : 1, SCAN_TILE);
-        CKA(hipMalloc(&cnt, sizeof(int64_t) * (Z + 1)));
-        CKA(hipMalloc(&scan, sizeof(int64_t) * (Z + 1)));
-        CKA(hipMalloc(&ptr64, sizeof(int64_t) * (Z + 1)));
-        CKA(hipMalloc(&tot, sizeof(int64_t) * (ntiles + 1)));
+        // update sets: counts, offsets, lists (CSR positions and factor-layout positions)
         if (n > 0) {
             k_pat_count<<<div_up(n, 128), 128, 0, s>>>(n, p->rowptr, p->colidx, cnt);
             CK(hipGetLastError());
@@ -257,8 +312,11 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
         p->npairs = npairs;
         CKA(hipMalloc(&p->pik, sizeof(int32_t) * (npairs + 1)));
         CKA(hipMalloc(&p->pkj, sizeof(int32_t) * (npairs + 1)));
+        CKA(hipMalloc(&p->sik, sizeof(int32_t) * (npairs + 1)));
+        CKA(hipMalloc(&p->skj, sizeof(int32_t) * (npairs + 1)));
         if (n > 0 && npairs > 0) {
-            k_pat_fill<<<div_up(n, 128), 128, 0, s>>>(n, p->rowptr, p->colidx, ptr64, p->pik, p->pkj);
+            k_pat_fill<<<div_up(n, 128), 128, 0, s>>>(n, (int)tri[0], p->rowptr, p->colidx, p->diag_pos, p->lrow,
+                                                       p->urow, ptr64, p->pik, p->pkj, p->sik, p->skj);
             CK(hipGetLastError());
         }
         CK(hipStreamSynchronize(s));

@@ -57,12 +57,16 @@ class DeviceSystem:
         return L.abilu_read_flags(self.work, clear)
 
     def factor_host(self):
-        """(X [Z,4,4], Dinv [N,4,4]) as float64 numpy arrays."""
-        X = self.LU[: self.nnzb * 16].double().cpu().numpy().reshape(self.nnzb, 4, 4)
+        """(X [Z,4,4] in CSR block order, Dinv [N,4,4]) as float64 numpy arrays."""
+        csr = self.torch.empty_like(self.LU)
+        L.abilu_factor_to_csr(self.pattern, self.prec, self.LU, csr)
+        X = csr[: self.nnzb * 16].double().cpu().numpy().reshape(self.nnzb, 4, 4)
         D = self.Dinv[: self.n * 16].double().cpu().numpy().reshape(self.n, 4, 4)
         return X, D
 
     def set_factor(self, X, D):
+        """Load a factor given in CSR block order (rounded to the factor precision)."""
         t = self.torch
-        self.LU[: self.nnzb * 16].copy_(t.from_numpy(np.ascontiguousarray(X, np.float64).reshape(-1)))
+        csr = t.from_numpy(np.ascontiguousarray(X, np.float64).reshape(-1)).to(self.device).to(self.LU.dtype)
+        L.abilu_factor_from_csr(self.pattern, self.prec, csr, self.LU)
         self.Dinv[: self.n * 16].copy_(t.from_numpy(np.ascontiguousarray(D, np.float64).reshape(-1)))
