@@ -117,7 +117,9 @@ def cpu_baseline(case, args):
 
 
 def load_traffic(kernel, shash):
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    """Measured bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated) recorded under
+    profiles/ for this kernel, or None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_tri2000_async_f32.txt")
     if not os.path.exists(path):
         return None
     try:

@@ -106,16 +106,6 @@ __device__ __forceinline__ int split_pos(int e, int i, int b0, int d, int lbase,
     return e < d ? lbase + (e - b0) : (e == d ? ZL + i : ZL + n + ubase + (e - d - 1));
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs. Remap so that each XCD walks one
-// contiguous range of block rows: neighbouring rows (whose blocks are gathered) then share
-// that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-    constexpr int NX = 8;
-    int q = nblocks / NX, rem = nblocks % NX;
-    int x = bid % NX, idx = bid / NX;
-    return (x < rem) ? x * (q + 1) + idx : rem * (q + 1) + (x - rem) * q + idx;
-}
-
 // Broadcast lane L of each quad (4 consecutive lanes) to the whole quad with one DPP
 // quad_perm move per 32-bit word. All four lanes of the quad must be active.
 template <int L>

@@ -153,56 +153,39 @@ __global__ void k_fill(int64_t len, T *v, T val) {
     if (t < len) v[t] = val;
 }
 
-// y = A x  (RESID: y = b - A x), double precision, CSR; two rows per quad, two blocks per step
+// y = A x  (RESID: y = b - A x), double precision, CSR; one quad per block row, four blocks
+// loaded per step (clamped: rows always hold at least their diagonal block)
 template <bool RESID>
 __global__ __launch_bounds__(WG) void k_spmv(int n, const int32_t *__restrict__ rowptr,
                                              const int32_t *__restrict__ colidx, const double *__restrict__ A,
                                              const double *__restrict__ x, double *__restrict__ y,
                                              const double *__restrict__ b) {
-    const int ib = blockIdx.x * ROWS_PER_WG2 + (threadIdx.x >> 2);
+    constexpr int SCH = 4;
+    const int i = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
     const int r = threadIdx.x & 3;
-    if (ib >= n) return;
-    int ii[RPQ], b0[RPQ], b1[RPQ];
-    double acc[RPQ];
+    if (i >= n) return;
+    const int b0 = rowptr[i], b1 = rowptr[i + 1];
+    double acc = 0.0;
+    for (int e0 = b0; e0 < b1; e0 += SCH) {
+        int j[SCH];
+        double a[SCH][4], xv[SCH];
 #pragma unroll
-    for (int h = 0; h < RPQ; ++h) {
-        ii[h] = ib + h * ROWS_PER_WG;
-        const int i = min(ii[h], n - 1);
-        b0[h] = rowptr[i];
-        b1[h] = (ii[h] < n) ? rowptr[i + 1] : b0[h];
-        acc[h] = 0.0;
+        for (int u = 0; u < SCH; ++u) {
+            const int e = min(e0 + u, b1 - 1);
+            j[u] = colidx[e];
+            load_row(A + (int64_t)e * BB, r, a[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < SCH; ++u) xv[u] = x[(int64_t)j[u] * 4 + r];
+#pragma unroll
+        for (int u = 0; u < SCH; ++u) {
+            double xj[4];
+            gather_vec(xv[u], xj);
+            const double c = a[u][0] * xj[0] + a[u][1] * xj[1] + a[u][2] * xj[2] + a[u][3] * xj[3];
+            acc += (e0 + u < b1) ? c : 0.0;
+        }
     }
-    int cnt = 0;
-#pragma unroll
-    for (int h = 0; h < RPQ; ++h) cnt = max(cnt, b1[h] - b0[h]);
-    for (int t0 = 0; t0 < cnt; t0 += 2) {
-        int j[RPQ][2];
-        double a[RPQ][2][4], xv[RPQ][2];
-#pragma unroll
-        for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = (b1[h] > b0[h]) ? min(b0[h] + t0 + u, b1[h] - 1) : 0;
-                j[h][u] = colidx[e];
-                load_row(A + (int64_t)e * BB, r, a[h][u]);
-            }
-#pragma unroll
-        for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) xv[h][u] = x[(int64_t)j[h][u] * 4 + r];
-#pragma unroll
-        for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                double xj[4];
-                gather_vec(xv[h][u], xj);
-                const double c = a[h][u][0] * xj[0] + a[h][u][1] * xj[1] + a[h][u][2] * xj[2] + a[h][u][3] * xj[3];
-                acc[h] += (b0[h] + t0 + u < b1[h]) ? c : 0.0;
-            }
-    }
-#pragma unroll
-    for (int h = 0; h < RPQ; ++h)
-        if (ii[h] < n) y[(int64_t)ii[h] * 4 + r] = RESID ? b[(int64_t)ii[h] * 4 + r] - acc[h] : acc[h];
+    y[(int64_t)i * 4 + r] = RESID ? b[(int64_t)i * 4 + r] - acc : acc;
 }
 
 template <typename T>
@@ -280,7 +263,7 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
         // backward sweeps 2..nsw (sweep 1 produced za)
         const T *zprev = za;
         for (int q = 2; q <= nsw; ++q) {
-            ProfScope ps(NAME("apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, false));
+            ProfScope ps(NAME(q == nsw ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, false));
             if (q == nsw) {
                 k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, (T *)nullptr);
             } else {
@@ -307,7 +290,7 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
         LAUNCHED();
     }
     for (int q = 1; q <= nsw; ++q) {
-        ProfScope ps(NAME("apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, q == nsw));
+        ProfScope ps(NAME(q == nsw ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, q == nsw));
         if (q == nsw)
             k_bwd<T, T, double, true, true><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, z, za);
         else
@@ -339,7 +322,7 @@ abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv
 abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x, double *y, const double *b,
                        hipStream_t s) {
     if (p->n == 0) return ABILU_OK;
-    const int grid = div_up(p->n, ROWS_PER_WG2);
+    const int grid = div_up(p->n, ROWS_PER_WG);
     const Sizes z = sizes(p);
     // rowptr, colidx, A (f64), x gathered once, y written (+ b read)
     const double by = 4 * (z.N + 1) + 4 * z.Z + 128 * z.Z + 32 * z.N + 32 * z.N;
