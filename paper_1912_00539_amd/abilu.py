@@ -42,6 +42,19 @@ class FgmresResult(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class GenSpec(C.Structure):
+    """abilu_gen_spec (include/abilu_gen.h)."""
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("cfl", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+GEN_KINDS = {"tri": 0, "aniso": 1}
+
+
+def gen_spec(req: dict) -> GenSpec:
+    return GenSpec(GEN_KINDS[req["kind"]], int(req["nx"]), int(req["ny"]), float(req["cfl"]), int(req["seed"]))
+
+
 _lib = None
 
 
@@ -78,6 +91,9 @@ def lib():
             "abilu_profile_report": ([C.c_char_p, sz], st),
             "abilu_status_string": ([st], C.c_char_p),
             "abilu_last_error": ([C.c_char_p, sz], st),
+            "abilu_gen_sizes": ([C.POINTER(GenSpec), C.POINTER(i32), C.POINTER(i64)], st),
+            "abilu_gen_scratch_bytes": ([C.POINTER(GenSpec)], sz),
+            "abilu_gen_build": ([C.POINTER(GenSpec), vp, vp, vp, vp, vp, vp], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -225,3 +241,21 @@ def abilu_profile_report() -> dict:
     buf = C.create_string_buffer(1 << 16)
     _check(lib().abilu_profile_report(buf, len(buf)), "abilu_profile_report")
     return json.loads(buf.value.decode())
+
+
+def abilu_gen_sizes(req: dict):
+    """(N, Z) of a generated request (host only)."""
+    spec = gen_spec(req); n = C.c_int32(); z = C.c_int64()
+    _check(lib().abilu_gen_sizes(C.byref(spec), C.byref(n), C.byref(z)), "abilu_gen_sizes")
+    return n.value, z.value
+
+
+def abilu_gen_scratch_bytes(req: dict) -> int:
+    spec = gen_spec(req)
+    return int(lib().abilu_gen_scratch_bytes(C.byref(spec)))
+
+
+def abilu_gen_build(req: dict, rowptr, colidx, A, b, scratch, stream=None) -> int:
+    spec = gen_spec(req)
+    return _check(lib().abilu_gen_build(C.byref(spec), _ptr(rowptr), _ptr(colidx), _ptr(A), _ptr(b), _ptr(scratch),
+                                        _stream(stream)), "abilu_gen_build")

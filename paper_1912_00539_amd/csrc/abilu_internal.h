@@ -89,6 +89,13 @@ inline Sizes sizes(const abilu_pattern *p) {
     return Sizes{(double)p->n, (double)p->nnzb, (double)p->nnzb_lower, (double)p->nnzb_upper, (double)p->npairs};
 }
 
+// ------------------------------------------------------------------ device prefix sums (scan.hip)
+// Tiles needed by scan_exclusive for `len` elements; the `tot` scratch needs scan_tiles(len) + 1
+// int64 entries, `tmp` len entries. out64 (optional) gets len + 1 offsets, out32 len + 1 offsets.
+int scan_tiles(int64_t len);
+hipError_t scan_exclusive(int64_t len, const int64_t *in, int64_t *tmp, int64_t *tot, int64_t *out64,
+                          int32_t *out32, hipStream_t s);
+
 // ------------------------------------------------------------------ entry points used across files
 abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv, abilu_prec prec,
                         const double *r, double *z, int nsweeps, abilu_mode mode, char *work,

@@ -10,15 +10,14 @@
 // SYNC sweeps read the previous sweep's vector (ping-pong); ASYNC sweeps update in place.
 // From the zero initial guess the first SYNC forward sweep is y = r, so it is not launched; the
 // last forward sweep also produces the first backward sweep z = Dinv y (its rows are at hand).
-#include "abilu_internal.h"
+#include "kernels.h"
 
 using namespace abilu;
 using namespace abilu_dev;
+using namespace abilu_k;
 
 namespace {
 
-constexpr int RPQ = 2;                       // block rows per quad
-constexpr int ROWS_PER_WG2 = RPQ * ROWS_PER_WG;
 
 // Forward sweep over the strictly lower part of the factor layout (lrow/lcol/Lb).
 // Each quad owns rows ib and ib + 64 and loads two blocks of each per step (clamped, so the
@@ -28,59 +27,7 @@ template <typename T, typename YI, bool EMIT_Z>
 __global__ __launch_bounds__(WG) void k_fwd(int n, const int32_t *__restrict__ lrow, const int32_t *__restrict__ lcol,
                                             const T *__restrict__ Lb, const double *__restrict__ rhs, const YI *yin,
                                             T *yout, const T *__restrict__ Dinv, T *__restrict__ zout) {
-    const int ib = blockIdx.x * ROWS_PER_WG2 + (threadIdx.x >> 2);
-    const int r = threadIdx.x & 3;
-    if (ib >= n) return;
-    int ii[RPQ], b0[RPQ], b1[RPQ];
-    T acc[RPQ];
-#pragma unroll
-    for (int h = 0; h < RPQ; ++h) {
-        ii[h] = ib + h * ROWS_PER_WG;
-        const int i = min(ii[h], n - 1);
-        b0[h] = lrow[i];
-        b1[h] = (ii[h] < n) ? lrow[i + 1] : b0[h];
-        acc[h] = (T)rhs[(int64_t)i * 4 + r];
-    }
-    int cnt = 0;
-#pragma unroll
-    for (int h = 0; h < RPQ; ++h) cnt = max(cnt, b1[h] - b0[h]);
-    for (int t0 = 0; t0 < cnt; t0 += 2) {
-        int j[RPQ][2];
-        T l[RPQ][2][4], yv[RPQ][2];
-#pragma unroll
-        for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = (b1[h] > b0[h]) ? min(b0[h] + t0 + u, b1[h] - 1) : 0;
-                j[h][u] = lcol[e];
-                load_row(Lb + (int64_t)e * BB, r, l[h][u]);
-            }
-#pragma unroll
-        for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) yv[h][u] = (T)yin[(int64_t)j[h][u] * 4 + r];
-#pragma unroll
-        for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                T yj[4];
-                gather_vec(yv[h][u], yj);
-                const T c = l[h][u][0] * yj[0] + l[h][u][1] * yj[1] + l[h][u][2] * yj[2] + l[h][u][3] * yj[3];
-                acc[h] -= (b0[h] + t0 + u < b1[h]) ? c : T(0);
-            }
-    }
-#pragma unroll
-    for (int h = 0; h < RPQ; ++h) {
-        if (ii[h] < n) {
-            yout[(int64_t)ii[h] * 4 + r] = acc[h];
-            if constexpr (EMIT_Z) {
-                T dr[4], yi[4];
-                load_row(Dinv + (int64_t)ii[h] * BB, r, dr);
-                gather_vec(acc[h], yi);
-                zout[(int64_t)ii[h] * 4 + r] = dr[0] * yi[0] + dr[1] * yi[1] + dr[2] * yi[2] + dr[3] * yi[3];
-            }
-        }
-    }
+    fwd_body<T, YI, EMIT_Z>(blockIdx.x, n, lrow, lcol, Lb, rhs, yin, yout, Dinv, zout);
 }
 
 // Backward sweep over the strictly upper part (urow/ucol/Ub), then z_i = Dinv_i (y_i - sum).
@@ -89,62 +36,7 @@ template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
 __global__ __launch_bounds__(WG) void k_bwd(int n, const int32_t *__restrict__ urow, const int32_t *__restrict__ ucol,
                                             const T *__restrict__ Ub, const T *__restrict__ Dinv,
                                             const YI *__restrict__ y, const T *zin, ZO *zout, T *zout2) {
-    const int ib = blockIdx.x * ROWS_PER_WG2 + (threadIdx.x >> 2);
-    const int r = threadIdx.x & 3;
-    if (ib >= n) return;
-    int ii[RPQ], b0[RPQ], b1[RPQ];
-    T acc[RPQ];
-#pragma unroll
-    for (int h = 0; h < RPQ; ++h) {
-        ii[h] = ib + h * ROWS_PER_WG;
-        const int i = min(ii[h], n - 1);
-        acc[h] = (T)y[(int64_t)i * 4 + r];
-        if constexpr (OFFDIAG) {
-            b0[h] = urow[i];
-            b1[h] = (ii[h] < n) ? urow[i + 1] : b0[h];
-        }
-    }
-    if constexpr (OFFDIAG) {
-        int cnt = 0;
-#pragma unroll
-        for (int h = 0; h < RPQ; ++h) cnt = max(cnt, b1[h] - b0[h]);
-        for (int t0 = 0; t0 < cnt; t0 += 2) {
-            int j[RPQ][2];
-            T u4[RPQ][2][4], zv[RPQ][2];
-#pragma unroll
-            for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int e = (b1[h] > b0[h]) ? min(b0[h] + t0 + u, b1[h] - 1) : 0;
-                    j[h][u] = ucol[e];
-                    load_row(Ub + (int64_t)e * BB, r, u4[h][u]);
-                }
-#pragma unroll
-            for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) zv[h][u] = zin[(int64_t)j[h][u] * 4 + r];
-#pragma unroll
-            for (int h = 0; h < RPQ; ++h)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    T zj[4];
-                    gather_vec(zv[h][u], zj);
-                    const T c = u4[h][u][0] * zj[0] + u4[h][u][1] * zj[1] + u4[h][u][2] * zj[2] + u4[h][u][3] * zj[3];
-                    acc[h] -= (b0[h] + t0 + u < b1[h]) ? c : T(0);
-                }
-        }
-    }
-#pragma unroll
-    for (int h = 0; h < RPQ; ++h) {
-        if (ii[h] < n) {
-            T dr[4], a[4];
-            load_row(Dinv + (int64_t)ii[h] * BB, r, dr);
-            gather_vec(acc[h], a);
-            const T z = dr[0] * a[0] + dr[1] * a[1] + dr[2] * a[2] + dr[3] * a[3];
-            zout[(int64_t)ii[h] * 4 + r] = (ZO)z;
-            if constexpr (DUAL) zout2[(int64_t)ii[h] * 4 + r] = z;
-        }
-    }
+    bwd_body<T, YI, ZO, OFFDIAG, DUAL>(blockIdx.x, n, urow, ucol, Ub, Dinv, y, zin, zout, zout2);
 }
 
 template <typename T>
@@ -160,32 +52,7 @@ __global__ __launch_bounds__(WG) void k_spmv(int n, const int32_t *__restrict__ 
                                              const int32_t *__restrict__ colidx, const double *__restrict__ A,
                                              const double *__restrict__ x, double *__restrict__ y,
                                              const double *__restrict__ b) {
-    constexpr int SCH = 4;
-    const int i = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
-    const int r = threadIdx.x & 3;
-    if (i >= n) return;
-    const int b0 = rowptr[i], b1 = rowptr[i + 1];
-    double acc = 0.0;
-    for (int e0 = b0; e0 < b1; e0 += SCH) {
-        int j[SCH];
-        double a[SCH][4], xv[SCH];
-#pragma unroll
-        for (int u = 0; u < SCH; ++u) {
-            const int e = min(e0 + u, b1 - 1);
-            j[u] = colidx[e];
-            load_row(A + (int64_t)e * BB, r, a[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < SCH; ++u) xv[u] = x[(int64_t)j[u] * 4 + r];
-#pragma unroll
-        for (int u = 0; u < SCH; ++u) {
-            double xj[4];
-            gather_vec(xv[u], xj);
-            const double c = a[u][0] * xj[0] + a[u][1] * xj[1] + a[u][2] * xj[2] + a[u][3] * xj[3];
-            acc += (e0 + u < b1) ? c : 0.0;
-        }
-    }
-    y[(int64_t)i * 4 + r] = RESID ? b[(int64_t)i * 4 + r] - acc : acc;
+    spmv_body<RESID>(blockIdx.x, n, rowptr, colidx, A, x, y, b);
 }
 
 template <typename T>

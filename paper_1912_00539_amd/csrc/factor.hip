@@ -24,37 +24,13 @@
 //        U_ii uses the L_ik this quad has just written. The first sweep from A reads the X_kj of
 //        other rows from A itself (the initial guess, the oldest admissible value) and so needs no
 //        copy of A into X. Sums are accumulated in registers and stored once; no atomics on values.
-#include "abilu_internal.h"
+#include "kernels.h"
 
 using namespace abilu;
 using namespace abilu_dev;
+using namespace abilu_k;
 
 namespace {
-
-constexpr int CH = 2;   // blocks of a row loaded together
-
-template <typename T, typename S>
-__device__ __forceinline__ void load_block_row(const S *base, int64_t pos, int r, T (&v)[4]) {
-    load_row(base + pos * BB, r, v);
-}
-
-// t -= sum over the update set [p0, p1) of X_ik X_kj (this lane's row of the products).
-// L_ik from XL at factor-layout positions (or from A at CSR positions when L_FROM_A),
-// X_kj from XU likewise (or A when U_FROM_A).
-template <typename T, bool L_FROM_A, bool U_FROM_A>
-__device__ __forceinline__ void update_terms(int p0, int p1, int r, const int32_t *__restrict__ pik,
-                                             const int32_t *__restrict__ pkj, const int32_t *__restrict__ sik,
-                                             const int32_t *__restrict__ skj, const double *__restrict__ A,
-                                             const T *XL, const T *XU, T (&t)[4]) {
-    for (int q = p0; q < p1; ++q) {
-        T l[4], u[4];
-        if constexpr (L_FROM_A) load_block_row(A, pik[q], r, l);
-        else load_block_row(XL, sik[q], r, l);
-        if constexpr (U_FROM_A) load_block_row(A, pkj[q], r, u);
-        else load_block_row(XU, skj[q], r, u);
-        row_times_block_sub(l, u, t);
-    }
-}
 
 // X0 -> (optional) copy into Xout in factor layout, and D0 = inverses of X0's diagonal blocks.
 // SRC_CSR: X0 is A (CSR order, double); otherwise X0 is a factor-layout array of T.
@@ -64,27 +40,7 @@ __global__ __launch_bounds__(WG) void k_factor_init(int n, int ZL, const int32_t
                                                     const int32_t *__restrict__ lrow,
                                                     const int32_t *__restrict__ urow, const S *X0, T *Xout, T *D0,
                                                     unsigned *flags) {
-    const int i = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
-    const int r = threadIdx.x & 3;
-    if (i >= n) return;
-    if constexpr (COPY) {
-        static_assert(SRC_CSR, "copy reads A");
-        const int b0 = rowptr[i], d = diag_pos[i], b1 = rowptr[i + 1];
-        const int lb = lrow[i], ub = urow[i];
-        for (int e = b0; e < b1; ++e) {
-            T v[4];
-            load_row(X0 + (int64_t)e * BB, r, v);
-            store_row(Xout + (int64_t)split_pos(e, i, b0, d, lb, ub, ZL, n) * BB, r, v);
-        }
-    }
-    const int64_t dpos = SRC_CSR ? (int64_t)diag_pos[i] : (int64_t)ZL + i;
-    T u[4], M[16], R[16], out[4];
-    load_row(X0 + dpos * BB, r, u);
-    gather_block(u, M);
-    bool ok = inv4(M, R);
-    pick_row(R, r, out);
-    store_row(D0 + (int64_t)i * BB, r, out);
-    if (!ok && r == 0) atomicOr(flags, ABILU_FLAG_MODIFIED);
+    factor_init_body<T, S, SRC_CSR, COPY>(blockIdx.x, n, ZL, rowptr, diag_pos, lrow, urow, X0, Xout, D0, flags);
 }
 
 // One sweep.
@@ -95,80 +51,7 @@ __global__ __launch_bounds__(WG) void k_factor_sweep(
     const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
     const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
     const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
-    const int i = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
-    const int r = threadIdx.x & 3;
-    if (i >= n) return;
-    const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
-    const int lbase = lrow[i], ubase = urow[i];
-    // update-set extents: lower blocks [pb0, pd), diagonal [pd, pd1), upper [pd1, pb1)
-    const int pb0 = pair_ptr[b0], pd = pair_ptr[d], pd1 = pair_ptr[d + 1], pb1 = pair_ptr[b1];
-    T *XnL = Xn + (int64_t)lbase * BB;
-    T *XnU = Xn + ((int64_t)ZL + n + ubase) * BB;
-    unsigned fl = 0;
-
-    // strictly lower blocks: L_ij = (A_ij - sum) U_jj^{-1}
-    for (int e0 = b0; e0 < d; e0 += CH) {
-        T t[CH][4], dr[CH][4];
-        int j[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int e = min(e0 + u, d - 1);
-            load_row(A + (int64_t)e * BB, r, t[u]);
-            j[u] = colidx[e];
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) load_row(Dp + (int64_t)j[u] * BB, r, dr[u]);
-        if (pd > pb0) {
-#pragma unroll
-            for (int u = 0; u < CH; ++u)
-                if (e0 + u < d)
-                    update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
-                                                        skj, A, XL, XU, t[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            T x[4];
-            row_times_block(t[u], dr[u], x);
-            if (e0 + u < d) {
-                fl |= nonfinite4(x);
-                store_row(XnL + (int64_t)(e0 + u - b0) * BB, r, x);
-            }
-        }
-    }
-    // diagonal block U_ii = A_ii - sum, and its inverse
-    {
-        T t[4];
-        load_row(A + (int64_t)d * BB, r, t);
-        update_terms<T, L_FROM_A, U_FROM_A>(pd, pd1, r, pik, pkj, sik, skj, A, XL, XU, t);
-        fl |= nonfinite4(t);
-        store_row(Xn + ((int64_t)ZL + i) * BB, r, t);
-        T M[16], R[16], out[4];
-        gather_block(t, M);
-        if (!inv4(M, R)) fl |= ABILU_FLAG_MODIFIED;
-        pick_row(R, r, out);
-        store_row(Dn + (int64_t)i * BB, r, out);
-    }
-    // strictly upper blocks: U_ij = A_ij - sum
-    for (int e0 = d + 1; e0 < b1; e0 += CH) {
-        T t[CH][4];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) load_row(A + (int64_t)min(e0 + u, b1 - 1) * BB, r, t[u]);
-        if (pb1 > pd1) {
-#pragma unroll
-            for (int u = 0; u < CH; ++u)
-                if (e0 + u < b1)
-                    update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
-                                                        skj, A, XL, XU, t[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            if (e0 + u < b1) {
-                fl |= nonfinite4(t[u]);
-                store_row(XnU + (int64_t)(e0 + u - d - 1) * BB, r, t[u]);
-            }
-        }
-    }
-    if (fl) atomicOr(flags, fl);
+    factor_sweep_body<T, L_FROM_A, U_FROM_A>(blockIdx.x, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags);
 }
 
 // Conversions between the factor layout and CSR order (one quad per block row).

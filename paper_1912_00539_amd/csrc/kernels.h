@@ -1,0 +1,488 @@
+// Device bodies of the library's kernels, shared by the single-request kernels (one system per
+// launch) and the batched serving kernels (one launch over the tiles of many systems). Every body
+// takes its tile index `blk` explicitly; the arithmetic lives only here.
+#pragma once
+
+#include "abilu_internal.h"
+
+namespace abilu_k {
+
+using namespace abilu;
+using namespace abilu_dev;
+
+constexpr int CH = 2;                        // factor sweep: blocks of a row loaded together
+constexpr int RPQ = 2;                       // apply sweeps: block rows per quad
+constexpr int ROWS_PER_WG2 = RPQ * ROWS_PER_WG;
+constexpr int MAX_RESTART = 256;
+
+// status slots (double[8] in the workspace header, copied to the host)
+enum { ST_EST = 0, ST_HN = 1, ST_BETA = 2, ST_NUM = 3, ST_GUARD = 4 };
+// misc slots (double[16])
+enum { MI_NRM0 = 0, MI_NRM1 = 1, MI_HN = 2, MI_BETA = 3, MI_GUARD = 15 };
+
+template <typename T, typename S>
+__device__ __forceinline__ void load_block_row(const S *base, int64_t pos, int r, T (&v)[4]) {
+    load_row(base + pos * BB, r, v);
+}
+
+// t -= sum over the update set [p0, p1) of X_ik X_kj (this lane's row of the products).
+// L_ik from XL at factor-layout positions (or from A at CSR positions when L_FROM_A),
+// X_kj from XU likewise (or A when U_FROM_A).
+template <typename T, bool L_FROM_A, bool U_FROM_A>
+__device__ __forceinline__ void update_terms(int p0, int p1, int r, const int32_t *__restrict__ pik,
+                                             const int32_t *__restrict__ pkj, const int32_t *__restrict__ sik,
+                                             const int32_t *__restrict__ skj, const double *__restrict__ A,
+                                             const T *XL, const T *XU, T (&t)[4]) {
+    for (int q = p0; q < p1; ++q) {
+        T l[4], u[4];
+        if constexpr (L_FROM_A) load_block_row(A, pik[q], r, l);
+        else load_block_row(XL, sik[q], r, l);
+        if constexpr (U_FROM_A) load_block_row(A, pkj[q], r, u);
+        else load_block_row(XU, skj[q], r, u);
+        row_times_block_sub(l, u, t);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ bool skipped(const int *guard) { return guard && *guard == 0; }
+
+template <typename T, typename YI, bool EMIT_Z>
+__device__ __forceinline__ void fwd_body(int blk, int n, const int32_t *__restrict__ lrow, const int32_t *__restrict__ lcol,
+                                            const T *__restrict__ Lb, const double *__restrict__ rhs, const YI *yin,
+                                            T *yout, const T *__restrict__ Dinv, T *__restrict__ zout) {
+    const int ib = blk * ROWS_PER_WG2 + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (ib >= n) return;
+    int ii[RPQ], b0[RPQ], b1[RPQ];
+    T acc[RPQ];
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        ii[h] = ib + h * ROWS_PER_WG;
+        const int i = min(ii[h], n - 1);
+        b0[h] = lrow[i];
+        b1[h] = (ii[h] < n) ? lrow[i + 1] : b0[h];
+        acc[h] = (T)rhs[(int64_t)i * 4 + r];
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) cnt = max(cnt, b1[h] - b0[h]);
+    for (int t0 = 0; t0 < cnt; t0 += 2) {
+        int j[RPQ][2];
+        T l[RPQ][2][4], yv[RPQ][2];
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = (b1[h] > b0[h]) ? min(b0[h] + t0 + u, b1[h] - 1) : 0;
+                j[h][u] = lcol[e];
+                load_row(Lb + (int64_t)e * BB, r, l[h][u]);
+            }
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) yv[h][u] = (T)yin[(int64_t)j[h][u] * 4 + r];
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                T yj[4];
+                gather_vec(yv[h][u], yj);
+                const T c = l[h][u][0] * yj[0] + l[h][u][1] * yj[1] + l[h][u][2] * yj[2] + l[h][u][3] * yj[3];
+                acc[h] -= (b0[h] + t0 + u < b1[h]) ? c : T(0);
+            }
+    }
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        if (ii[h] < n) {
+            yout[(int64_t)ii[h] * 4 + r] = acc[h];
+            if constexpr (EMIT_Z) {
+                T dr[4], yi[4];
+                load_row(Dinv + (int64_t)ii[h] * BB, r, dr);
+                gather_vec(acc[h], yi);
+                zout[(int64_t)ii[h] * 4 + r] = dr[0] * yi[0] + dr[1] * yi[1] + dr[2] * yi[2] + dr[3] * yi[3];
+            }
+        }
+    }
+}
+
+template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
+__device__ __forceinline__ void bwd_body(int blk, int n, const int32_t *__restrict__ urow, const int32_t *__restrict__ ucol,
+                                            const T *__restrict__ Ub, const T *__restrict__ Dinv,
+                                            const YI *__restrict__ y, const T *zin, ZO *zout, T *zout2) {
+    const int ib = blk * ROWS_PER_WG2 + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (ib >= n) return;
+    int ii[RPQ], b0[RPQ], b1[RPQ];
+    T acc[RPQ];
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        ii[h] = ib + h * ROWS_PER_WG;
+        const int i = min(ii[h], n - 1);
+        acc[h] = (T)y[(int64_t)i * 4 + r];
+        if constexpr (OFFDIAG) {
+            b0[h] = urow[i];
+            b1[h] = (ii[h] < n) ? urow[i + 1] : b0[h];
+        }
+    }
+    if constexpr (OFFDIAG) {
+        int cnt = 0;
+#pragma unroll
+        for (int h = 0; h < RPQ; ++h) cnt = max(cnt, b1[h] - b0[h]);
+        for (int t0 = 0; t0 < cnt; t0 += 2) {
+            int j[RPQ][2];
+            T u4[RPQ][2][4], zv[RPQ][2];
+#pragma unroll
+            for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int e = (b1[h] > b0[h]) ? min(b0[h] + t0 + u, b1[h] - 1) : 0;
+                    j[h][u] = ucol[e];
+                    load_row(Ub + (int64_t)e * BB, r, u4[h][u]);
+                }
+#pragma unroll
+            for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) zv[h][u] = zin[(int64_t)j[h][u] * 4 + r];
+#pragma unroll
+            for (int h = 0; h < RPQ; ++h)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    T zj[4];
+                    gather_vec(zv[h][u], zj);
+                    const T c = u4[h][u][0] * zj[0] + u4[h][u][1] * zj[1] + u4[h][u][2] * zj[2] + u4[h][u][3] * zj[3];
+                    acc[h] -= (b0[h] + t0 + u < b1[h]) ? c : T(0);
+                }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < RPQ; ++h) {
+        if (ii[h] < n) {
+            T dr[4], a[4];
+            load_row(Dinv + (int64_t)ii[h] * BB, r, dr);
+            gather_vec(acc[h], a);
+            const T z = dr[0] * a[0] + dr[1] * a[1] + dr[2] * a[2] + dr[3] * a[3];
+            zout[(int64_t)ii[h] * 4 + r] = (ZO)z;
+            if constexpr (DUAL) zout2[(int64_t)ii[h] * 4 + r] = z;
+        }
+    }
+}
+
+template <bool RESID>
+__device__ __forceinline__ void spmv_body(int blk, int n, const int32_t *__restrict__ rowptr,
+                                             const int32_t *__restrict__ colidx, const double *__restrict__ A,
+                                             const double *__restrict__ x, double *__restrict__ y,
+                                             const double *__restrict__ b) {
+    constexpr int SCH = 4;
+    const int i = blk * ROWS_PER_WG + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (i >= n) return;
+    const int b0 = rowptr[i], b1 = rowptr[i + 1];
+    double acc = 0.0;
+    for (int e0 = b0; e0 < b1; e0 += SCH) {
+        int j[SCH];
+        double a[SCH][4], xv[SCH];
+#pragma unroll
+        for (int u = 0; u < SCH; ++u) {
+            const int e = min(e0 + u, b1 - 1);
+            j[u] = colidx[e];
+            load_row(A + (int64_t)e * BB, r, a[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < SCH; ++u) xv[u] = x[(int64_t)j[u] * 4 + r];
+#pragma unroll
+        for (int u = 0; u < SCH; ++u) {
+            double xj[4];
+            gather_vec(xv[u], xj);
+            const double c = a[u][0] * xj[0] + a[u][1] * xj[1] + a[u][2] * xj[2] + a[u][3] * xj[3];
+            acc += (e0 + u < b1) ? c : 0.0;
+        }
+    }
+    y[(int64_t)i * 4 + r] = RESID ? b[(int64_t)i * 4 + r] - acc : acc;
+}
+
+__device__ __forceinline__ void mdot_body(int blk, int64_t len, const double *__restrict__ V, int64_t ldv, int q,
+                                             const double *__restrict__ w, double *__restrict__ partial, int nb,
+                                             const int *guard) {
+    if (skipped(guard)) return;
+    __shared__ double sh[MAX_RESTART + 2][WG / 64];
+    const int64_t base = (int64_t)blk * VEC_TILE + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double wv[VEC_E];
+    const bool full = base + (int64_t)(VEC_E - 1) * WG < len;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        wv[e] = (full || t < len) ? w[t] : 0.0;
+    }
+    for (int k = 0; k < q; ++k) {
+        const double *vk = V + (int64_t)k * ldv;
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < VEC_E; ++e) {
+            const int64_t t = base + (int64_t)e * WG;
+            s += ((full || t < len) ? vk[t] : 0.0) * wv[e];
+        }
+        s = wave_sum(s);
+        if (lane == 0) sh[k][wave] = s;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) s += wv[e] * wv[e];
+    s = wave_sum(s);
+    if (lane == 0) sh[q][wave] = s;
+    __syncthreads();
+    for (int k = threadIdx.x; k <= q; k += WG)
+        partial[(int64_t)k * nb + blk] = ((sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]));
+}
+
+__device__ __forceinline__ void update_body(int blk, int64_t len, const double *__restrict__ V, int64_t ldv, int q,
+                                               const double *__restrict__ c, double alpha, double *__restrict__ w,
+                                               double *__restrict__ partial, const int *guard) {
+    if (skipped(guard)) return;
+    __shared__ double sh[WG / 64];
+    const int64_t base = (int64_t)blk * VEC_TILE + threadIdx.x;
+    const bool full = base + (int64_t)(VEC_E - 1) * WG < len;
+    double acc[VEC_E];
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        acc[e] = (full || t < len) ? w[t] : 0.0;
+    }
+    for (int k = 0; k < q; ++k) {
+        const double ck = alpha * c[k];
+        const double *vk = V + (int64_t)k * ldv;
+#pragma unroll
+        for (int e = 0; e < VEC_E; ++e) {
+            const int64_t t = base + (int64_t)e * WG;
+            acc[e] += ck * ((full || t < len) ? vk[t] : 0.0);
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        if (full || t < len) w[t] = acc[e];
+        s += acc[e] * acc[e];
+    }
+    if (partial) {
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[blk] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    }
+}
+
+__device__ __forceinline__ void reduce_cols_body(int blk, const double *__restrict__ partial, int nb,
+                                                    double *__restrict__ out, const int *guard) {
+    if (skipped(guard)) return;
+    __shared__ double sh[WG / 64];
+    const double *pc = partial + (int64_t)blk * nb;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += WG) s += pc[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blk] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__device__ __forceinline__ void scale_body(int blk, int64_t len, const double *w, double *v, const double *h) {
+    const double hv = *h;
+    const int64_t base = (int64_t)blk * VEC_TILE + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        if (t < len) v[t] = (hv != 0.0) ? w[t] / hv : w[t];
+    }
+}
+
+__device__ __forceinline__ void gs1_body(int blk, int k, int m, const double *__restrict__ red, double *H, double *coef, double *misc) {
+    for (int q = 0; q <= k; ++q) {
+        H[(int64_t)k * (m + 1) + q] = red[q];
+        coef[q] = red[q];
+    }
+    misc[MI_NRM0] = sqrt(red[k + 1]);
+}
+
+__device__ __forceinline__ void gs1_done_body(int blk, const double *__restrict__ nrm2, double *misc, int *guard) {
+    const double n1 = sqrt(nrm2[0]);
+    misc[MI_NRM1] = n1;
+    *guard = (n1 < 0.70710678118654752440 * misc[MI_NRM0]) ? 1 : 0;
+}
+
+__device__ __forceinline__ void gs2_body(int blk, int k, int m, const double *__restrict__ red, double *H, double *coef, const int *guard) {
+    if (*guard == 0) return;
+    for (int q = 0; q <= k; ++q) {
+        H[(int64_t)k * (m + 1) + q] += red[q];
+        coef[q] = red[q];
+    }
+}
+
+__device__ __forceinline__ void givens_body(int blk, int k, int m, const double *__restrict__ nrm2_pass2, const int *guard, double *H,
+                         double *cs, double *sn, double *g, double *misc, double *status) {
+    const double hn = (*guard) ? sqrt(nrm2_pass2[0]) : misc[MI_NRM1];
+    double *h = H + (int64_t)k * (m + 1);
+    h[k + 1] = hn;
+    for (int q = 0; q < k; ++q) {
+        const double a = h[q], b = h[q + 1];
+        h[q] = cs[q] * a + sn[q] * b;
+        h[q + 1] = -sn[q] * a + cs[q] * b;
+    }
+    const double a = h[k], b = h[k + 1];
+    const double rho = sqrt(a * a + b * b);
+    cs[k] = rho > 0 ? a / rho : 1.0;
+    sn[k] = rho > 0 ? b / rho : 0.0;
+    h[k] = rho;
+    h[k + 1] = 0.0;
+    g[k + 1] = -sn[k] * g[k];
+    g[k] = cs[k] * g[k];
+    misc[MI_HN] = hn;
+    status[ST_EST] = fabs(g[k + 1]);
+    status[ST_HN] = hn;
+    status[ST_GUARD] = (double)(*guard);
+}
+
+__device__ __forceinline__ void solve_body(int blk, int k, int m, const double *__restrict__ H, const double *__restrict__ g, double *coef) {
+    for (int q = k - 1; q >= 0; --q) {
+        double s = g[q];
+        for (int t = q + 1; t < k; ++t) s -= H[(int64_t)t * (m + 1) + q] * coef[t];
+        coef[q] = s / H[(int64_t)q * (m + 1) + q];
+    }
+}
+
+__device__ __forceinline__ void beta_body(int blk, int m, const double *__restrict__ red, double *g, double *misc, double *status, int slot) {
+    const double beta = sqrt(red[0]);
+    status[slot] = beta;
+    misc[MI_BETA] = beta;
+    if (g) {
+        g[0] = beta;
+        for (int q = 1; q <= m + 1; ++q) g[q] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void zero_body(int blk, int64_t len, double *v) {
+    const int64_t base = (int64_t)blk * VEC_TILE + threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < VEC_E; ++e) {
+        const int64_t t = base + (int64_t)e * WG;
+        if (t < len) v[t] = 0.0;
+    }
+}
+
+template <typename T, typename S, bool SRC_CSR, bool COPY>
+__device__ __forceinline__ void factor_init_body(int blk, int n, int ZL, const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ diag_pos,
+                                                    const int32_t *__restrict__ lrow,
+                                                    const int32_t *__restrict__ urow, const S *X0, T *Xout, T *D0,
+                                                    unsigned *flags) {
+    const int i = blk * ROWS_PER_WG + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (i >= n) return;
+    if constexpr (COPY) {
+        static_assert(SRC_CSR, "copy reads A");
+        const int b0 = rowptr[i], d = diag_pos[i], b1 = rowptr[i + 1];
+        const int lb = lrow[i], ub = urow[i];
+        for (int e = b0; e < b1; ++e) {
+            T v[4];
+            load_row(X0 + (int64_t)e * BB, r, v);
+            store_row(Xout + (int64_t)split_pos(e, i, b0, d, lb, ub, ZL, n) * BB, r, v);
+        }
+    }
+    const int64_t dpos = SRC_CSR ? (int64_t)diag_pos[i] : (int64_t)ZL + i;
+    T u[4], M[16], R[16], out[4];
+    load_row(X0 + dpos * BB, r, u);
+    gather_block(u, M);
+    bool ok = inv4(M, R);
+    pick_row(R, r, out);
+    store_row(D0 + (int64_t)i * BB, r, out);
+    if (!ok && r == 0) atomicOr(flags, ABILU_FLAG_MODIFIED);
+}
+
+template <typename T, bool L_FROM_A, bool U_FROM_A>
+__device__ __forceinline__ void factor_sweep_body(int blk, 
+    int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+    const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
+    const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
+    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
+    const int i = blk * ROWS_PER_WG + (threadIdx.x >> 2);
+    const int r = threadIdx.x & 3;
+    if (i >= n) return;
+    const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
+    const int lbase = lrow[i], ubase = urow[i];
+    // update-set extents: lower blocks [pb0, pd), diagonal [pd, pd1), upper [pd1, pb1)
+    const int pb0 = pair_ptr[b0], pd = pair_ptr[d], pd1 = pair_ptr[d + 1], pb1 = pair_ptr[b1];
+    T *XnL = Xn + (int64_t)lbase * BB;
+    T *XnU = Xn + ((int64_t)ZL + n + ubase) * BB;
+    unsigned fl = 0;
+
+    // strictly lower blocks: L_ij = (A_ij - sum) U_jj^{-1}
+    for (int e0 = b0; e0 < d; e0 += CH) {
+        T t[CH][4], dr[CH][4];
+        int j[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = min(e0 + u, d - 1);
+            load_row(A + (int64_t)e * BB, r, t[u]);
+            j[u] = colidx[e];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) load_row(Dp + (int64_t)j[u] * BB, r, dr[u]);
+        if (pd > pb0) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (e0 + u < d)
+                    update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
+                                                        skj, A, XL, XU, t[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            T x[4];
+            row_times_block(t[u], dr[u], x);
+            if (e0 + u < d) {
+                fl |= nonfinite4(x);
+                store_row(XnL + (int64_t)(e0 + u - b0) * BB, r, x);
+            }
+        }
+    }
+    // diagonal block U_ii = A_ii - sum, and its inverse
+    {
+        T t[4];
+        load_row(A + (int64_t)d * BB, r, t);
+        update_terms<T, L_FROM_A, U_FROM_A>(pd, pd1, r, pik, pkj, sik, skj, A, XL, XU, t);
+        fl |= nonfinite4(t);
+        store_row(Xn + ((int64_t)ZL + i) * BB, r, t);
+        T M[16], R[16], out[4];
+        gather_block(t, M);
+        if (!inv4(M, R)) fl |= ABILU_FLAG_MODIFIED;
+        pick_row(R, r, out);
+        store_row(Dn + (int64_t)i * BB, r, out);
+    }
+    // strictly upper blocks: U_ij = A_ij - sum
+    for (int e0 = d + 1; e0 < b1; e0 += CH) {
+        T t[CH][4];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) load_row(A + (int64_t)min(e0 + u, b1 - 1) * BB, r, t[u]);
+        if (pb1 > pd1) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (e0 + u < b1)
+                    update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
+                                                        skj, A, XL, XU, t[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (e0 + u < b1) {
+                fl |= nonfinite4(t[u]);
+                store_row(XnU + (int64_t)(e0 + u - d - 1) * BB, r, t[u]);
+            }
+        }
+    }
+    if (fl) atomicOr(flags, fl);
+}
+
+}  // namespace abilu_k

@@ -9,208 +9,79 @@
 // index order), so results do not depend on scheduling.
 #include <cmath>
 
-#include "abilu_internal.h"
+#include "kernels.h"
 
 using namespace abilu;
 using namespace abilu_dev;
+using namespace abilu_k;
 
 namespace {
 
-constexpr int MAX_RESTART = 256;
 
-// status slots (double[8] in the workspace header, copied to the host)
-enum { ST_EST = 0, ST_HN = 1, ST_BETA = 2, ST_NUM = 3, ST_GUARD = 4 };
-// misc slots (double[16])
-enum { MI_NRM0 = 0, MI_NRM1 = 1, MI_HN = 2, MI_BETA = 3, MI_GUARD = 15 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ bool skipped(const int *guard) { return guard && *guard == 0; }
 
 // partial[k*nb + b] = sum_{t in tile b} V_k[t] w[t] for k < q;  partial[q*nb + b] = sum w[t]^2
 __global__ __launch_bounds__(WG) void k_mdot(int64_t len, const double *__restrict__ V, int64_t ldv, int q,
                                              const double *__restrict__ w, double *__restrict__ partial, int nb,
                                              const int *guard) {
-    if (skipped(guard)) return;
-    __shared__ double sh[MAX_RESTART + 2][WG / 64];
-    const int64_t base = (int64_t)blockIdx.x * VEC_TILE + threadIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double wv[VEC_E];
-    const bool full = base + (int64_t)(VEC_E - 1) * WG < len;
-#pragma unroll
-    for (int e = 0; e < VEC_E; ++e) {
-        const int64_t t = base + (int64_t)e * WG;
-        wv[e] = (full || t < len) ? w[t] : 0.0;
-    }
-    for (int k = 0; k < q; ++k) {
-        const double *vk = V + (int64_t)k * ldv;
-        double s = 0.0;
-#pragma unroll
-        for (int e = 0; e < VEC_E; ++e) {
-            const int64_t t = base + (int64_t)e * WG;
-            s += ((full || t < len) ? vk[t] : 0.0) * wv[e];
-        }
-        s = wave_sum(s);
-        if (lane == 0) sh[k][wave] = s;
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int e = 0; e < VEC_E; ++e) s += wv[e] * wv[e];
-    s = wave_sum(s);
-    if (lane == 0) sh[q][wave] = s;
-    __syncthreads();
-    for (int k = threadIdx.x; k <= q; k += WG)
-        partial[(int64_t)k * nb + blockIdx.x] = ((sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]));
+    mdot_body(blockIdx.x, len, V, ldv, q, w, partial, nb, guard);
 }
 
 // w[t] += alpha * sum_k c[k] V_k[t]; if partial: partial[b] = sum over tile of new w[t]^2
 __global__ __launch_bounds__(WG) void k_update(int64_t len, const double *__restrict__ V, int64_t ldv, int q,
                                                const double *__restrict__ c, double alpha, double *__restrict__ w,
                                                double *__restrict__ partial, const int *guard) {
-    if (skipped(guard)) return;
-    __shared__ double sh[WG / 64];
-    const int64_t base = (int64_t)blockIdx.x * VEC_TILE + threadIdx.x;
-    const bool full = base + (int64_t)(VEC_E - 1) * WG < len;
-    double acc[VEC_E];
-#pragma unroll
-    for (int e = 0; e < VEC_E; ++e) {
-        const int64_t t = base + (int64_t)e * WG;
-        acc[e] = (full || t < len) ? w[t] : 0.0;
-    }
-    for (int k = 0; k < q; ++k) {
-        const double ck = alpha * c[k];
-        const double *vk = V + (int64_t)k * ldv;
-#pragma unroll
-        for (int e = 0; e < VEC_E; ++e) {
-            const int64_t t = base + (int64_t)e * WG;
-            acc[e] += ck * ((full || t < len) ? vk[t] : 0.0);
-        }
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int e = 0; e < VEC_E; ++e) {
-        const int64_t t = base + (int64_t)e * WG;
-        if (full || t < len) w[t] = acc[e];
-        s += acc[e] * acc[e];
-    }
-    if (partial) {
-        s = wave_sum(s);
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    }
+    update_body(blockIdx.x, len, V, ldv, q, c, alpha, w, partial, guard);
 }
 
 // out[col] = sum_b partial[col*nb + b], one workgroup per column, fixed order
 __global__ __launch_bounds__(WG) void k_reduce_cols(const double *__restrict__ partial, int nb,
                                                     double *__restrict__ out, const int *guard) {
-    if (skipped(guard)) return;
-    __shared__ double sh[WG / 64];
-    const double *pc = partial + (int64_t)blockIdx.x * nb;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += WG) s += pc[b];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) out[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    reduce_cols_body(blockIdx.x, partial, nb, out, guard);
 }
 
 // v = w / h (h read from device memory; left unchanged if h == 0)
 __global__ __launch_bounds__(WG) void k_scale(int64_t len, const double *w, double *v, const double *h) {
-    const double hv = *h;
-    const int64_t base = (int64_t)blockIdx.x * VEC_TILE + threadIdx.x;
-#pragma unroll
-    for (int e = 0; e < VEC_E; ++e) {
-        const int64_t t = base + (int64_t)e * WG;
-        if (t < len) v[t] = (hv != 0.0) ? w[t] / hv : w[t];
-    }
+    scale_body(blockIdx.x, len, w, v, h);
 }
 
 // ---- single-lane kernels on the small dense Hessenberg problem (column-major, ld = m+1)
 
 // After the first Gram-Schmidt pass: H(0:k,k) = dots, coef = dots, nrm0 = ||w|| before.
 __global__ void k_gs1(int k, int m, const double *__restrict__ red, double *H, double *coef, double *misc) {
-    for (int q = 0; q <= k; ++q) {
-        H[(int64_t)k * (m + 1) + q] = red[q];
-        coef[q] = red[q];
-    }
-    misc[MI_NRM0] = sqrt(red[k + 1]);
+    gs1_body(blockIdx.x, k, m, red, H, coef, misc);
 }
 
 // After the first update: decide on a second pass (guard = 1) if ||w'|| < ||w|| / sqrt(2).
 __global__ void k_gs1_done(const double *__restrict__ nrm2, double *misc, int *guard) {
-    const double n1 = sqrt(nrm2[0]);
-    misc[MI_NRM1] = n1;
-    *guard = (n1 < 0.70710678118654752440 * misc[MI_NRM0]) ? 1 : 0;
+    gs1_done_body(blockIdx.x, nrm2, misc, guard);
 }
 
 // After the second dot pass (only if guard): H(0:k,k) += dots2, coef = dots2.
 __global__ void k_gs2(int k, int m, const double *__restrict__ red, double *H, double *coef, const int *guard) {
-    if (*guard == 0) return;
-    for (int q = 0; q <= k; ++q) {
-        H[(int64_t)k * (m + 1) + q] += red[q];
-        coef[q] = red[q];
-    }
+    gs2_body(blockIdx.x, k, m, red, H, coef, guard);
 }
 
 // Final norm, Givens rotations, residual estimate.
 __global__ void k_givens(int k, int m, const double *__restrict__ nrm2_pass2, const int *guard, double *H,
                          double *cs, double *sn, double *g, double *misc, double *status) {
-    const double hn = (*guard) ? sqrt(nrm2_pass2[0]) : misc[MI_NRM1];
-    double *h = H + (int64_t)k * (m + 1);
-    h[k + 1] = hn;
-    for (int q = 0; q < k; ++q) {
-        const double a = h[q], b = h[q + 1];
-        h[q] = cs[q] * a + sn[q] * b;
-        h[q + 1] = -sn[q] * a + cs[q] * b;
-    }
-    const double a = h[k], b = h[k + 1];
-    const double rho = sqrt(a * a + b * b);
-    cs[k] = rho > 0 ? a / rho : 1.0;
-    sn[k] = rho > 0 ? b / rho : 0.0;
-    h[k] = rho;
-    h[k + 1] = 0.0;
-    g[k + 1] = -sn[k] * g[k];
-    g[k] = cs[k] * g[k];
-    misc[MI_HN] = hn;
-    status[ST_EST] = fabs(g[k + 1]);
-    status[ST_HN] = hn;
-    status[ST_GUARD] = (double)(*guard);
+    givens_body(blockIdx.x, k, m, nrm2_pass2, guard, H, cs, sn, g, misc, status);
 }
 
 // Back substitution on the k x k upper triangle: coef = y.
 __global__ void k_solve(int k, int m, const double *__restrict__ H, const double *__restrict__ g, double *coef) {
-    for (int q = k - 1; q >= 0; --q) {
-        double s = g[q];
-        for (int t = q + 1; t < k; ++t) s -= H[(int64_t)t * (m + 1) + q] * coef[t];
-        coef[q] = s / H[(int64_t)q * (m + 1) + q];
-    }
+    solve_body(blockIdx.x, k, m, H, g, coef);
 }
 
 // beta = sqrt(red[0]); g = [beta, 0, ...]; status[slot] = beta
 __global__ void k_beta(int m, const double *__restrict__ red, double *g, double *misc, double *status, int slot) {
-    const double beta = sqrt(red[0]);
-    status[slot] = beta;
-    misc[MI_BETA] = beta;
-    if (g) {
-        g[0] = beta;
-        for (int q = 1; q <= m + 1; ++q) g[q] = 0.0;
-    }
+    beta_body(blockIdx.x, m, red, g, misc, status, slot);
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
 __global__ __launch_bounds__(WG) void k_zero(int64_t len, double *v) {
-    const int64_t base = (int64_t)blockIdx.x * VEC_TILE + threadIdx.x;
-#pragma unroll
-    for (int e = 0; e < VEC_E; ++e) {
-        const int64_t t = base + (int64_t)e * WG;
-        if (t < len) v[t] = 0.0;
-    }
+    zero_body(blockIdx.x, len, v);
 }
 
 // ---- ILU residual: sums of ||(LU - A)_ij||^2 and ||A_ij||^2 over the pattern (factor layout)

@@ -110,74 +110,6 @@ __global__ void k_pat_tri_cols(int n, const int32_t *__restrict__ rowptr, const 
     for (int e = d + 1; e < b1; ++e) ucol[urow[i] + (e - d - 1)] = colidx[e];
 }
 
-// ---- exclusive scan of int64 counts (3 phases: tile scan, scan of tile totals, add)
-constexpr int SCAN_T = 256, SCAN_E = 8, SCAN_TILE = SCAN_T * SCAN_E;
-
-__device__ long long block_exclusive(long long v, long long *sh, long long *total) {
-    int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < SCAN_T; off <<= 1) {
-        long long a = (t >= off) ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += a;
-        __syncthreads();
-    }
-    long long inc = sh[t];
-    *total = sh[SCAN_T - 1];
-    __syncthreads();
-    return inc - v;
-}
-
-__global__ __launch_bounds__(SCAN_T) void k_scan_tiles(int64_t len, const int64_t *__restrict__ in,
-                                                       int64_t *__restrict__ out, int64_t *__restrict__ tot) {
-    __shared__ long long sh[SCAN_T];
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_E;
-    long long v[SCAN_E], s = 0;
-#pragma unroll
-    for (int q = 0; q < SCAN_E; ++q) {
-        v[q] = (base + q < len) ? in[base + q] : 0;
-        s += v[q];
-    }
-    long long total;
-    long long pre = block_exclusive(s, sh, &total);
-#pragma unroll
-    for (int q = 0; q < SCAN_E; ++q) {
-        if (base + q < len) out[base + q] = pre;
-        pre += v[q];
-    }
-    if (threadIdx.x == 0) tot[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(SCAN_T) void k_scan_totals(int ntiles, int64_t *__restrict__ tot,
-                                                        int64_t *__restrict__ grand) {
-    __shared__ long long sh[SCAN_T];
-    long long carry = 0;
-    for (int base = 0; base < ntiles; base += SCAN_T) {
-        int q = base + threadIdx.x;
-        long long v = (q < ntiles) ? tot[q] : 0;
-        long long total;
-        long long pre = block_exclusive(v, sh, &total);
-        if (q < ntiles) tot[q] = carry + pre;
-        carry += total;
-    }
-    if (threadIdx.x == 0) *grand = carry;
-}
-
-__global__ void k_scan_finish(int64_t len, const int64_t *__restrict__ scan, const int64_t *__restrict__ tot,
-                              const int64_t *__restrict__ grand, int64_t *__restrict__ ptr64,
-                              int32_t *__restrict__ ptr32) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < len) {
-        int64_t v = scan[e] + tot[e / SCAN_TILE];
-        ptr64[e] = v;
-        ptr32[e] = (int32_t)v;
-    } else if (e == len) {
-        ptr64[len] = *grand;
-        ptr32[len] = (int32_t)*grand;
-    }
-}
-
 void free_pattern(abilu_pattern *p) {
     if (!p) return;
     (void)hipFree(p->rowptr);
@@ -254,9 +186,7 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
         CK(hipMemcpyAsync(&herr, err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         if (herr) { st = ABILU_EPATTERN; goto fail; }
-        const int ntiles = div_up(Z > 0 ? Z : 1, SCAN_TILE);
-        const int ntiles_n = div_up(n > 0 ? n : 1, SCAN_TILE);
-        const int ntmax = ntiles > ntiles_n ? ntiles : ntiles_n;
+        const int ntmax = scan_tiles(Z > n ? Z : n);
         CKA(hipMalloc(&cnt, sizeof(int64_t) * (Z + n + 2)));
         CKA(hipMalloc(&scan, sizeof(int64_t) * (Z + n + 2)));
         CKA(hipMalloc(&ptr64, sizeof(int64_t) * (Z + n + 2)));
@@ -271,13 +201,7 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
         }
         for (int part = 0; part < 2; ++part) {
             const int64_t *counts = cnt + (part == 0 ? 0 : (n + 1));
-            k_scan_tiles<<<ntiles_n, SCAN_T, 0, s>>>(n, counts, scan, tot);
-            CK(hipGetLastError());
-            k_scan_totals<<<1, SCAN_T, 0, s>>>(ntiles_n, tot, tot + ntiles_n);
-            CK(hipGetLastError());
-            k_scan_finish<<<div_up(n + 1, 256), 256, 0, s>>>(n, scan, tot, tot + ntiles_n, ptr64,
-                                                             part == 0 ? p->lrow : p->urow);
-            CK(hipGetLastError());
+            CK(scan_exclusive(n, counts, scan, tot, ptr64, part == 0 ? p->lrow : p->urow, s));
             CK(hipMemcpyAsync(&tri[part], ptr64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
             CK(hipStreamSynchronize(s));
         }
@@ -299,12 +223,7 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
             k_pat_count<<<div_up(n, 128), 128, 0, s>>>(n, p->rowptr, p->colidx, cnt);
             CK(hipGetLastError());
         }
-        k_scan_tiles<<<ntiles, SCAN_T, 0, s>>>(Z, cnt, scan, tot);
-        CK(hipGetLastError());
-        k_scan_totals<<<1, SCAN_T, 0, s>>>(ntiles, tot, tot + ntiles);
-        CK(hipGetLastError());
-        k_scan_finish<<<div_up(Z + 1, 256), 256, 0, s>>>(Z, scan, tot, tot + ntiles, ptr64, p->pair_ptr);
-        CK(hipGetLastError());
+        CK(scan_exclusive(Z, cnt, scan, tot, ptr64, p->pair_ptr, s));
         int64_t npairs = 0;
         CK(hipMemcpyAsync(&npairs, ptr64 + Z, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));

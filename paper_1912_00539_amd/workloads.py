@@ -373,9 +373,12 @@ def serving_requests(count: int, seed: int):
     return out
 
 
-def request_case(req: dict) -> BSRCase:
+def request_case(req: dict, order: str = "device") -> BSRCase:
+    """Host twin of a serving request. order='device' uses the device generator's numbering
+    (natural for triangles, line order for anisotropic quads); 'rcm' reorders triangles by RCM."""
     if req["kind"] == "tri":
         m = split_tri_mesh(req["nx"], req["ny"], req["seed"])
-        return assemble(m, rcm_order(m, req["seed"]), req["seed"], "cfl", cfl=req["cfl"])
+        o = rcm_order(m, req["seed"]) if order == "rcm" else natural_order(m)
+        return assemble(m, o, req["seed"], "cfl", cfl=req["cfl"])
     m = aniso_quad_mesh(req["nx"], req["ny"])
     return assemble(m, line_order(m), req["seed"], "cfl", cfl=req["cfl"])
