@@ -55,6 +55,33 @@ def gen_spec(req: dict) -> GenSpec:
     return GenSpec(GEN_KINDS[req["kind"]], int(req["nx"]), int(req["ny"]), float(req["cfl"]), int(req["seed"]))
 
 
+class ServeConfig(C.Structure):
+    """abilu_serve_config (include/abilu_serve.h)."""
+    _fields_ = [("prec", C.c_int32), ("mode", C.c_int32), ("factor_sweeps", C.c_int32), ("apply_sweeps", C.c_int32),
+                ("restart", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("max_active", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("gen", GenSpec), ("arrival_s", C.c_double), ("d_x_out", C.c_void_p)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n", C.c_int32), ("nnzb", C.c_int64), ("iters", C.c_int32),
+                ("restarts", C.c_int32), ("converged", C.c_int32), ("reorth", C.c_int32), ("flags", C.c_uint32),
+                ("reserved", C.c_int32), ("rel_true_residual", C.c_double), ("t_arrival", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("footprint_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+def serve_config(prec: str = "f32", mode: str = "async", factor_sweeps: int = 1, apply_sweeps: int = 3,
+                 restart: int = 30, maxit: int = 300, rtol: float = 1e-2, max_active: int = 64) -> ServeConfig:
+    return ServeConfig(PRECS[prec], MODES[mode], int(factor_sweeps), int(apply_sweeps), int(restart), int(maxit),
+                       float(rtol), int(max_active), 0)
+
+
 _lib = None
 
 
@@ -94,6 +121,14 @@ def lib():
             "abilu_gen_sizes": ([C.POINTER(GenSpec), C.POINTER(i32), C.POINTER(i64)], st),
             "abilu_gen_scratch_bytes": ([C.POINTER(GenSpec)], sz),
             "abilu_gen_build": ([C.POINTER(GenSpec), vp, vp, vp, vp, vp, vp], st),
+            "abilu_serve_footprint": ([C.POINTER(ServeConfig), C.POINTER(GenSpec)], sz),
+            "abilu_serve_create": ([C.POINTER(ServeConfig), vp, sz, C.POINTER(vp)], st),
+            "abilu_serve_destroy": ([vp], st),
+            "abilu_serve_submit": ([vp, C.POINTER(Request), C.POINTER(i64)], st),
+            "abilu_serve_step": ([vp, vp, C.POINTER(i32), C.POINTER(i32)], st),
+            "abilu_serve_poll": ([vp, i64, C.POINTER(i32), C.POINTER(RequestResult)], st),
+            "abilu_serve_run": ([vp, C.POINTER(Request), i32, C.POINTER(RequestResult), C.POINTER(C.c_double), vp],
+                                st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -259,3 +294,60 @@ def abilu_gen_build(req: dict, rowptr, colidx, A, b, scratch, stream=None) -> in
     spec = gen_spec(req)
     return _check(lib().abilu_gen_build(C.byref(spec), _ptr(rowptr), _ptr(colidx), _ptr(A), _ptr(b), _ptr(scratch),
                                         _stream(stream)), "abilu_gen_build")
+
+
+def abilu_serve_footprint(cfg: ServeConfig, req: dict) -> int:
+    """Pool bytes a request holds (host only; 0 if the config or spec is invalid)."""
+    spec = gen_spec(req)
+    return int(lib().abilu_serve_footprint(C.byref(cfg), C.byref(spec)))
+
+
+class Server:
+    """Owns an abilu_server over a caller pool (a torch uint8 tensor kept alive here)."""
+
+    def __init__(self, cfg: ServeConfig, pool):
+        self.cfg = cfg
+        self.pool = pool
+        out = C.c_void_p()
+        _check(lib().abilu_serve_create(C.byref(cfg), _ptr(pool), pool.numel() * pool.element_size(), C.byref(out)),
+               "abilu_serve_create")
+        self.handle = out
+
+    def submit(self, req: dict, x_out=None) -> int:
+        r = Request(gen_spec(req), 0.0, _ptr(x_out))
+        rid = C.c_int64()
+        _check(lib().abilu_serve_submit(self.handle, C.byref(r), C.byref(rid)), "abilu_serve_submit")
+        return rid.value
+
+    def step(self, stream=None):
+        a = C.c_int32(); q = C.c_int32()
+        _check(lib().abilu_serve_step(self.handle, _stream(stream), C.byref(a), C.byref(q)), "abilu_serve_step")
+        return a.value, q.value
+
+    def poll(self, rid: int):
+        done = C.c_int32(); res = RequestResult()
+        _check(lib().abilu_serve_poll(self.handle, int(rid), C.byref(done), C.byref(res)), "abilu_serve_poll")
+        return res.as_dict() if done.value else None
+
+    def run(self, reqs, arrivals=None, x_outs=None, stream=None):
+        """Serve a trace; returns (list of result dicts, elapsed seconds)."""
+        cnt = len(reqs)
+        arr = (Request * max(cnt, 1))()
+        for q, rq in enumerate(reqs):
+            arr[q] = Request(gen_spec(rq), float(arrivals[q]) if arrivals is not None else 0.0,
+                             _ptr(x_outs[q]) if x_outs is not None else None)
+        res = (RequestResult * max(cnt, 1))()
+        el = C.c_double()
+        _check(lib().abilu_serve_run(self.handle, arr, cnt, res, C.byref(el), _stream(stream)), "abilu_serve_run")
+        return [res[q].as_dict() for q in range(cnt)], el.value
+
+    def destroy(self):
+        if self.handle is not None and self.handle.value:
+            lib().abilu_serve_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

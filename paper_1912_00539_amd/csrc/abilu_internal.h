@@ -96,6 +96,18 @@ int scan_tiles(int64_t len);
 hipError_t scan_exclusive(int64_t len, const int64_t *in, int64_t *tmp, int64_t *tot, int64_t *out64,
                           int32_t *out32, hipStream_t s);
 
+// ------------------------------------------------------------------ pattern analysis into caller buffers
+// (pattern.hip; used by abilu_build_pattern and by the server, which carves the arrays out of its
+// pool). Scratch: pattern_scratch_bytes(n, Z) device bytes, kept between the two stages.
+size_t pattern_scratch_bytes(int32_t n, int64_t Z);
+abilu_status pattern_count(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx, int32_t *diag_pos,
+                           int32_t *lrow, int32_t *urow, int32_t *pair_ptr, void *scratch, int64_t *h_pinned,
+                           hipStream_t s, int64_t *ZL, int64_t *ZU, int64_t *npairs);
+abilu_status pattern_fill(int32_t n, int64_t Z, int64_t ZL, int64_t ZU, int64_t npairs, const int32_t *rowptr,
+                          const int32_t *colidx, const int32_t *diag_pos, const int32_t *lrow, const int32_t *urow,
+                          int32_t *lcol, int32_t *ucol, int32_t *pik, int32_t *pkj, int32_t *sik, int32_t *skj,
+                          const void *scratch, hipStream_t s);
+
 // ------------------------------------------------------------------ entry points used across files
 abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv, abilu_prec prec,
                         const double *r, double *z, int nsweeps, abilu_mode mode, char *work,

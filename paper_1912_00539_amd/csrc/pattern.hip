@@ -130,6 +130,84 @@ void free_pattern(abilu_pattern *p) {
 
 }  // namespace
 
+namespace abilu {
+
+size_t pattern_scratch_bytes(int32_t n, int64_t Z) {
+    const int64_t len = Z + n + 2;
+    return 256 + sizeof(int64_t) * (size_t)(3 * len + scan_tiles(Z > n ? Z : n) + 1);
+}
+
+// Validation, diagonal positions, lower/upper row offsets and the update-set offsets
+// (pair_ptr). Blocking: reads back the error word and the three totals (two stream syncs).
+abilu_status pattern_count(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx, int32_t *diag_pos,
+                           int32_t *lrow, int32_t *urow, int32_t *pair_ptr, void *scratch, int64_t *h_pinned,
+                           hipStream_t s, int64_t *ZL, int64_t *ZU, int64_t *npairs) {
+    unsigned *err = (unsigned *)scratch;
+    const int64_t len = Z + n + 2;
+    int64_t *cnt = (int64_t *)((char *)scratch + 256);
+    int64_t *tmp = cnt + len, *ptr64 = tmp + len, *tot = ptr64 + len;
+#define CK(x)                                              \
+    do {                                                   \
+        if (!hip_ok((x), #x)) return ABILU_EDEVICE;        \
+    } while (0)
+    CK(hipMemsetAsync(err, 0, sizeof(unsigned), s));
+    if (n > 0) {
+        k_pat_rows<<<div_up(n, 256), 256, 0, s>>>(n, Z, rowptr, colidx, diag_pos, err);
+        CK(hipGetLastError());
+    }
+    CK(hipMemcpyAsync(h_pinned, err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (*(const unsigned *)h_pinned) return ABILU_EPATTERN;
+    // row offsets of the strictly lower / upper parts of the factor layout
+    if (n > 0) {
+        k_pat_tri_counts<<<div_up(n, 256), 256, 0, s>>>(n, rowptr, diag_pos, cnt, cnt + (n + 1));
+        CK(hipGetLastError());
+    }
+    for (int part = 0; part < 2; ++part) {
+        CK(scan_exclusive(n, cnt + (part == 0 ? 0 : (n + 1)), tmp, tot, ptr64, part == 0 ? lrow : urow, s));
+        CK(hipMemcpyAsync(h_pinned + part, ptr64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    }
+    // update-set sizes and offsets; ptr64 keeps the int64 offsets for pattern_fill
+    if (n > 0) {
+        k_pat_count<<<div_up(n, 128), 128, 0, s>>>(n, rowptr, colidx, cnt);
+        CK(hipGetLastError());
+    }
+    CK(scan_exclusive(Z, cnt, tmp, tot, ptr64, pair_ptr, s));
+    CK(hipMemcpyAsync(h_pinned + 2, ptr64 + Z, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    *ZL = h_pinned[0];
+    *ZU = h_pinned[1];
+    *npairs = h_pinned[2];
+    if (*ZL + *ZU + n != Z || *npairs < 0 || *npairs > (int64_t)INT_MAX) return ABILU_EPATTERN;
+    return ABILU_OK;
+#undef CK
+}
+
+// Columns of the lower/upper parts and the update-set lists (non-blocking; the scratch must
+// still hold what pattern_count left there).
+abilu_status pattern_fill(int32_t n, int64_t Z, int64_t ZL, int64_t ZU, int64_t npairs, const int32_t *rowptr,
+                          const int32_t *colidx, const int32_t *diag_pos, const int32_t *lrow, const int32_t *urow,
+                          int32_t *lcol, int32_t *ucol, int32_t *pik, int32_t *pkj, int32_t *sik, int32_t *skj,
+                          const void *scratch, hipStream_t s) {
+    const int64_t len = Z + n + 2;
+    const int64_t *ptr64 = (const int64_t *)((const char *)scratch + 256) + 2 * len;
+    if (!hip_ok(hipMemsetAsync(lcol, 0, sizeof(int32_t) * (ZL + 1), s), "lcol clear") ||
+        !hip_ok(hipMemsetAsync(ucol, 0, sizeof(int32_t) * (ZU + 1), s), "ucol clear"))
+        return ABILU_EDEVICE;
+    if (n > 0) {
+        k_pat_tri_cols<<<div_up(n, 256), 256, 0, s>>>(n, rowptr, colidx, diag_pos, lrow, urow, lcol, ucol);
+        if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+    }
+    if (n > 0 && npairs > 0) {
+        k_pat_fill<<<div_up(n, 128), 128, 0, s>>>(n, (int)ZL, rowptr, colidx, diag_pos, lrow, urow, ptr64, pik, pkj,
+                                                   sik, skj);
+        if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+    }
+    return ABILU_OK;
+}
+
+}  // namespace abilu
+
 extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_rowptr,
                                             const int32_t *d_colidx, int32_t bs, void *stream,
                                             abilu_pattern **out) {
@@ -141,10 +219,10 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
     const int n = nbrows;
 
     abilu_pattern *p = new abilu_pattern();
-    int64_t *cnt = nullptr, *scan = nullptr, *tot = nullptr, *ptr64 = nullptr;
-    unsigned *err = nullptr;
+    void *scratch = nullptr;
     abilu_status st = ABILU_OK;
     int32_t ends[2] = {0, 0};
+    int64_t ZL = 0, ZU = 0, npairs = 0;
 #define CK(x)                                  \
     do {                                       \
         if (!hip_ok((x), #x)) {                \
@@ -174,86 +252,34 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
         CKA(hipMalloc(&p->colidx, sizeof(int32_t) * (Z + 1)));
         CKA(hipMalloc(&p->diag_pos, sizeof(int32_t) * (n + 1)));
         CKA(hipMalloc(&p->pair_ptr, sizeof(int32_t) * (Z + 1)));
-        CKA(hipMalloc(&err, sizeof(unsigned)));
-        CK(hipMemcpyAsync(p->rowptr, d_rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
-        if (Z > 0) CK(hipMemcpyAsync(p->colidx, d_colidx, sizeof(int32_t) * Z, hipMemcpyDeviceToDevice, s));
-        CK(hipMemsetAsync(err, 0, sizeof(unsigned), s));
-        if (n > 0) {
-            k_pat_rows<<<div_up(n, 256), 256, 0, s>>>(n, Z, p->rowptr, p->colidx, p->diag_pos, err);
-            CK(hipGetLastError());
-        }
-        unsigned herr = 0;
-        CK(hipMemcpyAsync(&herr, err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-        CK(hipStreamSynchronize(s));
-        if (herr) { st = ABILU_EPATTERN; goto fail; }
-        const int ntmax = scan_tiles(Z > n ? Z : n);
-        CKA(hipMalloc(&cnt, sizeof(int64_t) * (Z + n + 2)));
-        CKA(hipMalloc(&scan, sizeof(int64_t) * (Z + n + 2)));
-        CKA(hipMalloc(&ptr64, sizeof(int64_t) * (Z + n + 2)));
-        CKA(hipMalloc(&tot, sizeof(int64_t) * (ntmax + 1)));
         CKA(hipMalloc(&p->lrow, sizeof(int32_t) * (n + 1)));
         CKA(hipMalloc(&p->urow, sizeof(int32_t) * (n + 1)));
-        // row offsets of the strictly lower / upper parts of the factor layout
-        int64_t tri[2] = {0, 0};
-        if (n > 0) {
-            k_pat_tri_counts<<<div_up(n, 256), 256, 0, s>>>(n, p->rowptr, p->diag_pos, cnt, cnt + (n + 1));
-            CK(hipGetLastError());
-        }
-        for (int part = 0; part < 2; ++part) {
-            const int64_t *counts = cnt + (part == 0 ? 0 : (n + 1));
-            CK(scan_exclusive(n, counts, scan, tot, ptr64, part == 0 ? p->lrow : p->urow, s));
-            CK(hipMemcpyAsync(&tri[part], ptr64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-            CK(hipStreamSynchronize(s));
-        }
-        p->nnzb_lower = tri[0];
-        p->nnzb_upper = tri[1];
-        if (tri[0] + tri[1] + n != Z) { st = ABILU_EPATTERN; goto fail; }
-        CKA(hipMalloc(&p->lcol, sizeof(int32_t) * (tri[0] + 1)));
-        CKA(hipMalloc(&p->ucol, sizeof(int32_t) * (tri[1] + 1)));
-        CK(hipMemsetAsync(p->lcol, 0, sizeof(int32_t) * (tri[0] + 1), s));
-        CK(hipMemsetAsync(p->ucol, 0, sizeof(int32_t) * (tri[1] + 1), s));
-        if (n > 0) {
-            k_pat_tri_cols<<<div_up(n, 256), 256, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow,
-                                                           p->lcol, p->ucol);
-            CK(hipGetLastError());
-        }
-
-        // update sets: counts, offsets, lists (CSR positions and factor-layout positions)
-        if (n > 0) {
-            k_pat_count<<<div_up(n, 128), 128, 0, s>>>(n, p->rowptr, p->colidx, cnt);
-            CK(hipGetLastError());
-        }
-        CK(scan_exclusive(Z, cnt, scan, tot, ptr64, p->pair_ptr, s));
-        int64_t npairs = 0;
-        CK(hipMemcpyAsync(&npairs, ptr64 + Z, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        CK(hipStreamSynchronize(s));
-        if (npairs < 0 || npairs > (int64_t)INT_MAX) { st = ABILU_EPATTERN; goto fail; }
+        CKA(hipMalloc(&scratch, pattern_scratch_bytes(n, Z)));
+        CK(hipMemcpyAsync(p->rowptr, d_rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+        if (Z > 0) CK(hipMemcpyAsync(p->colidx, d_colidx, sizeof(int32_t) * Z, hipMemcpyDeviceToDevice, s));
+        st = pattern_count(n, Z, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow, p->pair_ptr, scratch,
+                           (int64_t *)p->pinned, s, &ZL, &ZU, &npairs);
+        if (st != ABILU_OK) goto fail;
+        p->nnzb_lower = ZL;
+        p->nnzb_upper = ZU;
         p->npairs = npairs;
+        CKA(hipMalloc(&p->lcol, sizeof(int32_t) * (ZL + 1)));
+        CKA(hipMalloc(&p->ucol, sizeof(int32_t) * (ZU + 1)));
         CKA(hipMalloc(&p->pik, sizeof(int32_t) * (npairs + 1)));
         CKA(hipMalloc(&p->pkj, sizeof(int32_t) * (npairs + 1)));
         CKA(hipMalloc(&p->sik, sizeof(int32_t) * (npairs + 1)));
         CKA(hipMalloc(&p->skj, sizeof(int32_t) * (npairs + 1)));
-        if (n > 0 && npairs > 0) {
-            k_pat_fill<<<div_up(n, 128), 128, 0, s>>>(n, (int)tri[0], p->rowptr, p->colidx, p->diag_pos, p->lrow,
-                                                       p->urow, ptr64, p->pik, p->pkj, p->sik, p->skj);
-            CK(hipGetLastError());
-        }
+        st = pattern_fill(n, Z, ZL, ZU, npairs, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow, p->lcol,
+                          p->ucol, p->pik, p->pkj, p->sik, p->skj, scratch, s);
+        if (st != ABILU_OK) goto fail;
         CK(hipStreamSynchronize(s));
     }
-    (void)hipFree(cnt);
-    (void)hipFree(scan);
-    (void)hipFree(ptr64);
-    (void)hipFree(tot);
-    (void)hipFree(err);
+    (void)hipFree(scratch);
     *out = p;
     return ABILU_OK;
 fail:
     (void)hipStreamSynchronize(s);
-    (void)hipFree(cnt);
-    (void)hipFree(scan);
-    (void)hipFree(ptr64);
-    (void)hipFree(tot);
-    (void)hipFree(err);
+    (void)hipFree(scratch);
     free_pattern(p);
     return st;
 #undef CK

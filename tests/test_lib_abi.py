@@ -80,3 +80,38 @@ def test_gen_rejects_bad_specs():
     spec = L.GenSpec(7, 3, 3, 1.0, 0)
     assert L.lib().abilu_gen_sizes(C.byref(spec), None, None) == L.ABILU_EINVAL
     assert L.lib().abilu_gen_build(None, None, None, None, None, None, None) == L.ABILU_EINVAL
+
+
+def test_serve_footprint_host_only():
+    """Pool bytes per request (no device work): about 3 kB per cell for an FP32 preconditioner,
+    an FP64 system and FGMRES(30) bases; FP64 factors, SYNC ping-pong buffers and longer
+    restarts cost more."""
+    req = dict(kind="tri", nx=224, ny=224, cfl=100.0, seed=1)
+    n, _ = L.abilu_gen_sizes(req)
+    base = L.abilu_serve_footprint(L.serve_config(), req)
+    assert 2.8e3 <= base / n <= 3.2e3
+    assert L.abilu_serve_footprint(L.serve_config(prec="f64"), req) > base
+    assert L.abilu_serve_footprint(L.serve_config(mode="sync", factor_sweeps=2), req) > base
+    assert L.abilu_serve_footprint(L.serve_config(restart=50), req) > base
+    assert L.abilu_serve_footprint(L.serve_config(restart=0), req) == 0
+    assert L.abilu_serve_footprint(L.serve_config(restart=257), req) == 0
+    assert L.abilu_serve_footprint(L.serve_config(max_active=0), req) == 0
+    assert L.abilu_serve_footprint(L.serve_config(), dict(kind="tri", nx=0, ny=1, cfl=1.0, seed=0)) == 0
+
+
+def test_serve_rejects_bad_arguments():
+    lib = L.lib()
+    out = C.c_void_p(1)
+    cfg = L.serve_config()
+    assert lib.abilu_serve_create(C.byref(cfg), None, 1 << 20, C.byref(out)) == L.ABILU_EINVAL
+    assert out.value is None
+    assert lib.abilu_serve_create(C.byref(cfg), C.c_void_p(4096 + 8), 1 << 20, C.byref(out)) == L.ABILU_EINVAL
+    bad = L.serve_config(prec="f32", maxit=-1)
+    assert lib.abilu_serve_create(C.byref(bad), C.c_void_p(4096), 1 << 20, C.byref(out)) == L.ABILU_EINVAL
+    assert lib.abilu_serve_create(C.byref(cfg), C.c_void_p(4096), 1 << 20, None) == L.ABILU_EINVAL
+    assert lib.abilu_serve_destroy(None) == L.ABILU_EINVAL
+    assert lib.abilu_serve_step(None, None, None, None) == L.ABILU_EINVAL
+    assert lib.abilu_serve_submit(None, None, None) == L.ABILU_EINVAL
+    done = C.c_int32()
+    assert lib.abilu_serve_poll(None, 0, C.byref(done), None) == L.ABILU_EINVAL
+    assert lib.abilu_serve_run(None, None, 0, None, None, None) == L.ABILU_EINVAL
