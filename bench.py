@@ -8,6 +8,10 @@ random permutation + reverse Cuthill-McKee). Factor and sweeps in FP32, Krylov i
 
 value = algorithmic bytes of every kernel of the step / wall time of the step (GB/s); the byte
 counts come from the library (one figure per launch, every array element counted once).
+
+The "serving" object measures the continuous-batching server on a stream of independent solves
+(FP32 preconditioner, batched launches) against one-solve-at-a-time FP64 on the same stream:
+solves/s at saturation and p50/p99 latency under Poisson arrivals.
 Prints one JSON line.
 """
 import argparse
@@ -132,6 +136,72 @@ def load_traffic(kernel, shash):
     return e.get("bytes_per_launch")
 
 
+def percentiles(lat):
+    import numpy as np
+    a = np.asarray(lat, dtype=np.float64)
+    return {"p50_ms": round(float(np.percentile(a, 50)) * 1e3, 3), "p99_ms": round(float(np.percentile(a, 99)) * 1e3, 3),
+            "mean_ms": round(float(a.mean()) * 1e3, 3), "max_ms": round(float(a.max()) * 1e3, 3)}
+
+
+def serving_bench(args):
+    """Continuous batching (FP32 preconditioner, FP64 Krylov, batched launches) against the plain
+    one-solve-at-a-time FP64 form, on the same request stream: saturation (all released at t = 0)
+    and Poisson arrivals at 0.8 x the one-at-a-time throughput."""
+    import numpy as np
+    import torch
+    from paper_1912_00539_amd import abilu as L
+    from paper_1912_00539_amd import workloads as W
+    reqs = W.serving_requests(args.serve_requests, seed=args.serve_seed)
+    common = dict(mode="async", factor_sweeps=args.build_sweeps, apply_sweeps=args.apply_sweeps, restart=30,
+                  maxit=300, rtol=args.rtol)
+    forms = {"batched_f32": L.serve_config(prec="f32", max_active=args.serve_slots, **common),
+             "one_at_a_time_f64": L.serve_config(prec="f64", max_active=1, **common)}
+    pool = torch.empty(int(args.serve_pool_gib * 2**30) // 256 * 256, dtype=torch.uint8, device="cuda")
+    warm = W.serving_requests(8, seed=args.serve_seed + 1)
+    for cfg in forms.values():
+        srv = L.Server(cfg, pool)
+        srv.run(warm)
+        srv.destroy()
+
+    def run(name, arrivals):
+        srv = L.Server(forms[name], pool)
+        res, el = srv.run(reqs, arrivals=arrivals)
+        srv.destroy()
+        lat = [r["t_done"] - r["t_arrival"] for r in res]
+        ok = sum(1 for r in res if r["converged"] and r["rel_true_residual"] <= args.rtol)
+        out = {"solves_per_s": round(len(reqs) / el, 2), "elapsed_s": round(el, 3), **percentiles(lat),
+               "converged": ok, "max_rel_true_residual": max(r["rel_true_residual"] for r in res),
+               "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
+               "max_admitted": None}
+        ev = sorted([(r["t_admit"], 1) for r in res] + [(r["t_done"], -1) for r in res], key=lambda e: (e[0], e[1]))
+        cur = peak = 0
+        for _, d in ev:
+            cur += d
+            peak = max(peak, cur)
+        out["max_admitted"] = peak
+        log(f"serving {name}: {out}")
+        return out
+
+    sat = {name: run(name, None) for name in forms}
+    lam = 0.8 * sat["one_at_a_time_f64"]["solves_per_s"]
+    u = W.uniform01(args.serve_seed, 14, np.arange(len(reqs), dtype=np.int64))
+    arrivals = np.cumsum(-np.log1p(-u) / lam)
+    poisson = {name: run(name, arrivals) for name in forms}
+    cells = [L.abilu_gen_sizes(r)[0] for r in reqs]
+    del pool
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{len(reqs)} independent FGMRES(30) solves to rtol {args.rtol}: split-quad triangle or "
+                    "anisotropic-quad meshes (50/50), cells log-uniform in [1e4, 1e6] "
+                    f"(mean {np.mean(cells):.0f}, total {np.sum(cells)}), CFL ~ U(10, 1000), generated on the device",
+        "preconditioner": f"ASYNC, {args.build_sweeps} factor sweep(s), {args.apply_sweeps} apply sweep pairs",
+        "pool_GiB": args.serve_pool_gib, "slots": args.serve_slots,
+        "saturation": sat,
+        "poisson": {"rate_per_s": round(lam, 2), **poisson},
+        "speedup_solves_per_s": round(sat["batched_f32"]["solves_per_s"] / sat["one_at_a_time_f64"]["solves_per_s"], 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +219,12 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-seed", type=int, default=7)
+    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-pool-gib", type=float, default=64.0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--only-serving", action="store_true", help="print the serving object alone (profiling)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -164,6 +240,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     L.lib()
+    if args.only_serving:
+        print(json.dumps({"serving": serving_bench(args)}), flush=True)
+        return
     t = time.perf_counter()
     case = W.case(args.workload)
     log(f"generated {args.workload}: N={case.n} Z={case.nnzb} in {time.perf_counter() - t:.1f} s")
@@ -256,6 +335,9 @@ def main():
         "compare": compare,
         "source_hash": shash,
     }
+    del sysm
+    torch.cuda.empty_cache()
+    out["serving"] = None if args.no_serving else serving_bench(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(case, args)

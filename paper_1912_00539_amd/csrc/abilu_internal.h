@@ -100,6 +100,12 @@ hipError_t scan_exclusive(int64_t len, const int64_t *in, int64_t *tmp, int64_t 
 // (pattern.hip; used by abilu_build_pattern and by the server, which carves the arrays out of its
 // pool). Scratch: pattern_scratch_bytes(n, Z) device bytes, kept between the two stages.
 size_t pattern_scratch_bytes(int32_t n, int64_t Z);
+abilu_status pattern_validate_async(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx,
+                                    int32_t *diag_pos, void *scratch, unsigned *h_err, hipStream_t s);
+abilu_status pattern_count_async(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx,
+                                 const int32_t *diag_pos, int32_t *lrow, int32_t *urow, int32_t *pair_ptr,
+                                 void *scratch, int64_t *h_sizes, hipStream_t s);
+bool pattern_sizes_ok(int32_t n, int64_t Z, const int64_t *sizes);   // sizes = {ZL, ZU, npairs}
 abilu_status pattern_count(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx, int32_t *diag_pos,
                            int32_t *lrow, int32_t *urow, int32_t *pair_ptr, void *scratch, int64_t *h_pinned,
                            hipStream_t s, int64_t *ZL, int64_t *ZU, int64_t *npairs);

@@ -137,12 +137,27 @@ size_t pattern_scratch_bytes(int32_t n, int64_t Z) {
     return 256 + sizeof(int64_t) * (size_t)(3 * len + scan_tiles(Z > n ? Z : n) + 1);
 }
 
-// Validation, diagonal positions, lower/upper row offsets and the update-set offsets
-// (pair_ptr). Blocking: reads back the error word and the three totals (two stream syncs).
-abilu_status pattern_count(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx, int32_t *diag_pos,
-                           int32_t *lrow, int32_t *urow, int32_t *pair_ptr, void *scratch, int64_t *h_pinned,
-                           hipStream_t s, int64_t *ZL, int64_t *ZU, int64_t *npairs) {
+// Non-blocking stage 1a: validation and diagonal positions; the error word (nonzero: invalid
+// pattern) is copied to h_err when the stream reaches it.
+abilu_status pattern_validate_async(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx,
+                                    int32_t *diag_pos, void *scratch, unsigned *h_err, hipStream_t s) {
     unsigned *err = (unsigned *)scratch;
+    if (!hip_ok(hipMemsetAsync(err, 0, sizeof(unsigned), s), "pattern error clear")) return ABILU_EDEVICE;
+    if (n > 0) {
+        k_pat_rows<<<div_up(n, 256), 256, 0, s>>>(n, Z, rowptr, colidx, diag_pos, err);
+        if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+    }
+    if (!hip_ok(hipMemcpyAsync(h_err, err, sizeof(unsigned), hipMemcpyDeviceToHost, s), "pattern error readback"))
+        return ABILU_EDEVICE;
+    return ABILU_OK;
+}
+
+// Non-blocking stage 1b (valid patterns only): lower/upper row offsets and the update-set
+// offsets (pair_ptr); h_sizes receives ZL, ZU and the number of pairs. ptr64 in the scratch
+// keeps the int64 pair offsets for pattern_fill.
+abilu_status pattern_count_async(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx,
+                                 const int32_t *diag_pos, int32_t *lrow, int32_t *urow, int32_t *pair_ptr,
+                                 void *scratch, int64_t *h_sizes, hipStream_t s) {
     const int64_t len = Z + n + 2;
     int64_t *cnt = (int64_t *)((char *)scratch + 256);
     int64_t *tmp = cnt + len, *ptr64 = tmp + len, *tot = ptr64 + len;
@@ -150,37 +165,44 @@ abilu_status pattern_count(int32_t n, int64_t Z, const int32_t *rowptr, const in
     do {                                                   \
         if (!hip_ok((x), #x)) return ABILU_EDEVICE;        \
     } while (0)
-    CK(hipMemsetAsync(err, 0, sizeof(unsigned), s));
-    if (n > 0) {
-        k_pat_rows<<<div_up(n, 256), 256, 0, s>>>(n, Z, rowptr, colidx, diag_pos, err);
-        CK(hipGetLastError());
-    }
-    CK(hipMemcpyAsync(h_pinned, err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
-    if (*(const unsigned *)h_pinned) return ABILU_EPATTERN;
-    // row offsets of the strictly lower / upper parts of the factor layout
     if (n > 0) {
         k_pat_tri_counts<<<div_up(n, 256), 256, 0, s>>>(n, rowptr, diag_pos, cnt, cnt + (n + 1));
         CK(hipGetLastError());
     }
     for (int part = 0; part < 2; ++part) {
         CK(scan_exclusive(n, cnt + (part == 0 ? 0 : (n + 1)), tmp, tot, ptr64, part == 0 ? lrow : urow, s));
-        CK(hipMemcpyAsync(h_pinned + part, ptr64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(h_sizes + part, ptr64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     }
-    // update-set sizes and offsets; ptr64 keeps the int64 offsets for pattern_fill
     if (n > 0) {
         k_pat_count<<<div_up(n, 128), 128, 0, s>>>(n, rowptr, colidx, cnt);
         CK(hipGetLastError());
     }
     CK(scan_exclusive(Z, cnt, tmp, tot, ptr64, pair_ptr, s));
-    CK(hipMemcpyAsync(h_pinned + 2, ptr64 + Z, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
+    CK(hipMemcpyAsync(h_sizes + 2, ptr64 + Z, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    return ABILU_OK;
+#undef CK
+}
+
+bool pattern_sizes_ok(int32_t n, int64_t Z, const int64_t *sizes) {
+    return sizes[0] >= 0 && sizes[1] >= 0 && sizes[0] + sizes[1] + n == Z && sizes[2] >= 0 &&
+           sizes[2] <= (int64_t)INT_MAX;
+}
+
+// Blocking stage 1 (two stream syncs).
+abilu_status pattern_count(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx, int32_t *diag_pos,
+                           int32_t *lrow, int32_t *urow, int32_t *pair_ptr, void *scratch, int64_t *h_pinned,
+                           hipStream_t s, int64_t *ZL, int64_t *ZU, int64_t *npairs) {
+    abilu_status st = pattern_validate_async(n, Z, rowptr, colidx, diag_pos, scratch, (unsigned *)h_pinned, s);
+    if (st != ABILU_OK) return st;
+    if (!hip_ok(hipStreamSynchronize(s), "pattern validation sync")) return ABILU_EDEVICE;
+    if (*(const unsigned *)h_pinned) return ABILU_EPATTERN;
+    st = pattern_count_async(n, Z, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, scratch, h_pinned, s);
+    if (st != ABILU_OK) return st;
+    if (!hip_ok(hipStreamSynchronize(s), "pattern count sync")) return ABILU_EDEVICE;
     *ZL = h_pinned[0];
     *ZU = h_pinned[1];
     *npairs = h_pinned[2];
-    if (*ZL + *ZU + n != Z || *npairs < 0 || *npairs > (int64_t)INT_MAX) return ABILU_EPATTERN;
-    return ABILU_OK;
-#undef CK
+    return pattern_sizes_ok(n, Z, h_pinned) ? ABILU_OK : ABILU_EPATTERN;
 }
 
 // Columns of the lower/upper parts and the update-set lists (non-blocking; the scratch must

@@ -36,6 +36,7 @@ namespace {
 constexpr int HDR = 128;        // per-slot status header: flags word at 0, status doubles at 64
 constexpr int MAX_SLOTS = 4096;
 constexpr int ONE_WG = 64;      // threads per workgroup of the single-lane kernels
+constexpr int64_t ADMIT_MIN_CELLS = 1 << 20;   // admission budget per step when few cells are active
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -374,36 +375,41 @@ struct abilu_server {
 
 namespace {
 
-abilu_status fail_request(abilu_server *s, Req &r, abilu_status st) {
-    (void)s;
-    r.state = Q_DONE;
-    r.res.status = st;
-    r.res.t_done = now_s() - s->t0;
-    return ABILU_OK;
+// Admission of a batch of requests on the setup stream, in three passes with one stream sync
+// between them (not one per request): device generation of each system and validation of its
+// pattern; update-set counts; then the fill, the status header and the slot descriptor. A
+// request whose pattern is invalid or exceeds its reserved capacity fails alone.
+char *block_ptr(abilu_server *s, const Req &r, size_t o) { return o == NONE ? nullptr : s->pool + r.off + o; }
+
+abilu_status admit_begin(abilu_server *s, Req &r) {
+    const ReqLayout &L = r.L;
+    int32_t *rowptr = (int32_t *)block_ptr(s, r, L.rowptr), *colidx = (int32_t *)block_ptr(s, r, L.colidx);
+    if (abilu_gen_build(&r.spec, rowptr, colidx, (double *)block_ptr(s, r, L.A), (double *)block_ptr(s, r, L.b),
+                        block_ptr(s, r, L.scratch), s->setup) != ABILU_OK)
+        return ABILU_EDEVICE;
+    return pattern_validate_async(r.n, r.Z, rowptr, colidx, (int32_t *)block_ptr(s, r, L.diag_pos),
+                                  block_ptr(s, r, L.scratch), (unsigned *)(s->h_small + 8 * r.slot), s->setup);
 }
 
-// Generate and analyse request r into its pool block on the setup stream (blocking on that
-// stream only), then publish its slot descriptor. Returns a device error; request-level
-// failures are recorded in r.
-abilu_status admit(abilu_server *s, Req &r, int slot) {
-    const abilu_serve_config &c = s->cfg;
-    char *base = s->pool + r.off;
-    auto P = [&](size_t o) -> void * { return o == NONE ? nullptr : (void *)(base + o); };
+abilu_status admit_count(abilu_server *s, Req &r) {
     const ReqLayout &L = r.L;
+    return pattern_count_async(r.n, r.Z, (const int32_t *)block_ptr(s, r, L.rowptr),
+                               (const int32_t *)block_ptr(s, r, L.colidx), (const int32_t *)block_ptr(s, r, L.diag_pos),
+                               (int32_t *)block_ptr(s, r, L.lrow), (int32_t *)block_ptr(s, r, L.urow),
+                               (int32_t *)block_ptr(s, r, L.pair_ptr), block_ptr(s, r, L.scratch),
+                               s->h_small + 8 * r.slot + 1, s->setup);
+}
+
+abilu_status admit_finish(abilu_server *s, Req &r, int64_t ZL, int64_t ZU, int64_t np) {
+    const ReqLayout &L = r.L;
+    auto P = [&](size_t o) -> void * { return block_ptr(s, r, o); };
+    const int slot = r.slot;
     hipStream_t st = s->setup;
     int32_t *rowptr = (int32_t *)P(L.rowptr), *colidx = (int32_t *)P(L.colidx);
-    if (abilu_gen_build(&r.spec, rowptr, colidx, (double *)P(L.A), (double *)P(L.b), P(L.scratch), st) != ABILU_OK)
-        return ABILU_EDEVICE;
-    int64_t ZL = 0, ZU = 0, np = 0;
-    abilu_status ps = pattern_count(r.n, r.Z, rowptr, colidx, (int32_t *)P(L.diag_pos), (int32_t *)P(L.lrow),
-                                    (int32_t *)P(L.urow), (int32_t *)P(L.pair_ptr), P(L.scratch), s->h_small, st,
-                                    &ZL, &ZU, &np);
-    if (ps == ABILU_EDEVICE) return ps;
-    if (ps == ABILU_OK && (ZL > L.zcap || ZU > L.zcap || np > L.pcap)) ps = ABILU_EPATTERN;
-    if (ps != ABILU_OK) return fail_request(s, r, ps);
-    ps = pattern_fill(r.n, r.Z, ZL, ZU, np, rowptr, colidx, (int32_t *)P(L.diag_pos), (int32_t *)P(L.lrow),
-                      (int32_t *)P(L.urow), (int32_t *)P(L.lcol), (int32_t *)P(L.ucol), (int32_t *)P(L.pik),
-                      (int32_t *)P(L.pkj), (int32_t *)P(L.sik), (int32_t *)P(L.skj), P(L.scratch), st);
+    abilu_status ps = pattern_fill(r.n, r.Z, ZL, ZU, np, rowptr, colidx, (int32_t *)P(L.diag_pos),
+                                   (int32_t *)P(L.lrow), (int32_t *)P(L.urow), (int32_t *)P(L.lcol),
+                                   (int32_t *)P(L.ucol), (int32_t *)P(L.pik), (int32_t *)P(L.pkj), (int32_t *)P(L.sik),
+                                   (int32_t *)P(L.skj), P(L.scratch), st);
     if (ps != ABILU_OK) return ps;
     Slot &d = s->h_slots[slot];
     d = Slot{};
@@ -446,13 +452,11 @@ abilu_status admit(abilu_server *s, Req &r, int slot) {
     d.Z = (double *)P(L.Z);
     d.flags = (unsigned *)(s->d_hdr + (size_t)slot * HDR);
     d.status = (double *)(s->d_hdr + (size_t)slot * HDR + 64);
-    (void)c;
     if (!hip_ok(hipMemsetAsync(s->d_hdr + (size_t)slot * HDR, 0, HDR, st), "serve header clear") ||
         !hip_ok(hipMemsetAsync(d.misc, 0, 8 * 16, st), "serve misc clear") ||
         !hip_ok(hipMemcpyAsync(s->d_slots + slot, &d, sizeof(Slot), hipMemcpyHostToDevice, st), "serve slot upload") ||
         !hip_ok(hipEventRecord(s->ev[slot], st), "serve setup event"))
         return ABILU_EDEVICE;
-    r.slot = slot;
     r.state = Q_READY;
     r.res.t_admit = now_s() - s->t0;
     return ABILU_OK;
@@ -466,26 +470,59 @@ void release(abilu_server *s, Req &r) {
     s->alloc.release(r.off, r.L.total);
 }
 
-// Admit queued requests in arrival order while a slot and pool space are free.
-abilu_status admit_queued(abilu_server *s) {
+void fail_request(abilu_server *s, Req &r, abilu_status st) {
+    r.state = Q_DONE;
+    r.res.status = st;
+    r.res.t_done = now_s() - s->t0;
+    release(s, r);
+}
+
+// Admit queued requests in arrival order while a slot and pool space are free (the head of the
+// queue waits for memory; later requests do not overtake it), at most `cell_budget` block rows
+// per call beyond the first request: admission then proceeds alongside the ticks instead of
+// filling the pool in one burst whose requests would all finish together.
+abilu_status admit_queued(abilu_server *s, int64_t cell_budget) {
+    std::vector<int64_t> batch;
+    int slot = 0;
+    int64_t cells = 0;
     while (!s->queue.empty()) {
+        if (!batch.empty() && cells + s->reqs[s->queue.front()].n > cell_budget) break;
+        while (slot < s->cfg.max_active && s->slot_req[slot] >= 0) ++slot;
+        if (slot >= s->cfg.max_active) break;
         Req &r = s->reqs[s->queue.front()];
-        int slot = -1;
-        for (int q = 0; q < s->cfg.max_active; ++q)
-            if (s->slot_req[q] < 0) {
-                slot = q;
-                break;
-            }
-        if (slot < 0) return ABILU_OK;
         size_t off = 0;
-        if (!s->alloc.alloc(r.L.total, &off)) return ABILU_OK;   // head of line waits for memory
+        if (!s->alloc.alloc(r.L.total, &off)) break;
         const int64_t id = s->queue.front();
         s->queue.pop_front();
         r.off = off;
+        r.slot = slot;
         s->slot_req[slot] = id;
-        const abilu_status st = admit(s, r, slot);
-        if (st != ABILU_OK) return st;
-        if (r.state == Q_DONE) release(s, r);
+        batch.push_back(id);
+        cells += r.n;
+    }
+    if (batch.empty()) return ABILU_OK;
+    for (int64_t id : batch)
+        if (admit_begin(s, s->reqs[id]) != ABILU_OK) return ABILU_EDEVICE;
+    if (!hip_ok(hipStreamSynchronize(s->setup), "serve admission sync")) return ABILU_EDEVICE;
+    std::vector<int64_t> valid;
+    for (int64_t id : batch) {
+        Req &r = s->reqs[id];
+        if (*(const unsigned *)(s->h_small + 8 * r.slot)) {
+            fail_request(s, r, ABILU_EPATTERN);
+            continue;
+        }
+        if (admit_count(s, r) != ABILU_OK) return ABILU_EDEVICE;
+        valid.push_back(id);
+    }
+    if (!hip_ok(hipStreamSynchronize(s->setup), "serve admission sync")) return ABILU_EDEVICE;
+    for (int64_t id : valid) {
+        Req &r = s->reqs[id];
+        const int64_t *sz = s->h_small + 8 * r.slot + 1;
+        if (!pattern_sizes_ok(r.n, r.Z, sz) || sz[0] > r.L.zcap || sz[1] > r.L.zcap || sz[2] > r.L.pcap) {
+            fail_request(s, r, ABILU_EPATTERN);
+            continue;
+        }
+        if (admit_finish(s, r, sz[0], sz[1], sz[2]) != ABILU_OK) return ABILU_EDEVICE;
     }
     return ABILU_OK;
 }
@@ -788,8 +825,7 @@ void advance(abilu_server *s, Req &r) {
 }
 
 abilu_status step_impl(abilu_server *s, hipStream_t st) {
-    abilu_status e = admit_queued(s);
-    if (e != ABILU_OK) return e;
+    abilu_status e;
     Group groups[3] = {{Q_FACTOR, {}, {}}, {Q_ITER, {}, {}}, {Q_CYCLE_END, {}, {}}};
     for (int q = 0; q < s->cfg.max_active; ++q) {
         const int64_t id = s->slot_req[q];
@@ -820,7 +856,11 @@ abilu_status step_impl(abilu_server *s, hipStream_t st) {
             used += T.count;
         }
     }
-    if (used == 0) return ABILU_OK;
+    int64_t tick_cells = 0;
+    for (const Group &G : groups)
+        for (int64_t id : G.ids) tick_cells += s->reqs[id].n;
+    const int64_t budget = std::max<int64_t>(ADMIT_MIN_CELLS, tick_cells);
+    if (used == 0) return admit_queued(s, budget);
     if (!hip_ok(hipMemcpyAsync(s->d_tab, s->h_tab, sizeof(Member) * used, hipMemcpyHostToDevice, st), "serve tables"))
         return ABILU_EDEVICE;
     for (Group &G : groups) {
@@ -829,9 +869,11 @@ abilu_status step_impl(abilu_server *s, hipStream_t st) {
         if (e != ABILU_OK) return e;
     }
     if (!hip_ok(hipMemcpyAsync(s->h_hdr, s->d_hdr, (size_t)s->cfg.max_active * HDR, hipMemcpyDeviceToHost, st),
-                "serve status readback") ||
-        !hip_ok(hipStreamSynchronize(st), "serve tick sync"))
+                "serve status readback"))
         return ABILU_EDEVICE;
+    // admissions run on the setup stream while the device works through the tick
+    if ((e = admit_queued(s, budget)) != ABILU_OK) return e;
+    if (!hip_ok(hipStreamSynchronize(st), "serve tick sync")) return ABILU_EDEVICE;
     // advance, retire finished requests (copy x out first)
     bool copied = false;
     std::vector<int64_t> done;
@@ -950,7 +992,7 @@ extern "C" abilu_status abilu_serve_create(const abilu_serve_config *cfg, void *
               hip_ok(hipHostMalloc((void **)&s->h_tab, sizeof(Member) * s->tab_cap, hipHostMallocDefault),
                      "serve pinned") &&
               hip_ok(hipHostMalloc((void **)&s->h_hdr, (size_t)HDR * S, hipHostMallocDefault), "serve pinned") &&
-              hip_ok(hipHostMalloc((void **)&s->h_small, 64 * sizeof(int64_t), hipHostMallocDefault), "serve pinned");
+              hip_ok(hipHostMalloc((void **)&s->h_small, 8 * sizeof(int64_t) * S, hipHostMallocDefault), "serve pinned");
     for (int q = 0; ok && q < S; ++q)
         ok = hip_ok(hipEventCreateWithFlags(&s->ev[q], hipEventDisableTiming), "serve events");
     if (ok) ok = hip_ok(hipMemset(s->d_hdr, 0, (size_t)HDR * S), "serve header init");
