@@ -166,13 +166,15 @@ def serving_bench(args):
     def run(name, arrivals):
         srv = L.Server(forms[name], pool)
         res, el = srv.run(reqs, arrivals=arrivals)
+        stats = srv.stats()
         srv.destroy()
         lat = [r["t_done"] - r["t_arrival"] for r in res]
         ok = sum(1 for r in res if r["converged"] and r["rel_true_residual"] <= args.rtol)
         out = {"solves_per_s": round(len(reqs) / el, 2), "elapsed_s": round(el, 3), **percentiles(lat),
                "converged": ok, "max_rel_true_residual": max(r["rel_true_residual"] for r in res),
                "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
-               "max_admitted": None}
+               "solve_path_GBps": round(stats["bytes"] / el / 1e9, 1), "ticks": stats["ticks"],
+               "launches": stats["launches"], "max_admitted": None}
         ev = sorted([(r["t_admit"], 1) for r in res] + [(r["t_done"], -1) for r in res], key=lambda e: (e[0], e[1]))
         cur = peak = 0
         for _, d in ev:

@@ -97,6 +97,19 @@ abilu_status abilu_serve_poll(abilu_server *srv, int64_t id, int32_t *done, abil
 abilu_status abilu_serve_run(abilu_server *srv, const abilu_request *reqs, int32_t count,
                              abilu_request_result *results, double *elapsed_s, void *stream);
 
+typedef struct {
+    int64_t ticks;      /* ticks that launched work */
+    int64_t launches;   /* batched kernel launches */
+    int64_t admitted;   /* requests admitted (generated and analysed) */
+    int64_t retired;    /* requests finished after at least one tick */
+    double bytes;       /* algorithmic bytes of the batched solve kernels: for every launch, the
+                           sum over its members of what the single-system kernel touches (every
+                           array element once); generation and pattern analysis not included */
+} abilu_serve_stats_t;
+
+/* Counters since the server was created (host only). */
+abilu_status abilu_serve_stats(const abilu_server *srv, abilu_serve_stats_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,14 @@ class RequestResult(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class ServeStats(C.Structure):
+    _fields_ = [("ticks", C.c_int64), ("launches", C.c_int64), ("admitted", C.c_int64), ("retired", C.c_int64),
+                ("bytes", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 def serve_config(prec: str = "f32", mode: str = "async", factor_sweeps: int = 1, apply_sweeps: int = 3,
                  restart: int = 30, maxit: int = 300, rtol: float = 1e-2, max_active: int = 64) -> ServeConfig:
     return ServeConfig(PRECS[prec], MODES[mode], int(factor_sweeps), int(apply_sweeps), int(restart), int(maxit),
@@ -129,6 +137,7 @@ def lib():
             "abilu_serve_poll": ([vp, i64, C.POINTER(i32), C.POINTER(RequestResult)], st),
             "abilu_serve_run": ([vp, C.POINTER(Request), i32, C.POINTER(RequestResult), C.POINTER(C.c_double), vp],
                                 st),
+            "abilu_serve_stats": ([vp, C.POINTER(ServeStats)], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -340,6 +349,11 @@ class Server:
         el = C.c_double()
         _check(lib().abilu_serve_run(self.handle, arr, cnt, res, C.byref(el), _stream(stream)), "abilu_serve_run")
         return [res[q].as_dict() for q in range(cnt)], el.value
+
+    def stats(self) -> dict:
+        out = ServeStats()
+        _check(lib().abilu_serve_stats(self.handle, C.byref(out)), "abilu_serve_stats")
+        return out.as_dict()
 
     def destroy(self):
         if self.handle is not None and self.handle.value:

@@ -75,6 +75,7 @@ struct ProfScope {
 };
 int prof_mark();                          // index of the next profiled launch
 void prof_cancel_bytes(int from, int to); // zero the bytes of launches [from, to): skipped work
+void prof_add_bytes(int slot, double delta);  // correct the bytes of one profiled launch
 
 abilu_status launch_status();   // hipGetLastError -> status (records the error text)
 
@@ -87,6 +88,42 @@ struct Sizes {
 };
 inline Sizes sizes(const abilu_pattern *p) {
     return Sizes{(double)p->n, (double)p->nnzb, (double)p->nnzb_lower, (double)p->nnzb_upper, (double)p->npairs};
+}
+
+// Algorithmic bytes of one launch (every element touched once; gathered vector entries once).
+// forward: lrow, columns and blocks of the strictly lower part, r (f64),
+// input vector (element size sY), output vector; EMIT_Z adds Dinv and the z output.
+inline double bytes_fwd(const Sizes &z, double sF, double sY, bool emit) {
+    double b = 4 * (z.N + 1) + 4 * z.ZL + 16 * sF * z.ZL + 32 * z.N + 4 * z.N * sY + 4 * z.N * sF;
+    return emit ? b + 16 * sF * z.N + 4 * z.N * sF : b;
+}
+// backward: urow, columns and blocks of the strictly upper part, y, z input,
+// Dinv, output (element size sZ), optional second output in precision sF
+inline double bytes_bwd(const Sizes &z, double sF, double sZ, bool dual) {
+    double b = 4 * (z.N + 1) + 4 * z.ZU + 16 * sF * z.ZU + 4 * z.N * sF + 4 * z.N * sF + 16 * sF * z.N + 4 * z.N * sZ;
+    return dual ? b + 4 * z.N * sF : b;
+}
+
+// Algorithmic bytes of one launch: every array element touched once.
+// init with copy: rowptr, diag_pos, lrow, urow, A (f64), X0 written, Dinv written
+// init without copy: diag_pos, diagonal blocks of the source, Dinv written
+inline double bytes_init(const Sizes &z, double sS, double sF, bool copy) {
+    if (copy) return 4 * (z.N + 1) + 12 * z.N + 128 * z.Z + 16 * sF * z.Z + 16 * sF * z.N;
+    return 4 * z.N + 16 * sS * z.N + 16 * sF * z.N;
+}
+// sweep: rowptr, diag_pos, lrow, urow, colidx of strictly lower blocks, pair_ptr at 4 places per
+// row, the pair lists, A (f64), the blocks the update sets read from X (min(2P, Z) of them, half
+// on each side; none when a side comes from A), Dinv read, X written, Dinv written
+inline double bytes_sweep(const Sizes &z, double sF, bool l_from_a, bool u_from_a) {
+    const double m = (2 * z.P < z.Z ? 2 * z.P : z.Z) / 2;
+    const double xr = (l_from_a ? 0.0 : 16 * sF * m) + (u_from_a ? 0.0 : 16 * sF * m);
+    return 4 * (z.N + 1) + 12 * z.N + 4 * z.ZL + 16 * z.N + 8 * z.P + 128 * z.Z + xr + 16 * sF * z.N +
+           16 * sF * z.Z + 16 * sF * z.N;
+}
+
+// SpMV: rowptr, colidx, A (f64), x gathered once, y written (+ b read when RESID)
+inline double bytes_spmv(const Sizes &z, bool resid) {
+    return 4 * (z.N + 1) + 4 * z.Z + 128 * z.Z + 32 * z.N + 32 * z.N + (resid ? 32 * z.N : 0.0);
 }
 
 // ------------------------------------------------------------------ device prefix sums (scan.hip)

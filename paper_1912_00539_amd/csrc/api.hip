@@ -89,6 +89,10 @@ ProfScope::ProfScope(const char *name, hipStream_t s, double bytes) : slot(-1), 
 
 int prof_mark() { return g_prof.on ? g_prof.used : 0; }
 
+void prof_add_bytes(int slot, double delta) {
+    if (g_prof.on && slot >= 0 && slot < g_prof.used) g_prof.bytes_of_slot[slot] += delta;
+}
+
 void prof_cancel_bytes(int from, int to) {
     if (!g_prof.on) return;
     for (int q = from; q < to && q < g_prof.used; ++q) g_prof.bytes_of_slot[q] = 0.0;

@@ -62,20 +62,6 @@ const char *tname<float>() { return "f32"; }
 template <>
 const char *tname<double>() { return "f64"; }
 
-// Algorithmic bytes of one launch (every element touched once; gathered vector entries once).
-// forward: lrow, columns and blocks of the strictly lower part, r (f64),
-// input vector (element size sY), output vector; EMIT_Z adds Dinv and the z output.
-double bytes_fwd(const Sizes &z, double sF, double sY, bool emit) {
-    double b = 4 * (z.N + 1) + 4 * z.ZL + 16 * sF * z.ZL + 32 * z.N + 4 * z.N * sY + 4 * z.N * sF;
-    return emit ? b + 16 * sF * z.N + 4 * z.N * sF : b;
-}
-// backward: urow, columns and blocks of the strictly upper part, y, z input,
-// Dinv, output (element size sZ), optional second output in precision sF
-double bytes_bwd(const Sizes &z, double sF, double sZ, bool dual) {
-    double b = 4 * (z.N + 1) + 4 * z.ZU + 16 * sF * z.ZU + 4 * z.N * sF + 4 * z.N * sF + 16 * sF * z.N + 4 * z.N * sZ;
-    return dual ? b + 4 * z.N * sF : b;
-}
-
 template <typename T>
 abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const double *r, double *z, int nsw,
                      abilu_mode mode, char *work, const Workspace &W, hipStream_t s) {
@@ -191,13 +177,11 @@ abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x,
     if (p->n == 0) return ABILU_OK;
     const int grid = div_up(p->n, ROWS_PER_WG);
     const Sizes z = sizes(p);
-    // rowptr, colidx, A (f64), x gathered once, y written (+ b read)
-    const double by = 4 * (z.N + 1) + 4 * z.Z + 128 * z.Z + 32 * z.N + 32 * z.N;
     if (b) {
-        ProfScope ps("spmv_resid", s, by + 32 * z.N);
+        ProfScope ps("spmv_resid", s, bytes_spmv(z, true));
         k_spmv<true><<<grid, WG, 0, s>>>(p->n, p->rowptr, p->colidx, A, x, y, b);
     } else {
-        ProfScope ps("spmv", s, by);
+        ProfScope ps("spmv", s, bytes_spmv(z, false));
         k_spmv<false><<<grid, WG, 0, s>>>(p->n, p->rowptr, p->colidx, A, x, y, nullptr);
     }
     return launch_status();

@@ -80,23 +80,6 @@ const char *tname<float>() { return "f32"; }
 template <>
 const char *tname<double>() { return "f64"; }
 
-// Algorithmic bytes of one launch: every array element touched once.
-// init with copy: rowptr, diag_pos, lrow, urow, A (f64), X0 written, Dinv written
-// init without copy: diag_pos, diagonal blocks of the source, Dinv written
-double bytes_init(const Sizes &z, double sS, double sF, bool copy) {
-    if (copy) return 4 * (z.N + 1) + 12 * z.N + 128 * z.Z + 16 * sF * z.Z + 16 * sF * z.N;
-    return 4 * z.N + 16 * sS * z.N + 16 * sF * z.N;
-}
-// sweep: rowptr, diag_pos, lrow, urow, colidx of strictly lower blocks, pair_ptr at 4 places per
-// row, the pair lists, A (f64), the blocks the update sets read from X (min(2P, Z) of them, half
-// on each side; none when a side comes from A), Dinv read, X written, Dinv written
-double bytes_sweep(const Sizes &z, double sF, bool l_from_a, bool u_from_a) {
-    const double m = (2 * z.P < z.Z ? 2 * z.P : z.Z) / 2;
-    const double xr = (l_from_a ? 0.0 : 16 * sF * m) + (u_from_a ? 0.0 : 16 * sF * m);
-    return 4 * (z.N + 1) + 12 * z.N + 4 * z.ZL + 16 * z.N + 8 * z.P + 128 * z.Z + xr + 16 * sF * z.N +
-           16 * sF * z.Z + 16 * sF * z.N;
-}
-
 template <typename T, bool LA, bool UA>
 void launch_sweep(const abilu_pattern *p, int grid, hipStream_t s, const double *A, const T *XL, const T *XU,
                   const T *Dp, T *Xn, T *Dn, unsigned *flags) {

@@ -346,7 +346,7 @@ struct Req {
     size_t off = 0;
     ReqLayout L{};
     int32_t n = 0;
-    int64_t Z = 0;
+    int64_t Z = 0, ZL = 0, ZU = 0, P = 0;   // pattern sizes (after admission)
     int k = 0, iters = 0, restarts = 0, reorth = 0;
     double bnorm = 0, tol = 0, beta = 0, est = 0;
     uint32_t flags = 0;
@@ -371,6 +371,8 @@ struct abilu_server {
     std::deque<int64_t> queue;                     // released, not yet admitted (FIFO)
     std::vector<int64_t> slot_req;                 // slot -> request id or -1
     double t0 = 0.0;                               // clock origin
+    double stat_bytes = 0.0;                       // algorithmic bytes of the batched launches
+    int64_t stat_launches = 0, stat_ticks = 0, stat_admitted = 0, stat_retired = 0;
 };
 
 namespace {
@@ -411,6 +413,9 @@ abilu_status admit_finish(abilu_server *s, Req &r, int64_t ZL, int64_t ZU, int64
                                    (int32_t *)P(L.ucol), (int32_t *)P(L.pik), (int32_t *)P(L.pkj), (int32_t *)P(L.sik),
                                    (int32_t *)P(L.skj), P(L.scratch), st);
     if (ps != ABILU_OK) return ps;
+    r.ZL = ZL;
+    r.ZU = ZU;
+    r.P = np;
     Slot &d = s->h_slots[slot];
     d = Slot{};
     d.n = r.n;
@@ -459,6 +464,7 @@ abilu_status admit_finish(abilu_server *s, Req &r, int64_t ZL, int64_t ZU, int64
         return ABILU_EDEVICE;
     r.state = Q_READY;
     r.res.t_admit = now_s() - s->t0;
+    ++s->stat_admitted;
     return ABILU_OK;
 }
 
@@ -550,9 +556,11 @@ struct Group {
     State st;
     std::vector<int64_t> ids;
     Table t[SH_COUNT];
+    int pass2 = 0;              // profile slot of the first launch of the second Gram-Schmidt pass
 };
 
-// Kernel launches of one group (identical sequence for every member).
+// Kernel launches of one group (identical sequence for every member). Every launch is recorded
+// with the sum over its members of the single-system kernel's algorithmic bytes.
 template <typename T>
 abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
     const abilu_serve_config &c = s->cfg;
@@ -560,6 +568,19 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
     const int m = c.restart;
     const int nsw = c.apply_sweeps, fsw = c.factor_sweeps;
     const bool sync = c.mode == ABILU_SYNC;
+    const double sF = sizeof(T);
+    // sum of f(sizes, request) over the members
+    auto B = [&](auto f) {
+        double b = 0;
+        for (int64_t id : G.ids) {
+            const Req &r = s->reqs[id];
+            b += f(Sizes{(double)r.n, (double)r.Z, (double)r.ZL, (double)r.ZU, (double)r.P}, r);
+        }
+        s->stat_bytes += b;
+        ++s->stat_launches;
+        return b;
+    };
+    auto nv8 = [](const Sizes &z) { return 32.0 * z.N; };   // bytes of one FP64 Krylov vector
 #define L_(shape) dim3(G.t[shape].tiles), dim3(WG), 0, st
 #define A_(shape) sl, G.t[shape].d, G.t[shape].count
 #define ONE_() dim3(div_up(G.t[SH_ONE].count, ONE_WG)), dim3(ONE_WG), 0, st
@@ -567,14 +588,17 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
     do {                                                       \
         if (launch_status() != ABILU_OK) return ABILU_EDEVICE; \
     } while (0)
+    // dots of w with V_0..V_{q-1} and ||w||^2; q = k + q_plus, or 0 when q_plus < 0
     auto mdot = [&](int w, int q_plus, int guard) -> abilu_status {
+        auto qof = [&](const Req &r) { return q_plus < 0 ? 0 : r.k + q_plus; };
         {
-            ProfScope ps("serve_mdot", st);
+            ProfScope ps("serve_mdot", st, B([&](const Sizes &z, const Req &r) { return (qof(r) + 1) * nv8(z); }));
             kb_mdot<<<L_(SH_VEC)>>>(A_(SH_VEC), w, q_plus, guard);
         }
         CKL();
         {
-            ProfScope ps("serve_reduce", st);
+            ProfScope ps("serve_reduce", st,
+                         B([&](const Sizes &, const Req &r) { return 8.0 * (qof(r) + 1) * r.L.nb_vec; }));
             if (q_plus < 0)
                 kb_reduce<<<L_(SH_ONE)>>>(A_(SH_ONE), guard);
             else
@@ -583,51 +607,97 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
         CKL();
         return ABILU_OK;
     };
+    // w += alpha sum_k coef_k base_k over q = k + q_plus vectors (+ ||w||^2 partials)
+    auto update = [&](int base, int q_plus, double alpha, int w, int norm, int guard) -> abilu_status {
+        {
+            ProfScope ps("serve_update", st,
+                         B([&](const Sizes &z, const Req &r) { return (r.k + q_plus + 2) * nv8(z); }));
+            kb_update<<<L_(SH_VEC)>>>(A_(SH_VEC), base, q_plus, alpha, w, norm, guard);
+        }
+        CKL();
+        if (norm) {
+            ProfScope ps("serve_reduce", st, B([&](const Sizes &, const Req &r) { return 8.0 * r.L.nb_vec; }));
+            kb_reduce<<<L_(SH_ONE)>>>(A_(SH_ONE), guard);
+            CKL();
+        }
+        return ABILU_OK;
+    };
     auto small = [&](int op) -> abilu_status {
-        ProfScope ps("serve_small", st);
+        ProfScope ps("serve_small", st, B([](const Sizes &, const Req &) { return 0.0; }));
         kb_small<<<ONE_()>>>(A_(SH_ONE), op, m);
+        CKL();
+        return ABILU_OK;
+    };
+    auto scale = [&](int w, int v, int hslot) -> abilu_status {
+        ProfScope ps("serve_scale", st, B([&](const Sizes &z, const Req &) { return 2 * nv8(z); }));
+        kb_scale<<<L_(SH_VEC)>>>(A_(SH_VEC), w, v, hslot);
+        CKL();
+        return ABILU_OK;
+    };
+    auto init = [&](bool copy, int sel) -> abilu_status {
+        ProfScope ps("serve_factor_init", st, B([&](const Sizes &z, const Req &) { return bytes_init(z, 8, sF, copy); }));
+        if (copy)
+            kb_factor_init<T, true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), sel);
+        else
+            kb_factor_init<T, false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), sel);
+        CKL();
+        return ABILU_OK;
+    };
+    auto fwd = [&](const char *name, bool yin_f64, bool emit, int yin, int yout) -> abilu_status {
+        ProfScope ps(name, st, B([&](const Sizes &z, const Req &) { return bytes_fwd(z, sF, yin_f64 ? 8 : sF, emit); }));
+        if (yin_f64) {
+            if (emit) kb_fwd<T, double, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yin, yout);
+            else kb_fwd<T, double, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yin, yout);
+        } else {
+            if (emit) kb_fwd<T, T, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yin, yout);
+            else kb_fwd<T, T, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yin, yout);
+        }
+        CKL();
+        return ABILU_OK;
+    };
+    auto spmv = [&](bool resid, int xin, int yout) -> abilu_status {
+        ProfScope ps(resid ? "serve_spmv_resid" : "serve_spmv", st,
+                     B([&](const Sizes &z, const Req &) { return bytes_spmv(z, resid); }));
+        if (resid)
+            kb_spmv<true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), xin, yout);
+        else
+            kb_spmv<false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), xin, yout);
         CKL();
         return ABILU_OK;
     };
     abilu_status e;
     if (G.st == Q_FACTOR) {
         if (fsw == 0) {
-            ProfScope ps("serve_factor_init", st);
-            kb_factor_init<T, true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), 0);
-            CKL();
+            if ((e = init(true, 0)) != ABILU_OK) return e;
         } else if (!sync) {
+            if ((e = init(false, 0)) != ABILU_OK) return e;
             {
-                ProfScope ps("serve_factor_init", st);
-                kb_factor_init<T, false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), 0);
-            }
-            CKL();
-            {
-                ProfScope ps("serve_factor_sweep_fromA", st);
+                ProfScope ps("serve_factor_sweep_fromA", st,
+                             B([&](const Sizes &z, const Req &) { return bytes_sweep(z, sF, false, true); }));
                 kb_factor_sweep<T, false, true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), 0);
             }
             CKL();
             for (int q = 1; q < fsw; ++q) {
-                ProfScope ps("serve_factor_sweep", st);
+                ProfScope ps("serve_factor_sweep", st,
+                             B([&](const Sizes &z, const Req &) { return bytes_sweep(z, sF, false, false); }));
                 kb_factor_sweep<T, false, false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), 0);
                 CKL();
             }
         } else {
             // sweep q writes X1/D1 when (fsw - q) is odd, LU/Dinv when even (the last is LU/Dinv)
             auto one = [&](int q) { return ((fsw - q) % 2) != 0; };
+            if ((e = init(false, one(0) ? 8 : 0)) != ABILU_OK) return e;
             {
-                ProfScope ps("serve_factor_init", st);
-                kb_factor_init<T, false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), one(0) ? 8 : 0);
-            }
-            CKL();
-            {
-                ProfScope ps("serve_factor_sweep_fromA", st);
+                ProfScope ps("serve_factor_sweep_fromA", st,
+                             B([&](const Sizes &z, const Req &) { return bytes_sweep(z, sF, true, true); }));
                 kb_factor_sweep<T, true, true>
                     <<<L_(SH_ROW64)>>>(A_(SH_ROW64), (one(0) ? 2 : 0) | (one(1) ? 4 : 0) | (one(1) ? 8 : 0));
             }
             CKL();
             for (int q = 2; q <= fsw; ++q) {
                 const int sel = (one(q - 1) ? 3 : 0) | (one(q) ? 12 : 0);
-                ProfScope ps("serve_factor_sweep", st);
+                ProfScope ps("serve_factor_sweep", st,
+                             B([&](const Sizes &z, const Req &) { return bytes_sweep(z, sF, false, false); }));
                 kb_factor_sweep<T, false, false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), sel);
                 CKL();
             }
@@ -636,41 +706,39 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
         if ((e = mdot(R_B, -1, 0)) != ABILU_OK) return e;
         if ((e = small(OP_BETA0)) != ABILU_OK) return e;
         {
-            ProfScope ps("serve_scale", st);
+            ProfScope ps("serve_zero", st, B([&](const Sizes &z, const Req &) { return nv8(z); }));
             kb_zero<<<L_(SH_VEC)>>>(A_(SH_VEC), R_X);
-            CKL();
-            kb_scale<<<L_(SH_VEC)>>>(A_(SH_VEC), R_B, R_V0, MI_BETA);
-            CKL();
         }
-        return ABILU_OK;
+        CKL();
+        return scale(R_B, R_V0, MI_BETA);
     }
     if (G.st == Q_ITER) {
         // z_k = M^{-1} v_k
         if (nsw == 0) {
-            ProfScope ps("serve_apply_copy", st);
+            ProfScope ps("serve_apply_copy", st, B([&](const Sizes &z, const Req &) { return 2 * nv8(z); }));
             kb_copy<<<L_(SH_VEC)>>>(A_(SH_VEC), R_VK, R_ZK);
             CKL();
         } else if (!sync) {
             {
-                ProfScope ps("serve_apply_fill", st);
+                ProfScope ps("serve_apply_fill", st, B([&](const Sizes &z, const Req &) { return 8 * z.N * sF; }));
                 kb_fill2<T><<<L_(SH_FILL)>>>(A_(SH_FILL));
             }
             CKL();
+            for (int q = 1; q <= nsw; ++q)
+                if ((e = fwd("serve_apply_fwd", false, false, R_YA, R_YA)) != ABILU_OK) return e;
             for (int q = 1; q <= nsw; ++q) {
-                ProfScope ps("serve_apply_fwd", st);
-                kb_fwd<T, T, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_YA, R_YA);
-                CKL();
-            }
-            for (int q = 1; q <= nsw; ++q) {
-                ProfScope ps(q == nsw ? "serve_apply_bwd_last" : "serve_apply_bwd", st);
-                if (q == nsw)
+                const bool last = q == nsw;
+                ProfScope ps(last ? "serve_apply_bwd_last" : "serve_apply_bwd", st,
+                             B([&](const Sizes &z, const Req &) { return bytes_bwd(z, sF, last ? 8 : sF, last); }));
+                if (last)
                     kb_bwd<T, T, double, true, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_YA, R_ZA, R_ZK);
                 else
                     kb_bwd<T, T, T, true, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_YA, R_ZA, R_ZA);
                 CKL();
             }
         } else if (nsw == 1) {
-            ProfScope ps("serve_apply_diag", st);
+            ProfScope ps("serve_apply_diag", st,
+                         B([&](const Sizes &z, const Req &) { return 32 * z.N + 16 * sF * z.N + 32 * z.N; }));
             kb_bwd<T, double, double, false, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_VK, R_ZA, R_ZK);
             CKL();
         } else {
@@ -678,21 +746,16 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
             for (int q = 2; q <= nsw; ++q) {
                 ycur = (q % 2 == 0) ? R_YA : R_YB;
                 const bool last = q == nsw;
-                ProfScope ps(last ? "serve_apply_fwd_emitz" : "serve_apply_fwd", st);
-                if (q == 2) {
-                    if (last) kb_fwd<T, double, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_VK, ycur);
-                    else kb_fwd<T, double, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_VK, ycur);
-                } else {
-                    if (last) kb_fwd<T, T, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yprev, ycur);
-                    else kb_fwd<T, T, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yprev, ycur);
-                }
-                CKL();
+                if ((e = fwd(last ? "serve_apply_fwd_emitz" : "serve_apply_fwd", q == 2, last, yprev, ycur)) != ABILU_OK)
+                    return e;
                 yprev = ycur;
             }
             int zprev = R_ZA;
             for (int q = 2; q <= nsw; ++q) {
-                ProfScope ps(q == nsw ? "serve_apply_bwd_last" : "serve_apply_bwd", st);
-                if (q == nsw) {
+                const bool last = q == nsw;
+                ProfScope ps(last ? "serve_apply_bwd_last" : "serve_apply_bwd", st,
+                             B([&](const Sizes &z, const Req &) { return bytes_bwd(z, sF, last ? 8 : sF, false); }));
+                if (last) {
                     kb_bwd<T, T, double, true, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), ycur, zprev, R_ZK);
                 } else {
                     const int zcur = (zprev == R_ZA) ? R_ZB : R_ZA;
@@ -702,59 +765,28 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
                 CKL();
             }
         }
-        {
-            ProfScope ps("serve_spmv", st);
-            kb_spmv<false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), R_ZK, R_VK1);
-        }
-        CKL();
+        if ((e = spmv(false, R_ZK, R_VK1)) != ABILU_OK) return e;
         // Gram-Schmidt pass 1, then pass 2 only where the device set the guard
         if ((e = mdot(R_VK1, 1, 0)) != ABILU_OK) return e;
         if ((e = small(OP_GS1)) != ABILU_OK) return e;
-        {
-            ProfScope ps("serve_update", st);
-            kb_update<<<L_(SH_VEC)>>>(A_(SH_VEC), R_VBASE, 1, -1.0, R_VK1, 1, 0);
-            CKL();
-            kb_reduce<<<L_(SH_ONE)>>>(A_(SH_ONE), 0);
-            CKL();
-        }
+        if ((e = update(R_VBASE, 1, -1.0, R_VK1, 1, 0)) != ABILU_OK) return e;
         if ((e = small(OP_GS1_DONE)) != ABILU_OK) return e;
+        // launches pass2 .. pass2 + 4: mdot, reduce, gs2, update, reduce (bytes corrected after
+        // the tick for members whose guard stayed clear)
+        G.pass2 = prof_mark();
         if ((e = mdot(R_VK1, 1, 1)) != ABILU_OK) return e;
         if ((e = small(OP_GS2)) != ABILU_OK) return e;
-        {
-            ProfScope ps("serve_update", st);
-            kb_update<<<L_(SH_VEC)>>>(A_(SH_VEC), R_VBASE, 1, -1.0, R_VK1, 1, 1);
-            CKL();
-            kb_reduce<<<L_(SH_ONE)>>>(A_(SH_ONE), 1);
-            CKL();
-        }
+        if ((e = update(R_VBASE, 1, -1.0, R_VK1, 1, 1)) != ABILU_OK) return e;
         if ((e = small(OP_GIVENS)) != ABILU_OK) return e;
-        {
-            ProfScope ps("serve_scale", st);
-            kb_scale<<<L_(SH_VEC)>>>(A_(SH_VEC), R_VK1, R_VK1, MI_HN);
-        }
-        CKL();
-        return ABILU_OK;
+        return scale(R_VK1, R_VK1, MI_HN);
     }
     // end of a restart cycle over k Arnoldi steps: x += Z y, true residual, next V_0
     if ((e = small(OP_SOLVE)) != ABILU_OK) return e;
-    {
-        ProfScope ps("serve_update", st);
-        kb_update<<<L_(SH_VEC)>>>(A_(SH_VEC), R_ZBASE, 0, 1.0, R_X, 0, 0);
-    }
-    CKL();
-    {
-        ProfScope ps("serve_spmv_resid", st);
-        kb_spmv<true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), R_X, R_V0);
-    }
-    CKL();
+    if ((e = update(R_ZBASE, 0, 1.0, R_X, 0, 0)) != ABILU_OK) return e;
+    if ((e = spmv(true, R_X, R_V0)) != ABILU_OK) return e;
     if ((e = mdot(R_V0, -1, 0)) != ABILU_OK) return e;
     if ((e = small(OP_BETA_CE)) != ABILU_OK) return e;
-    {
-        ProfScope ps("serve_scale", st);
-        kb_scale<<<L_(SH_VEC)>>>(A_(SH_VEC), R_V0, R_V0, MI_BETA);
-    }
-    CKL();
-    return ABILU_OK;
+    return scale(R_V0, R_V0, MI_BETA);
 #undef L_
 #undef A_
 #undef ONE_
@@ -874,6 +906,29 @@ abilu_status step_impl(abilu_server *s, hipStream_t st) {
     // admissions run on the setup stream while the device works through the tick
     if ((e = admit_queued(s, budget)) != ABILU_OK) return e;
     if (!hip_ok(hipStreamSynchronize(st), "serve tick sync")) return ABILU_EDEVICE;
+    ++s->stat_ticks;
+    // the second Gram-Schmidt pass exited at once where the guard stayed clear: remove its bytes
+    {
+        Group &G = groups[1];
+        double dm = 0, dr = 0, du = 0, dr2 = 0;
+        for (int64_t id : G.ids) {
+            const Req &r = s->reqs[id];
+            const double *stv = (const double *)(s->h_hdr + (size_t)r.slot * HDR + 64);
+            if (stv[ST_GUARD] != 0.0) continue;
+            const double nv8 = 32.0 * r.n, q = r.k + 1;
+            dm += (q + 1) * nv8;
+            dr += 8.0 * (q + 1) * r.L.nb_vec;
+            du += (q + 2) * nv8;
+            dr2 += 8.0 * r.L.nb_vec;
+        }
+        s->stat_bytes -= dm + dr + du + dr2;
+        if (!G.ids.empty()) {
+            prof_add_bytes(G.pass2, -dm);
+            prof_add_bytes(G.pass2 + 1, -dr);
+            prof_add_bytes(G.pass2 + 3, -du);
+            prof_add_bytes(G.pass2 + 4, -dr2);
+        }
+    }
     // advance, retire finished requests (copy x out first)
     bool copied = false;
     std::vector<int64_t> done;
@@ -898,6 +953,7 @@ abilu_status step_impl(abilu_server *s, hipStream_t st) {
         Req &r = s->reqs[id];
         r.res.t_done = t;
         release(s, r);
+        ++s->stat_retired;
     }
     return ABILU_OK;
 }
@@ -1075,5 +1131,15 @@ extern "C" abilu_status abilu_serve_run(abilu_server *srv, const abilu_request *
         }
     }
     if (elapsed_s) *elapsed_s = now_s() - srv->t0 - start;
+    return ABILU_OK;
+}
+
+extern "C" abilu_status abilu_serve_stats(const abilu_server *srv, abilu_serve_stats_t *out) {
+    if (!srv || !out) return ABILU_EINVAL;
+    out->ticks = srv->stat_ticks;
+    out->launches = srv->stat_launches;
+    out->admitted = srv->stat_admitted;
+    out->retired = srv->stat_retired;
+    out->bytes = srv->stat_bytes;
     return ABILU_OK;
 }

@@ -267,3 +267,26 @@ def test_edge_cases():
     out, _ = srv.run([MIX[0], dict(kind="tri", nx=0, ny=3, cfl=1.0, seed=0)])
     srv.destroy()
     assert out[1]["status"] == lib.ABILU_EINVAL and out[0]["iters"] == res[0]["iters"]
+
+
+def test_stats_bytes_match_single_system_profile():
+    """The server's algorithmic byte count equals the single-system path's per-launch byte model
+    (the library profile of abilu_factor + fgmres_solve) over the same requests (SYNC: the same
+    iterations and Gram-Schmidt decisions), plus the one normalisation of V_0 the server does
+    ahead at the last cycle end of each request (read and write of 4N doubles)."""
+    lib = L()
+    reqs = MIX[:5]
+    cfg = cfg_of("f64", "sync", 2, restart=10, maxit=60)
+    srv = lib.Server(cfg, pool_for(cfg, reqs))
+    res, _ = srv.run(reqs)
+    st = srv.stats()
+    srv.destroy()
+    assert st["admitted"] == len(reqs) and st["retired"] == len(reqs) and st["ticks"] > 0
+    lib.abilu_profile_enable(True, 100000)
+    for req in reqs:
+        single_path(req, "f64", "sync", 2)
+    rep = lib.abilu_profile_report()
+    lib.abilu_profile_enable(False)
+    single = sum(v[2] for k, v in rep.items() if not k.startswith(("_", "gen_")))   # generation not counted
+    ahead = sum(64.0 * r["n"] for r in res if r["iters"] > 0)
+    assert abs(st["bytes"] - (single + ahead)) <= 1e-9 * single, (st["bytes"], single, ahead)
