@@ -39,12 +39,6 @@ __global__ __launch_bounds__(WG) void k_bwd(int n, const int32_t *__restrict__ u
     bwd_body<T, YI, ZO, OFFDIAG, DUAL>(blockIdx.x, n, urow, ucol, Ub, Dinv, y, zin, zout, zout2);
 }
 
-template <typename T>
-__global__ void k_fill(int64_t len, T *v, T val) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < len) v[t] = val;
-}
-
 // y = A x  (RESID: y = b - A x), double precision, CSR; one quad per block row, four blocks
 // loaded per step (clamped: rows always hold at least their diagonal block)
 template <bool RESID>
@@ -67,7 +61,6 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
                      abilu_mode mode, char *work, const Workspace &W, hipStream_t s) {
     const int n = p->n;
     const int grid = div_up(n, ROWS_PER_WG2);
-    const int64_t nv = 4 * (int64_t)n;
     const T *Lb = LU;                                              // strictly lower part
     const T *Ub = LU + ((int64_t)p->nnzb_lower + n) * BB;          // strictly upper part
     const int32_t *lrow = p->lrow, *lcol = p->lcol, *urow = p->urow, *ucol = p->ucol;
@@ -83,71 +76,56 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
 #define LAUNCHED() \
     if (launch_status() != ABILU_OK) return ABILU_EDEVICE
 
-    if (mode == ABILU_SYNC) {
-        if (nsw == 1) {
-            ProfScope ps(NAME("apply_diag"), s, 32 * zz.N + 16 * sF * zz.N + 32 * zz.N);
-            k_bwd<T, double, double, false, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, r, (const T *)nullptr, z,
-                                                                       (T *)nullptr);
-            LAUNCHED();
-            return ABILU_OK;
-        }
-        // forward sweeps 2..nsw (sweep 1 is y = r)
-        const T *yprev = nullptr;
-        T *ycur = nullptr;
-        for (int q = 2; q <= nsw; ++q) {
-            ycur = (q % 2 == 0) ? ya : yb;
-            const bool last = (q == nsw);
-            ProfScope ps(NAME(last ? "apply_fwd_emitz" : "apply_fwd"), s, bytes_fwd(zz, sF, q == 2 ? 8 : sF, last));
-            if (q == 2) {
-                if (last)
-                    k_fwd<T, double, true><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, r, ycur, Dinv, za);
-                else
-                    k_fwd<T, double, false><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, r, ycur, Dinv, (T *)nullptr);
-            } else {
-                if (last)
-                    k_fwd<T, T, true><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, yprev, ycur, Dinv, za);
-                else
-                    k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, yprev, ycur, Dinv, (T *)nullptr);
-            }
-            LAUNCHED();
-            yprev = ycur;
-        }
-        const T *yfin = ycur;
-        // backward sweeps 2..nsw (sweep 1 produced za)
-        const T *zprev = za;
-        for (int q = 2; q <= nsw; ++q) {
-            ProfScope ps(NAME(q == nsw ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, false));
-            if (q == nsw) {
-                k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, (T *)nullptr);
-            } else {
-                T *zcur = (zprev == za) ? zb : za;
-                k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, zcur, (T *)nullptr);
-                zprev = zcur;
-            }
-            LAUNCHED();
-        }
+    // From the zero initial guess, sweep 1 forward is y = r and sweep 1 backward is z = Dinv y:
+    // they are not launched (the first forward sweep reads r, the last forward sweep also emits
+    // z = Dinv y). In ASYNC mode this is the admissible schedule in which no read of sweep 1 sees
+    // a value written in the same sweep; sweeps 2..nsw then update y and z in place. SYNC sweeps
+    // read the previous sweep's vector (ping-pong ya/yb, za/zb).
+    const bool sync = mode == ABILU_SYNC;
+    if (nsw == 1) {
+        ProfScope ps(NAME("apply_diag"), s, 32 * zz.N + 16 * sF * zz.N + 32 * zz.N);
+        k_bwd<T, double, double, false, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, r, (const T *)nullptr, z,
+                                                                   (T *)nullptr);
+        LAUNCHED();
         return ABILU_OK;
     }
-
-    // ASYNC: zero initial guesses, in-place sweeps
-    {
-        ProfScope ps("apply_fill", s, 2 * 4 * zz.N * sF);
-        k_fill<T><<<div_up(nv, 256), 256, 0, s>>>(nv, ya, T(0));
+    const T *yprev = nullptr;   // nullptr: sweep 1, i.e. r itself
+    T *ycur = nullptr;
+    for (int q = 2; q <= nsw; ++q) {
+        ycur = (!sync || q % 2 == 0) ? ya : yb;
+        const bool last = (q == nsw);
+        ProfScope ps(NAME(last ? "apply_fwd_emitz" : "apply_fwd"), s, bytes_fwd(zz, sF, q == 2 ? 8 : sF, last));
+        if (q == 2) {
+            if (last)
+                k_fwd<T, double, true><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, r, ycur, Dinv, za);
+            else
+                k_fwd<T, double, false><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, r, ycur, Dinv, (T *)nullptr);
+        } else {
+            if (last)
+                k_fwd<T, T, true><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, yprev, ycur, Dinv, za);
+            else
+                k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, yprev, ycur, Dinv, (T *)nullptr);
+        }
         LAUNCHED();
-        k_fill<T><<<div_up(nv, 256), 256, 0, s>>>(nv, za, T(0));
-        LAUNCHED();
+        yprev = ycur;
     }
-    for (int q = 1; q <= nsw; ++q) {
-        ProfScope ps(NAME("apply_fwd"), s, bytes_fwd(zz, sF, sF, false));
-        k_fwd<T, T, false><<<grid, WG, 0, s>>>(n, lrow, lcol, Lb, r, ya, ya, Dinv, (T *)nullptr);
-        LAUNCHED();
-    }
-    for (int q = 1; q <= nsw; ++q) {
-        ProfScope ps(NAME(q == nsw ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, q == nsw ? 8 : sF, q == nsw));
-        if (q == nsw)
-            k_bwd<T, T, double, true, true><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, z, za);
-        else
-            k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, za, (T *)nullptr);
+    const T *yfin = ycur;
+    // backward sweeps 2..nsw (sweep 1 produced za)
+    T *zprev = za;
+    for (int q = 2; q <= nsw; ++q) {
+        const bool last = (q == nsw);
+        ProfScope ps(NAME(last ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, last ? 8 : sF, last && !sync));
+        if (last) {
+            // ASYNC: the in-place copy keeps rows updated later in this sweep reading fresh values
+            if (sync)
+                k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, (T *)nullptr);
+            else
+                k_bwd<T, T, double, true, true><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, zprev);
+        } else {
+            T *zcur = sync ? ((zprev == za) ? zb : za) : za;
+            k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, zcur, (T *)nullptr);
+            zprev = zcur;
+        }
         LAUNCHED();
     }
     return ABILU_OK;

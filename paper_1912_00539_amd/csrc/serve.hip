@@ -117,16 +117,6 @@ __global__ __launch_bounds__(WG) void kb_factor_sweep(const Slot *slots, const M
                                  fbuf_d<T>(S, sel & 2), fbuf_x<T>(S, sel & 4), fbuf_d<T>(S, sel & 8), S.flags);
 }
 
-template <typename T>
-__global__ void kb_fill2(const Slot *slots, const Member *mem, int nmem) {
-    MEMBER();
-    const int64_t t = (int64_t)blk * 256 + threadIdx.x;
-    if (t < S.nv) {
-        ((T *)S.ya)[t] = T(0);
-        ((T *)S.za)[t] = T(0);
-    }
-}
-
 template <typename T, typename YI, bool EMIT_Z>
 __global__ __launch_bounds__(WG) void kb_fwd(const Slot *slots, const Member *mem, int nmem, int yin, int yout) {
     MEMBER();
@@ -534,7 +524,7 @@ abilu_status admit_queued(abilu_server *s, int64_t cell_budget) {
 }
 
 // ---- per-tick member tables
-enum Shape { SH_ROW64 = 0, SH_ROW128, SH_VEC, SH_FILL, SH_COLSQ, SH_ONE, SH_COUNT };
+enum Shape { SH_ROW64 = 0, SH_ROW128, SH_VEC, SH_COLSQ, SH_ONE, SH_COUNT };
 
 struct Table {
     const Member *d = nullptr;
@@ -546,7 +536,6 @@ int tiles_of(const Req &r, int shape, State g) {
         case SH_ROW64: return div_up(r.n, ROWS_PER_WG);
         case SH_ROW128: return div_up(r.n, ROWS_PER_WG2);
         case SH_VEC: return r.L.nb_vec;
-        case SH_FILL: return div_up(4 * (int64_t)r.n, 256);
         case SH_COLSQ: return g == Q_ITER ? r.k + 2 : 1;
         default: return 1;
     }
@@ -718,33 +707,17 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
             ProfScope ps("serve_apply_copy", st, B([&](const Sizes &z, const Req &) { return 2 * nv8(z); }));
             kb_copy<<<L_(SH_VEC)>>>(A_(SH_VEC), R_VK, R_ZK);
             CKL();
-        } else if (!sync) {
-            {
-                ProfScope ps("serve_apply_fill", st, B([&](const Sizes &z, const Req &) { return 8 * z.N * sF; }));
-                kb_fill2<T><<<L_(SH_FILL)>>>(A_(SH_FILL));
-            }
-            CKL();
-            for (int q = 1; q <= nsw; ++q)
-                if ((e = fwd("serve_apply_fwd", false, false, R_YA, R_YA)) != ABILU_OK) return e;
-            for (int q = 1; q <= nsw; ++q) {
-                const bool last = q == nsw;
-                ProfScope ps(last ? "serve_apply_bwd_last" : "serve_apply_bwd", st,
-                             B([&](const Sizes &z, const Req &) { return bytes_bwd(z, sF, last ? 8 : sF, last); }));
-                if (last)
-                    kb_bwd<T, T, double, true, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_YA, R_ZA, R_ZK);
-                else
-                    kb_bwd<T, T, T, true, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_YA, R_ZA, R_ZA);
-                CKL();
-            }
         } else if (nsw == 1) {
             ProfScope ps("serve_apply_diag", st,
                          B([&](const Sizes &z, const Req &) { return 32 * z.N + 16 * sF * z.N + 32 * z.N; }));
             kb_bwd<T, double, double, false, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_VK, R_ZA, R_ZK);
             CKL();
         } else {
+            // sweep 1 forward is y = v_k and sweep 1 backward z = Dinv y (emitted by the last forward
+            // sweep); ASYNC sweeps 2.. update in place, SYNC sweeps ping-pong
             int yprev = R_VK, ycur = R_YA;
             for (int q = 2; q <= nsw; ++q) {
-                ycur = (q % 2 == 0) ? R_YA : R_YB;
+                ycur = (!sync || q % 2 == 0) ? R_YA : R_YB;
                 const bool last = q == nsw;
                 if ((e = fwd(last ? "serve_apply_fwd_emitz" : "serve_apply_fwd", q == 2, last, yprev, ycur)) != ABILU_OK)
                     return e;
@@ -753,12 +726,14 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
             int zprev = R_ZA;
             for (int q = 2; q <= nsw; ++q) {
                 const bool last = q == nsw;
+                const bool dual = last && !sync;
                 ProfScope ps(last ? "serve_apply_bwd_last" : "serve_apply_bwd", st,
-                             B([&](const Sizes &z, const Req &) { return bytes_bwd(z, sF, last ? 8 : sF, false); }));
+                             B([&](const Sizes &z, const Req &) { return bytes_bwd(z, sF, last ? 8 : sF, dual); }));
                 if (last) {
-                    kb_bwd<T, T, double, true, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), ycur, zprev, R_ZK);
+                    if (dual) kb_bwd<T, T, double, true, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), ycur, zprev, R_ZK);
+                    else kb_bwd<T, T, double, true, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), ycur, zprev, R_ZK);
                 } else {
-                    const int zcur = (zprev == R_ZA) ? R_ZB : R_ZA;
+                    const int zcur = sync ? ((zprev == R_ZA) ? R_ZB : R_ZA) : R_ZA;
                     kb_bwd<T, T, T, true, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), ycur, zprev, zcur);
                     zprev = zcur;
                 }
