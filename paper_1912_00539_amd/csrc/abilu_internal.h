@@ -43,7 +43,7 @@ constexpr int ROWS_PER_WG = WG / BS;    // one quad of 4 lanes per block row
 constexpr int VEC_E = 8;
 constexpr int VEC_TILE = WG * VEC_E;    // 2048 doubles per workgroup
 
-inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+__host__ __device__ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ------------------------------------------------------------------ workspace layout
 struct Workspace {

@@ -4,61 +4,20 @@
 #include <climits>
 #include <cstring>
 
-#include "abilu_internal.h"
+#include "setup_kernels.h"
 
 namespace {
 
-// position of column j in row k, or -1 (binary search over the sorted row)
-__device__ __forceinline__ int find_col(const int32_t *rowptr, const int32_t *colidx, int k, int j) {
-    int lo = rowptr[k], hi = rowptr[k + 1] - 1;
-    while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
-        int c = colidx[mid];
-        if (c == j) return mid;
-        if (c < j) lo = mid + 1; else hi = mid - 1;
-    }
-    return -1;
+using namespace abilu_setup;
+
+__global__ void k_pat_rows(int n, int64_t Z, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                           int32_t *__restrict__ diag_pos, unsigned *__restrict__ err) {
+    pat_rows_body(blockIdx.x, n, Z, rowptr, colidx, diag_pos, err);
 }
 
-__global__ void k_pat_rows(int n, int64_t Z, const int32_t *__restrict__ rowptr,
-                           const int32_t *__restrict__ colidx, int32_t *__restrict__ diag_pos,
-                           unsigned *__restrict__ err) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b0 = rowptr[i], b1 = rowptr[i + 1];
-    bool bad = (b0 < 0) || (b1 < b0) || ((int64_t)b1 > Z);
-    int d = -1;
-    if (!bad) {
-        int prev = -1;
-        for (int e = b0; e < b1; ++e) {
-            int j = colidx[e];
-            if (j < 0 || j >= n || j <= prev) { bad = true; break; }
-            prev = j;
-            if (j == i) d = e;
-        }
-    }
-    if (d < 0) bad = true;
-    diag_pos[i] = d;
-    if (bad) atomicOr(err, 1u);
-}
-
-// one thread per block row; counts |K(i,j)| for every block of the row
 __global__ void k_pat_count(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
                             int64_t *__restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b0 = rowptr[i], b1 = rowptr[i + 1];
-    for (int e = b0; e < b1; ++e) {
-        int j = colidx[e];
-        int lim = i < j ? i : j;
-        int c = 0;
-        for (int f = b0; f < b1; ++f) {
-            int k = colidx[f];
-            if (k >= lim) break;
-            c += (find_col(rowptr, colidx, k, j) >= 0);
-        }
-        cnt[e] = c;
-    }
+    pat_count_body(blockIdx.x, n, rowptr, colidx, cnt);
 }
 
 __global__ void k_pat_fill(int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
@@ -66,48 +25,19 @@ __global__ void k_pat_fill(int n, int ZL, const int32_t *__restrict__ rowptr, co
                            const int32_t *__restrict__ urow, const int64_t *__restrict__ ptr,
                            int32_t *__restrict__ pik, int32_t *__restrict__ pkj, int32_t *__restrict__ sik,
                            int32_t *__restrict__ skj) {
-    using abilu_dev::split_pos;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b0 = rowptr[i], b1 = rowptr[i + 1];
-    for (int e = b0; e < b1; ++e) {
-        int j = colidx[e];
-        int lim = i < j ? i : j;
-        int64_t o = ptr[e];
-        for (int f = b0; f < b1; ++f) {
-            int k = colidx[f];
-            if (k >= lim) break;
-            int g = find_col(rowptr, colidx, k, j);
-            if (g >= 0) {
-                pik[o] = f;
-                pkj[o] = g;
-                sik[o] = split_pos(f, i, b0, diag_pos[i], lrow[i], urow[i], ZL, n);
-                skj[o] = split_pos(g, k, rowptr[k], diag_pos[k], lrow[k], urow[k], ZL, n);
-                ++o;
-            }
-        }
-    }
+    pat_fill_body(blockIdx.x, n, ZL, rowptr, colidx, diag_pos, lrow, urow, ptr, pik, pkj, sik, skj);
 }
 
-// per-row counts of strictly lower / upper blocks
 __global__ void k_pat_tri_counts(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ diag_pos,
                                  int64_t *__restrict__ nl, int64_t *__restrict__ nu) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    nl[i] = diag_pos[i] - rowptr[i];
-    nu[i] = rowptr[i + 1] - diag_pos[i] - 1;
+    pat_tri_counts_body(blockIdx.x, n, rowptr, diag_pos, nl, nu);
 }
 
-// columns of the lower and upper parts in factor-layout order
 __global__ void k_pat_tri_cols(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
                                const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow,
                                const int32_t *__restrict__ urow, int32_t *__restrict__ lcol,
                                int32_t *__restrict__ ucol) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int b0 = rowptr[i], d = diag_pos[i], b1 = rowptr[i + 1];
-    for (int e = b0; e < d; ++e) lcol[lrow[i] + (e - b0)] = colidx[e];
-    for (int e = d + 1; e < b1; ++e) ucol[urow[i] + (e - d - 1)] = colidx[e];
+    pat_tri_cols_body(blockIdx.x, n, rowptr, colidx, diag_pos, lrow, urow, lcol, ucol);
 }
 
 void free_pattern(abilu_pattern *p) {

@@ -26,6 +26,7 @@
 #include "abilu_gen.h"
 #include "abilu_serve.h"
 #include "kernels.h"
+#include "setup_kernels.h"
 
 using namespace abilu;
 using namespace abilu_dev;
@@ -208,6 +209,125 @@ __global__ void kb_small(const Slot *slots, const Member *mem, int nmem, int op,
     }
 }
 
+// ------------------------------------------------------------------ batched admission kernels
+// Generation and pattern analysis of many requests in one launch per step, over per-member
+// descriptors and member tables (as the solve kernels), with the bodies of the single-request
+// kernels.
+struct SetupDesc {
+    int32_t n, kind, nx, ny;
+    int64_t Z;
+    double cfl;
+    uint64_t seed;
+    int32_t *rowptr, *colidx, *diag_pos, *lrow, *urow, *lcol, *ucol, *pair_ptr, *pik, *pkj, *sik, *skj;
+    double *A, *b;
+    int64_t *cnt, *tmp, *ptr64, *tot;   // scratch: 3 x (Z + n + 2) + tiles + 1 int64
+    int32_t slot, pad;
+};
+
+// scans: row lengths -> rowptr; lower / upper counts -> lrow / urow (totals ZL, ZU); pair counts
+// -> pair_ptr (total npairs); adm[4m + 1 + which - 1] receives the totals
+enum { SC_ROWPTR = 0, SC_LROW, SC_UROW, SC_PAIR };
+
+// M.slot holds the member's index in the admitted batch (descriptors, staged slots and
+// admission words are indexed by it; the table may skip members that failed)
+#define SMEMBER()                                         \
+    const Member M = mem[find_member(mem, nmem, blockIdx.x)]; \
+    const int m_ = M.slot;                                \
+    const SetupDesc &D = sd[m_];                          \
+    const int blk = blockIdx.x - M.tile0
+
+__device__ __forceinline__ int64_t scan_len(const SetupDesc &D, int which) { return which == SC_PAIR ? D.Z : D.n; }
+__device__ __forceinline__ const int64_t *scan_in(const SetupDesc &D, int which) {
+    return which == SC_UROW ? D.cnt + (D.n + 1) : D.cnt;
+}
+
+__global__ void kbs_gen_rowlen(const SetupDesc *sd, const Member *mem, int nmem) {
+    SMEMBER();
+    if (D.kind == ABILU_GEN_TRI) abilu_setup::gen_rowlen_body<ABILU_GEN_TRI>(blk, D.nx, D.ny, D.seed, D.n, D.cnt);
+    else abilu_setup::gen_rowlen_body<ABILU_GEN_ANISO>(blk, D.nx, D.ny, D.seed, D.n, D.cnt);
+}
+
+__global__ __launch_bounds__(WG) void kbs_gen_fill(const SetupDesc *sd, const Member *mem, int nmem) {
+    SMEMBER();
+    if (D.kind == ABILU_GEN_TRI)
+        abilu_setup::gen_fill_body<ABILU_GEN_TRI>(blk, D.nx, D.ny, D.cfl, D.seed, D.n, D.rowptr, D.colidx, D.A, D.b);
+    else
+        abilu_setup::gen_fill_body<ABILU_GEN_ANISO>(blk, D.nx, D.ny, D.cfl, D.seed, D.n, D.rowptr, D.colidx, D.A, D.b);
+}
+
+__global__ __launch_bounds__(abilu_setup::SCAN_T) void kbs_scan_tiles(const SetupDesc *sd, const Member *mem, int nmem,
+                                                                     int which) {
+    SMEMBER();
+    abilu_setup::scan_tiles_body(blk, scan_len(D, which), scan_in(D, which), D.tmp, D.tot);
+}
+
+// one workgroup per member
+__global__ __launch_bounds__(abilu_setup::SCAN_T) void kbs_scan_totals(const SetupDesc *sd, const Member *mem, int nmem,
+                                                                      int which) {
+    SMEMBER();
+    (void)blk;
+    const int nt = div_up(scan_len(D, which) > 0 ? scan_len(D, which) : 1, abilu_setup::SCAN_TILE);
+    abilu_setup::scan_totals_body(nt, D.tot, D.tot + nt);
+}
+
+__global__ void kbs_scan_finish(const SetupDesc *sd, const Member *mem, int nmem, int which, int64_t *adm) {
+    SMEMBER();
+    const int64_t len = scan_len(D, which);
+    const int nt = div_up(len > 0 ? len : 1, abilu_setup::SCAN_TILE);
+    int32_t *out32 = which == SC_ROWPTR ? D.rowptr : (which == SC_LROW ? D.lrow : (which == SC_UROW ? D.urow : D.pair_ptr));
+    abilu_setup::scan_finish_body(blk, len, D.tmp, D.tot, D.tot + nt, which == SC_PAIR ? D.ptr64 : nullptr, out32);
+    if (which != SC_ROWPTR && (int64_t)blk * blockDim.x + threadIdx.x == len) adm[4 * m_ + which] = D.tot[nt];
+}
+
+__global__ void kbs_pat_rows(const SetupDesc *sd, const Member *mem, int nmem, int64_t *adm) {
+    SMEMBER();
+    abilu_setup::pat_rows_body(blk, D.n, D.Z, D.rowptr, D.colidx, D.diag_pos, (unsigned *)(adm + 4 * m_));
+}
+
+__global__ void kbs_pat_tri_counts(const SetupDesc *sd, const Member *mem, int nmem) {
+    SMEMBER();
+    abilu_setup::pat_tri_counts_body(blk, D.n, D.rowptr, D.diag_pos, D.cnt, D.cnt + (D.n + 1));
+}
+
+__global__ void kbs_pat_count(const SetupDesc *sd, const Member *mem, int nmem) {
+    SMEMBER();
+    abilu_setup::pat_count_body(blk, D.n, D.rowptr, D.colidx, D.cnt);
+}
+
+__global__ void kbs_pat_tri_cols(const SetupDesc *sd, const Member *mem, int nmem, const int64_t *adm) {
+    SMEMBER();
+    abilu_setup::pat_tri_cols_body(blk, D.n, D.rowptr, D.colidx, D.diag_pos, D.lrow, D.urow, D.lcol, D.ucol);
+    if (blk == 0 && threadIdx.x == 0) {   // the padding entry after each part
+        D.lcol[adm[4 * m_ + SC_LROW]] = 0;
+        D.ucol[adm[4 * m_ + SC_UROW]] = 0;
+    }
+}
+
+__global__ void kbs_pat_fill(const SetupDesc *sd, const Member *mem, int nmem, const int64_t *adm) {
+    SMEMBER();
+    abilu_setup::pat_fill_body(blk, D.n, (int)adm[4 * m_ + SC_LROW], D.rowptr, D.colidx, D.diag_pos, D.lrow, D.urow,
+                               D.ptr64, D.pik, D.pkj, D.sik, D.skj);
+}
+
+// Publish member m: its slot descriptor (with ZL from the analysis), a cleared status header and
+// cleared scalars. One workgroup per member.
+__global__ void kbs_publish(const SetupDesc *sd, const Member *mem, int nmem, const Slot *staged, Slot *slots,
+                            char *hdr, const int64_t *adm) {
+    SMEMBER();
+    (void)blk;
+    const int slot = D.slot;
+    // copy the staged descriptor word by word (word 0, holding n and ZL, by thread 0, which then
+    // sets ZL)
+    static_assert(sizeof(Slot) % 8 == 0, "slot descriptor is copied in 8-byte words");
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(staged + m_);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(slots + slot);
+    for (int w = threadIdx.x; w < (int)(sizeof(Slot) / 8); w += blockDim.x) dst[w] = src[w];
+    if (threadIdx.x == 0) slots[slot].ZL = (int32_t)adm[4 * m_ + SC_LROW];
+    const Slot &v = staged[m_];
+    if (threadIdx.x < HDR / 8) ((double *)(hdr + (size_t)slot * HDR))[threadIdx.x] = 0.0;
+    if (threadIdx.x < 16) v.misc[threadIdx.x] = 0.0;
+}
+
 // ------------------------------------------------------------------ host side
 
 double now_s() {
@@ -355,7 +475,12 @@ struct abilu_server {
     Member *d_tab = nullptr, *h_tab = nullptr;     // per-tick member tables (pinned staging)
     int tab_cap = 0;
     char *d_hdr = nullptr, *h_hdr = nullptr;       // per-slot status headers
-    int64_t *h_small = nullptr;                    // pinned, pattern analysis readbacks
+    // batched admission: per-member setup descriptors, staged slot descriptors, member tables
+    // and the error/size words read back, device and pinned host copies
+    SetupDesc *d_sdesc = nullptr, *h_sdesc = nullptr;
+    Slot *d_sslot = nullptr;
+    Member *d_stab = nullptr, *h_stab = nullptr;
+    int64_t *d_adm = nullptr, *h_adm = nullptr;    // per member: error word, ZL, ZU, npairs
     std::vector<hipEvent_t> ev;                    // per slot: setup finished
     std::vector<Req> reqs;
     std::deque<int64_t> queue;                     // released, not yet admitted (FIFO)
@@ -367,65 +492,136 @@ struct abilu_server {
 
 namespace {
 
-// Admission of a batch of requests on the setup stream, in three passes with one stream sync
-// between them (not one per request): device generation of each system and validation of its
-// pattern; update-set counts; then the fill, the status header and the slot descriptor. A
-// request whose pattern is invalid or exceeds its reserved capacity fails alone.
+// Admission of a batch of requests on the setup stream: every step of generation and pattern
+// analysis is one launch for the whole batch, with two stream syncs per batch (error words, then
+// the part sizes, are read back). A request whose pattern is invalid or exceeds its reserved
+// capacity fails alone.
 char *block_ptr(abilu_server *s, const Req &r, size_t o) { return o == NONE ? nullptr : s->pool + r.off + o; }
 
-abilu_status admit_begin(abilu_server *s, Req &r) {
-    const ReqLayout &L = r.L;
-    int32_t *rowptr = (int32_t *)block_ptr(s, r, L.rowptr), *colidx = (int32_t *)block_ptr(s, r, L.colidx);
-    if (abilu_gen_build(&r.spec, rowptr, colidx, (double *)block_ptr(s, r, L.A), (double *)block_ptr(s, r, L.b),
-                        block_ptr(s, r, L.scratch), s->setup) != ABILU_OK)
-        return ABILU_EDEVICE;
-    return pattern_validate_async(r.n, r.Z, rowptr, colidx, (int32_t *)block_ptr(s, r, L.diag_pos),
-                                  block_ptr(s, r, L.scratch), (unsigned *)(s->h_small + 8 * r.slot), s->setup);
+void release(abilu_server *s, Req &r) {
+    if (r.slot >= 0) {
+        s->slot_req[r.slot] = -1;
+        r.slot = -1;
+    }
+    s->alloc.release(r.off, r.L.total);
 }
 
-abilu_status admit_count(abilu_server *s, Req &r) {
-    const ReqLayout &L = r.L;
-    return pattern_count_async(r.n, r.Z, (const int32_t *)block_ptr(s, r, L.rowptr),
-                               (const int32_t *)block_ptr(s, r, L.colidx), (const int32_t *)block_ptr(s, r, L.diag_pos),
-                               (int32_t *)block_ptr(s, r, L.lrow), (int32_t *)block_ptr(s, r, L.urow),
-                               (int32_t *)block_ptr(s, r, L.pair_ptr), block_ptr(s, r, L.scratch),
-                               s->h_small + 8 * r.slot + 1, s->setup);
+void fail_request(abilu_server *s, Req &r, abilu_status st) {
+    r.state = Q_DONE;
+    r.res.status = st;
+    r.res.t_done = now_s() - s->t0;
+    release(s, r);
 }
 
-abilu_status admit_finish(abilu_server *s, Req &r, int64_t ZL, int64_t ZU, int64_t np) {
+enum SetupShape { SS_ROW256 = 0, SS_ROW64, SS_ROW128, SS_SCAN_N, SS_SCAN_Z, SS_FIN_N, SS_FIN_Z, SS_ONE, SS_COUNT };
+
+int setup_tiles(const Req &r, int shape) {
+    const int64_t n = r.n, Z = r.Z;
+    switch (shape) {
+        case SS_ROW256: return div_up(n, 256);
+        case SS_ROW64: return div_up(n, ROWS_PER_WG);
+        case SS_ROW128: return div_up(n, 128);
+        case SS_SCAN_N: return div_up(n > 0 ? n : 1, abilu_setup::SCAN_TILE);
+        case SS_SCAN_Z: return div_up(Z > 0 ? Z : 1, abilu_setup::SCAN_TILE);
+        case SS_FIN_N: return div_up(n + 1, 256);
+        case SS_FIN_Z: return div_up(Z + 1, 256);
+        default: return 1;
+    }
+}
+
+// Member tables of the batch `ids` (member m = position in ids), uploaded to d_stab.
+struct SetupTables {
+    const Member *d[SS_COUNT];
+    int tiles[SS_COUNT];
+    int count;
+};
+
+abilu_status upload_setup_tables(abilu_server *s, const std::vector<int64_t> &ids, const std::vector<int> &members,
+                                 SetupTables &T) {
+    int used = 0;
+    T.count = (int)members.size();
+    for (int sh = 0; sh < SS_COUNT; ++sh) {
+        T.d[sh] = s->d_stab + used;
+        int tile = 0;
+        for (size_t q = 0; q < members.size(); ++q) {
+            const Req &r = s->reqs[ids[members[q]]];
+            s->h_stab[used + q] = Member{members[q], tile, 0, 0};
+            tile += setup_tiles(r, sh);
+        }
+        T.tiles[sh] = tile;
+        used += (int)members.size();
+    }
+    return hip_ok(hipMemcpyAsync(s->d_stab, s->h_stab, sizeof(Member) * used, hipMemcpyHostToDevice, s->setup),
+                  "serve setup tables")
+               ? ABILU_OK
+               : ABILU_EDEVICE;
+}
+
+abilu_status launch_scan(abilu_server *s, const SetupTables &T, int which) {
+    const bool z = which == SC_PAIR;
+    hipStream_t st = s->setup;
+    kbs_scan_tiles<<<T.tiles[z ? SS_SCAN_Z : SS_SCAN_N], abilu_setup::SCAN_T, 0, st>>>(
+        s->d_sdesc, T.d[z ? SS_SCAN_Z : SS_SCAN_N], T.count, which);
+    if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+    kbs_scan_totals<<<T.tiles[SS_ONE], abilu_setup::SCAN_T, 0, st>>>(s->d_sdesc, T.d[SS_ONE], T.count, which);
+    if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+    kbs_scan_finish<<<T.tiles[z ? SS_FIN_Z : SS_FIN_N], 256, 0, st>>>(s->d_sdesc, T.d[z ? SS_FIN_Z : SS_FIN_N],
+                                                                      T.count, which, s->d_adm);
+    return launch_status();
+}
+
+void stage_request(abilu_server *s, Req &r, int m) {
     const ReqLayout &L = r.L;
     auto P = [&](size_t o) -> void * { return block_ptr(s, r, o); };
-    const int slot = r.slot;
-    hipStream_t st = s->setup;
-    int32_t *rowptr = (int32_t *)P(L.rowptr), *colidx = (int32_t *)P(L.colidx);
-    abilu_status ps = pattern_fill(r.n, r.Z, ZL, ZU, np, rowptr, colidx, (int32_t *)P(L.diag_pos),
-                                   (int32_t *)P(L.lrow), (int32_t *)P(L.urow), (int32_t *)P(L.lcol),
-                                   (int32_t *)P(L.ucol), (int32_t *)P(L.pik), (int32_t *)P(L.pkj), (int32_t *)P(L.sik),
-                                   (int32_t *)P(L.skj), P(L.scratch), st);
-    if (ps != ABILU_OK) return ps;
-    r.ZL = ZL;
-    r.ZU = ZU;
-    r.P = np;
-    Slot &d = s->h_slots[slot];
+    SetupDesc &D = s->h_sdesc[m];
+    D = SetupDesc{};
+    D.n = r.n;
+    D.kind = r.spec.kind;
+    D.nx = r.spec.nx;
+    D.ny = r.spec.ny;
+    D.Z = r.Z;
+    D.cfl = r.spec.cfl;
+    D.seed = r.spec.seed;
+    D.rowptr = (int32_t *)P(L.rowptr);
+    D.colidx = (int32_t *)P(L.colidx);
+    D.diag_pos = (int32_t *)P(L.diag_pos);
+    D.lrow = (int32_t *)P(L.lrow);
+    D.urow = (int32_t *)P(L.urow);
+    D.lcol = (int32_t *)P(L.lcol);
+    D.ucol = (int32_t *)P(L.ucol);
+    D.pair_ptr = (int32_t *)P(L.pair_ptr);
+    D.pik = (int32_t *)P(L.pik);
+    D.pkj = (int32_t *)P(L.pkj);
+    D.sik = (int32_t *)P(L.sik);
+    D.skj = (int32_t *)P(L.skj);
+    D.A = (double *)P(L.A);
+    D.b = (double *)P(L.b);
+    const int64_t len = r.Z + r.n + 2;
+    D.cnt = (int64_t *)((char *)P(L.scratch) + 256);
+    D.tmp = D.cnt + len;
+    D.ptr64 = D.tmp + len;
+    D.tot = D.ptr64 + len;
+    D.slot = r.slot;
+    // the slot descriptor the tick kernels will use (ZL is filled in on the device)
+    Slot &d = s->h_slots[m];
     d = Slot{};
     d.n = r.n;
-    d.ZL = (int32_t)ZL;
     d.nb_vec = L.nb_vec;
     d.nv = 4 * (int64_t)r.n;
-    d.rowptr = rowptr;
-    d.colidx = colidx;
-    d.diag_pos = (const int32_t *)P(L.diag_pos);
-    d.pair_ptr = (const int32_t *)P(L.pair_ptr);
-    d.pik = (const int32_t *)P(L.pik);
-    d.pkj = (const int32_t *)P(L.pkj);
-    d.sik = (const int32_t *)P(L.sik);
-    d.skj = (const int32_t *)P(L.skj);
-    d.lrow = (const int32_t *)P(L.lrow);
-    d.urow = (const int32_t *)P(L.urow);
-    d.lcol = (const int32_t *)P(L.lcol);
-    d.ucol = (const int32_t *)P(L.ucol);
-    d.A = (const double *)P(L.A);
-    d.b = (const double *)P(L.b);
+    d.rowptr = D.rowptr;
+    d.colidx = D.colidx;
+    d.diag_pos = D.diag_pos;
+    d.pair_ptr = D.pair_ptr;
+    d.pik = D.pik;
+    d.pkj = D.pkj;
+    d.sik = D.sik;
+    d.skj = D.skj;
+    d.lrow = D.lrow;
+    d.urow = D.urow;
+    d.lcol = D.lcol;
+    d.ucol = D.ucol;
+    d.A = D.A;
+    d.b = D.b;
     d.x = (double *)P(L.x);
     d.LU = P(L.LU);
     d.Dinv = P(L.Dinv);
@@ -445,32 +641,8 @@ abilu_status admit_finish(abilu_server *s, Req &r, int64_t ZL, int64_t ZU, int64
     d.red = (double *)P(L.red);
     d.V = (double *)P(L.V);
     d.Z = (double *)P(L.Z);
-    d.flags = (unsigned *)(s->d_hdr + (size_t)slot * HDR);
-    d.status = (double *)(s->d_hdr + (size_t)slot * HDR + 64);
-    if (!hip_ok(hipMemsetAsync(s->d_hdr + (size_t)slot * HDR, 0, HDR, st), "serve header clear") ||
-        !hip_ok(hipMemsetAsync(d.misc, 0, 8 * 16, st), "serve misc clear") ||
-        !hip_ok(hipMemcpyAsync(s->d_slots + slot, &d, sizeof(Slot), hipMemcpyHostToDevice, st), "serve slot upload") ||
-        !hip_ok(hipEventRecord(s->ev[slot], st), "serve setup event"))
-        return ABILU_EDEVICE;
-    r.state = Q_READY;
-    r.res.t_admit = now_s() - s->t0;
-    ++s->stat_admitted;
-    return ABILU_OK;
-}
-
-void release(abilu_server *s, Req &r) {
-    if (r.slot >= 0) {
-        s->slot_req[r.slot] = -1;
-        r.slot = -1;
-    }
-    s->alloc.release(r.off, r.L.total);
-}
-
-void fail_request(abilu_server *s, Req &r, abilu_status st) {
-    r.state = Q_DONE;
-    r.res.status = st;
-    r.res.t_done = now_s() - s->t0;
-    release(s, r);
+    d.flags = (unsigned *)(s->d_hdr + (size_t)r.slot * HDR);
+    d.status = (double *)(s->d_hdr + (size_t)r.slot * HDR + 64);
 }
 
 // Admit queued requests in arrival order while a slot and pool space are free (the head of the
@@ -478,11 +650,11 @@ void fail_request(abilu_server *s, Req &r, abilu_status st) {
 // per call beyond the first request: admission then proceeds alongside the ticks instead of
 // filling the pool in one burst whose requests would all finish together.
 abilu_status admit_queued(abilu_server *s, int64_t cell_budget) {
-    std::vector<int64_t> batch;
+    std::vector<int64_t> ids;
     int slot = 0;
     int64_t cells = 0;
     while (!s->queue.empty()) {
-        if (!batch.empty() && cells + s->reqs[s->queue.front()].n > cell_budget) break;
+        if (!ids.empty() && cells + s->reqs[s->queue.front()].n > cell_budget) break;
         while (slot < s->cfg.max_active && s->slot_req[slot] >= 0) ++slot;
         if (slot >= s->cfg.max_active) break;
         Req &r = s->reqs[s->queue.front()];
@@ -493,34 +665,97 @@ abilu_status admit_queued(abilu_server *s, int64_t cell_budget) {
         r.off = off;
         r.slot = slot;
         s->slot_req[slot] = id;
-        batch.push_back(id);
+        ids.push_back(id);
         cells += r.n;
     }
-    if (batch.empty()) return ABILU_OK;
-    for (int64_t id : batch)
-        if (admit_begin(s, s->reqs[id]) != ABILU_OK) return ABILU_EDEVICE;
-    if (!hip_ok(hipStreamSynchronize(s->setup), "serve admission sync")) return ABILU_EDEVICE;
-    std::vector<int64_t> valid;
-    for (int64_t id : batch) {
-        Req &r = s->reqs[id];
-        if (*(const unsigned *)(s->h_small + 8 * r.slot)) {
-            fail_request(s, r, ABILU_EPATTERN);
-            continue;
+    if (ids.empty()) return ABILU_OK;
+    hipStream_t st = s->setup;
+    const int B = (int)ids.size();
+    for (int m = 0; m < B; ++m) stage_request(s, s->reqs[ids[m]], m);
+    std::vector<int> members(B);
+    for (int m = 0; m < B; ++m) members[m] = m;
+    SetupTables T;
+#define CKS(x)                                     \
+    do {                                           \
+        if (!hip_ok((x), #x)) return ABILU_EDEVICE; \
+    } while (0)
+#define CKL()                                                  \
+    do {                                                       \
+        if (launch_status() != ABILU_OK) return ABILU_EDEVICE; \
+    } while (0)
+    CKS(hipMemcpyAsync(s->d_sdesc, s->h_sdesc, sizeof(SetupDesc) * B, hipMemcpyHostToDevice, st));
+    CKS(hipMemcpyAsync(s->d_sslot, s->h_slots, sizeof(Slot) * B, hipMemcpyHostToDevice, st));
+    CKS(hipMemsetAsync(s->d_adm, 0, sizeof(int64_t) * 4 * B, st));
+    if (upload_setup_tables(s, ids, members, T) != ABILU_OK) return ABILU_EDEVICE;
+    // pass 1: generation (row lengths, row pointers, blocks and right-hand side) and validation
+    kbs_gen_rowlen<<<T.tiles[SS_ROW256], 256, 0, st>>>(s->d_sdesc, T.d[SS_ROW256], T.count);
+    CKL();
+    if (launch_scan(s, T, SC_ROWPTR) != ABILU_OK) return ABILU_EDEVICE;
+    kbs_gen_fill<<<T.tiles[SS_ROW64], WG, 0, st>>>(s->d_sdesc, T.d[SS_ROW64], T.count);
+    CKL();
+    kbs_pat_rows<<<T.tiles[SS_ROW256], 256, 0, st>>>(s->d_sdesc, T.d[SS_ROW256], T.count, s->d_adm);
+    CKL();
+    CKS(hipMemcpyAsync(s->h_adm, s->d_adm, sizeof(int64_t) * 4 * B, hipMemcpyDeviceToHost, st));
+    CKS(hipStreamSynchronize(st));
+    auto keep = [&](auto bad, abilu_status why) -> bool {   // drop failed members, true if any dropped
+        std::vector<int> next;
+        for (int m : members) {
+            Req &r = s->reqs[ids[m]];
+            if (bad(m, r)) fail_request(s, r, why);
+            else next.push_back(m);
         }
-        if (admit_count(s, r) != ABILU_OK) return ABILU_EDEVICE;
-        valid.push_back(id);
+        const bool changed = next.size() != members.size();
+        members.swap(next);
+        return changed;
+    };
+    if (keep([&](int m, const Req &) { return *(const unsigned *)(s->h_adm + 4 * m) != 0; }, ABILU_EPATTERN)) {
+        if (members.empty()) return ABILU_OK;
+        if (upload_setup_tables(s, ids, members, T) != ABILU_OK) return ABILU_EDEVICE;
     }
-    if (!hip_ok(hipStreamSynchronize(s->setup), "serve admission sync")) return ABILU_EDEVICE;
-    for (int64_t id : valid) {
-        Req &r = s->reqs[id];
-        const int64_t *sz = s->h_small + 8 * r.slot + 1;
-        if (!pattern_sizes_ok(r.n, r.Z, sz) || sz[0] > r.L.zcap || sz[1] > r.L.zcap || sz[2] > r.L.pcap) {
-            fail_request(s, r, ABILU_EPATTERN);
-            continue;
-        }
-        if (admit_finish(s, r, sz[0], sz[1], sz[2]) != ABILU_OK) return ABILU_EDEVICE;
+    // pass 2: lower / upper part offsets and update-set offsets, with their totals
+    kbs_pat_tri_counts<<<T.tiles[SS_ROW256], 256, 0, st>>>(s->d_sdesc, T.d[SS_ROW256], T.count);
+    CKL();
+    if (launch_scan(s, T, SC_LROW) != ABILU_OK || launch_scan(s, T, SC_UROW) != ABILU_OK) return ABILU_EDEVICE;
+    kbs_pat_count<<<T.tiles[SS_ROW128], 128, 0, st>>>(s->d_sdesc, T.d[SS_ROW128], T.count);
+    CKL();
+    if (launch_scan(s, T, SC_PAIR) != ABILU_OK) return ABILU_EDEVICE;
+    CKS(hipMemcpyAsync(s->h_adm, s->d_adm, sizeof(int64_t) * 4 * B, hipMemcpyDeviceToHost, st));
+    CKS(hipStreamSynchronize(st));
+    if (keep(
+            [&](int m, const Req &r) {
+                const int64_t *sz = s->h_adm + 4 * m + 1;
+                return !pattern_sizes_ok(r.n, r.Z, sz) || sz[0] > r.L.zcap || sz[1] > r.L.zcap || sz[2] > r.L.pcap;
+            },
+            ABILU_EPATTERN)) {
+        if (members.empty()) return ABILU_OK;
+        if (upload_setup_tables(s, ids, members, T) != ABILU_OK) return ABILU_EDEVICE;
     }
+    // pass 3: part columns, update-set lists, slot descriptors; the compute stream waits on the
+    // per-slot events before a request's first tick
+    kbs_pat_tri_cols<<<T.tiles[SS_ROW256], 256, 0, st>>>(s->d_sdesc, T.d[SS_ROW256], T.count, s->d_adm);
+    CKL();
+    kbs_pat_fill<<<T.tiles[SS_ROW128], 128, 0, st>>>(s->d_sdesc, T.d[SS_ROW128], T.count, s->d_adm);
+    CKL();
+    kbs_publish<<<T.tiles[SS_ONE], 64, 0, st>>>(s->d_sdesc, T.d[SS_ONE], T.count, s->d_sslot, s->d_slots, s->d_hdr,
+                                                 s->d_adm);
+    CKL();
+    const double t = now_s() - s->t0;
+    for (int m : members) {
+        Req &r = s->reqs[ids[m]];
+        const int64_t *sz = s->h_adm + 4 * m + 1;
+        r.ZL = sz[0];
+        r.ZU = sz[1];
+        r.P = sz[2];
+        CKS(hipEventRecord(s->ev[r.slot], st));
+        r.state = Q_READY;
+        r.res.t_admit = t;
+        ++s->stat_admitted;
+    }
+    // the staging buffers are rewritten by the next admission: let this one finish first
+    CKS(hipStreamSynchronize(st));
     return ABILU_OK;
+#undef CKS
+#undef CKL
 }
 
 // ---- per-tick member tables
@@ -985,7 +1220,13 @@ void free_server(abilu_server *s) {
     if (s->h_slots) (void)hipHostFree(s->h_slots);
     if (s->h_tab) (void)hipHostFree(s->h_tab);
     if (s->h_hdr) (void)hipHostFree(s->h_hdr);
-    if (s->h_small) (void)hipHostFree(s->h_small);
+    (void)hipFree(s->d_sdesc);
+    (void)hipFree(s->d_sslot);
+    (void)hipFree(s->d_stab);
+    (void)hipFree(s->d_adm);
+    if (s->h_sdesc) (void)hipHostFree(s->h_sdesc);
+    if (s->h_stab) (void)hipHostFree(s->h_stab);
+    if (s->h_adm) (void)hipHostFree(s->h_adm);
     delete s;
 }
 
@@ -1023,7 +1264,14 @@ extern "C" abilu_status abilu_serve_create(const abilu_serve_config *cfg, void *
               hip_ok(hipHostMalloc((void **)&s->h_tab, sizeof(Member) * s->tab_cap, hipHostMallocDefault),
                      "serve pinned") &&
               hip_ok(hipHostMalloc((void **)&s->h_hdr, (size_t)HDR * S, hipHostMallocDefault), "serve pinned") &&
-              hip_ok(hipHostMalloc((void **)&s->h_small, 8 * sizeof(int64_t) * S, hipHostMallocDefault), "serve pinned");
+              hip_ok(hipMalloc(&s->d_sdesc, sizeof(SetupDesc) * S), "serve setup descriptors") &&
+              hip_ok(hipMalloc(&s->d_sslot, sizeof(Slot) * S), "serve staged slots") &&
+              hip_ok(hipMalloc(&s->d_stab, sizeof(Member) * SS_COUNT * S), "serve setup tables") &&
+              hip_ok(hipMalloc(&s->d_adm, sizeof(int64_t) * 4 * S), "serve admission words") &&
+              hip_ok(hipHostMalloc((void **)&s->h_sdesc, sizeof(SetupDesc) * S, hipHostMallocDefault), "serve pinned") &&
+              hip_ok(hipHostMalloc((void **)&s->h_stab, sizeof(Member) * SS_COUNT * S, hipHostMallocDefault),
+                     "serve pinned") &&
+              hip_ok(hipHostMalloc((void **)&s->h_adm, sizeof(int64_t) * 4 * S, hipHostMallocDefault), "serve pinned");
     for (int q = 0; ok && q < S; ++q)
         ok = hip_ok(hipEventCreateWithFlags(&s->ev[q], hipEventDisableTiming), "serve events");
     if (ok) ok = hip_ok(hipMemset(s->d_hdr, 0, (size_t)HDR * S), "serve header init");
