@@ -470,3 +470,36 @@ def test_generator_shapes():
         assert np.allclose(np.diag(c.vals[e]), 1.0 + off, atol=0.1)
     t = W.case("tri", seed=1, nx=5, ny=4)
     assert t.n == 40 and np.bincount(np.repeat(np.arange(t.n), np.diff(t.rowptr))).max() <= 4
+
+
+@pytest.mark.parametrize("name,c", small_cases())
+def test_fixed_point_residual_dense(name, c):
+    """The fixed-point residual sum |X - h(X)| over the pattern, at a random iterate X, equals the
+    dense computation: the update-set sum S_ij is the dense product (L U)_ij minus the term with
+    k = min(i,j) (X_ij X_jj below the diagonal, X_ij on and above), and h(X) follows equation
+    blockH from it."""
+    rng = np.random.default_rng(11)
+    X = rng.uniform(-0.5, 0.5, c.vals.shape)
+    diag = np.zeros(c.nnzb, bool)
+    for i in range(c.n):
+        for e in range(c.rowptr[i], c.rowptr[i + 1]):
+            diag[e] = c.colidx[e] == i
+    X[diag] += 4.0 * np.eye(4)                       # nonsingular diagonal blocks
+    L, U = factors_dense(c.n, c.rowptr, c.colidx, X)
+    P = L @ U
+    pos = {}
+    for i in range(c.n):
+        for e in range(c.rowptr[i], c.rowptr[i + 1]):
+            pos[(i, int(c.colidx[e]))] = e
+    total = 0.0
+    for (i, j), e in pos.items():
+        blk = P[4 * i:4 * i + 4, 4 * j:4 * j + 4]
+        if i > j:
+            S = blk - X[e] @ X[pos[(j, j)]]
+            h = (c.vals[e] - S) @ np.linalg.inv(X[pos[(j, j)]])
+        else:
+            S = blk - X[e]
+            h = c.vals[e] - S
+        total += np.abs(X[e] - h).sum()
+    got = oracle.fixed_point_residual(c.n, c.rowptr, c.colidx, c.vals, X)
+    assert abs(got - total) <= 1e-10 * total, (got, total)
