@@ -53,7 +53,13 @@ typedef enum {
     ABILU_ENONFINITE = -5      /* a non-finite value appeared (FGMRES result) */
 } abilu_status;
 
-typedef enum { ABILU_SYNC = 0, ABILU_ASYNC = 1 } abilu_mode;
+/* ABILU_ASYNC_SERIAL: the asynchronous in-place iteration run by a single worker (one quad of
+ * lanes) over the block rows in order; the reference schedule with which the paper identifies
+ * the asynchronous iteration on one thread with the sequential algorithm (Sections 3.3, 4.2): a
+ * factor sweep is then a Gauss-Seidel sweep (from X0 = A, one sweep gives the exact ILU(0)), a
+ * forward apply sweep is forward substitution and a backward sweep (rows in descending order)
+ * back substitution. It occupies one compute unit lane group: for verification, not speed. */
+typedef enum { ABILU_SYNC = 0, ABILU_ASYNC = 1, ABILU_ASYNC_SERIAL = 2 } abilu_mode;
 typedef enum { ABILU_F64 = 0, ABILU_F32 = 1 } abilu_prec;
 typedef enum { ABILU_INIT_FROM_A = 0, ABILU_INIT_FROM_LU = 1 } abilu_init;
 
@@ -126,7 +132,10 @@ abilu_status abilu_factor(const abilu_pattern *p, const double *d_A, void *d_LU,
  *   forward  y_i <- r_i - sum_{j<i} L_ij y_j                  (L_ii = I)
  *   backward z_i <- U_ii^{-1} (y_i - sum_{j>i} U_ij z_j)
  * nsweeps forward sweeps then nsweeps backward sweeps (nsweeps = 0: z = r, no preconditioning).
- * SYNC sweeps read the previous sweep's vector; ASYNC sweeps update the vector in place.
+ * SYNC sweeps read the previous sweep's vector; ASYNC sweeps update the vector in place. From the
+ * zero initial guess the first sweeps are y = r and z = U_ii^{-1} y and are taken in that closed
+ * form (not launched) in both modes. ABILU_ASYNC_SERIAL runs every sweep, forward rows ascending
+ * and backward rows descending, from zero vectors.
  *   d_r double[4N] (read), d_z double[4N] (written; must not alias d_r)
  *   intermediate vectors are stored in prec; d_r is rounded to prec on load.
  * Non-blocking. Errors: ABILU_EINVAL, ABILU_EDEVICE.

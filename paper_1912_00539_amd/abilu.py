@@ -15,13 +15,13 @@ LIB_PATH = os.path.join(HERE, "lib", "libabilu.so")
 
 ABILU_OK, ABILU_WARN_MODIFIED, ABILU_WARN_NOCONV = 0, 1, 2
 ABILU_EINVAL, ABILU_EPATTERN, ABILU_ENOMEM, ABILU_EDEVICE, ABILU_ENONFINITE = -1, -2, -3, -4, -5
-ABILU_SYNC, ABILU_ASYNC = 0, 1
+ABILU_SYNC, ABILU_ASYNC, ABILU_ASYNC_SERIAL = 0, 1, 2
 ABILU_F64, ABILU_F32 = 0, 1
 ABILU_INIT_FROM_A, ABILU_INIT_FROM_LU = 0, 1
 ABILU_FLAG_MODIFIED, ABILU_FLAG_NONFINITE = 1, 2
 ABILU_FGMRES_ZERO_GUESS = 1
 
-MODES = {"sync": ABILU_SYNC, "async": ABILU_ASYNC}
+MODES = {"sync": ABILU_SYNC, "async": ABILU_ASYNC, "serial": ABILU_ASYNC_SERIAL}
 PRECS = {"f64": ABILU_F64, "f32": ABILU_F32}
 INITS = {"A": ABILU_INIT_FROM_A, "LU": ABILU_INIT_FROM_LU}
 

@@ -39,6 +39,28 @@ __global__ __launch_bounds__(WG) void k_bwd(int n, const int32_t *__restrict__ u
     bwd_body<T, YI, ZO, OFFDIAG, DUAL>(blockIdx.x, n, urow, ucol, Ub, Dinv, y, zin, zout, zout2);
 }
 
+// Single-worker sweeps (ABILU_ASYNC_SERIAL): one quad, in place; forward rows ascending,
+// backward rows descending (the second row slot of the body is past the end and skipped).
+template <typename T>
+__global__ __launch_bounds__(64) void k_fwd_serial(int n, const int32_t *__restrict__ lrow,
+                                                   const int32_t *__restrict__ lcol, const T *__restrict__ Lb,
+                                                   const double *__restrict__ rhs, T *y) {
+    for (int i = 0; i < n; ++i) {
+        fwd_rows<T, T, false>(i, n, n, lrow, lcol, Lb, rhs, y, y, (const T *)nullptr, (T *)nullptr);
+        __threadfence();
+    }
+}
+
+template <typename T, typename ZO, bool DUAL>
+__global__ __launch_bounds__(64) void k_bwd_serial(int n, const int32_t *__restrict__ urow,
+                                                   const int32_t *__restrict__ ucol, const T *__restrict__ Ub,
+                                                   const T *__restrict__ Dinv, const T *__restrict__ y, T *zin, ZO *zout) {
+    for (int i = n - 1; i >= 0; --i) {
+        bwd_rows<T, T, ZO, true, DUAL>(i, n, n, urow, ucol, Ub, Dinv, y, zin, zout, zin);
+        __threadfence();
+    }
+}
+
 // y = A x  (RESID: y = b - A x), double precision, CSR; one quad per block row, four blocks
 // loaded per step (clamped: rows always hold at least their diagonal block)
 template <bool RESID>
@@ -68,7 +90,7 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
     T *za = (T *)(work + W.za), *zb = (T *)(work + W.zb);
     char name[64];
     auto NAME = [&](const char *base) {
-        snprintf(name, sizeof name, "%s_%s_%s", base, tname<T>(), mode == ABILU_SYNC ? "sync" : "async");
+        snprintf(name, sizeof name, "%s_%s_%s", base, tname<T>(), mode == ABILU_SYNC ? "sync" : (mode == ABILU_ASYNC ? "async" : "serial"));
         return name;
     };
     const Sizes zz = sizes(p);
@@ -81,6 +103,27 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
     // z = Dinv y). In ASYNC mode this is the admissible schedule in which no read of sweep 1 sees
     // a value written in the same sweep; sweeps 2..nsw then update y and z in place. SYNC sweeps
     // read the previous sweep's vector (ping-pong ya/yb, za/zb).
+    if (mode == ABILU_ASYNC_SERIAL) {
+        const int64_t nv = 4 * (int64_t)n;
+        if (!hip_ok(hipMemsetAsync(ya, 0, sizeof(T) * nv, s), "serial apply clear") ||
+            !hip_ok(hipMemsetAsync(za, 0, sizeof(T) * nv, s), "serial apply clear"))
+            return ABILU_EDEVICE;
+        for (int q = 1; q <= nsw; ++q) {
+            ProfScope ps(NAME("apply_fwd"), s, bytes_fwd(zz, sF, sF, false));
+            k_fwd_serial<T><<<1, 4, 0, s>>>(n, lrow, lcol, Lb, r, ya);
+            LAUNCHED();
+        }
+        for (int q = 1; q <= nsw; ++q) {
+            const bool last = q == nsw;
+            ProfScope ps(NAME(last ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, last ? 8 : sF, last));
+            if (last)
+                k_bwd_serial<T, double, true><<<1, 4, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, z);
+            else
+                k_bwd_serial<T, T, false><<<1, 4, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, za);
+            LAUNCHED();
+        }
+        return ABILU_OK;
+    }
     const bool sync = mode == ABILU_SYNC;
     if (nsw == 1) {
         ProfScope ps(NAME("apply_diag"), s, 32 * zz.N + 16 * sF * zz.N + 32 * zz.N);
@@ -172,7 +215,7 @@ extern "C" abilu_status abilu_apply(const abilu_pattern *p, const void *d_LU, co
                                     size_t work_bytes, void *stream) {
     if (!p || nsweeps < 0) return ABILU_EINVAL;
     if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
-    if (mode != ABILU_SYNC && mode != ABILU_ASYNC) return ABILU_EINVAL;
+    if (mode != ABILU_SYNC && mode != ABILU_ASYNC && mode != ABILU_ASYNC_SERIAL) return ABILU_EINVAL;
     if (!d_work) return ABILU_EINVAL;
     const Workspace W = layout(p, prec, 0);
     if (work_bytes < W.total) return ABILU_EINVAL;

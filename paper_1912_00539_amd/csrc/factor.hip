@@ -54,6 +54,22 @@ __global__ __launch_bounds__(WG) void k_factor_sweep(
     factor_sweep_body<T, L_FROM_A, U_FROM_A>(blockIdx.x, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags);
 }
 
+// The asynchronous sweep with a single worker: one quad over the rows in ascending order, in
+// place (a Gauss-Seidel sweep). Launched with one workgroup of 4 lanes.
+template <typename T>
+__global__ __launch_bounds__(64) void k_factor_sweep_serial(
+    int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+    const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
+    const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, T *X, T *D,
+    unsigned *flags) {
+    for (int i = 0; i < n; ++i) {
+        factor_sweep_row<T, false, false, 1>(i, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, pik, pkj, sik,
+                                             skj, A, X, X, D, X, D, flags);
+        __threadfence();   // row i's blocks and inverse are visible to the rows after it
+    }
+}
+
 // Conversions between the factor layout and CSR order (one quad per block row).
 template <typename T, bool TO_CSR>
 __global__ __launch_bounds__(WG) void k_factor_permute(int n, int ZL, const int32_t *__restrict__ rowptr,
@@ -134,6 +150,25 @@ abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, i
         return init_dinv_X(LU, Dinv);
     }
 
+    if (mode == ABILU_ASYNC_SERIAL) {
+        // X0 copied into LU (from A) or taken from LU, then nsw in-place sweeps by one worker
+        if (init == ABILU_INIT_FROM_A) {
+            ProfScope ps(NAME("factor_init", "_copy"), s, bytes_init(z, 8, sF, true));
+            k_factor_init<T, double, true, true><<<grid, WG, 0, s>>>(n, ZL, p->rowptr, p->diag_pos, p->lrow, p->urow,
+                                                                     A, LU, Dinv, flags);
+            LAUNCHED();
+        } else if ((st = init_dinv_X(LU, Dinv)) != ABILU_OK) {
+            return st;
+        }
+        for (int q = 0; q < nsw; ++q) {
+            ProfScope ps(NAME("factor_sweep", "_serial"), s, bytes_sweep(z, sF, false, false));
+            k_factor_sweep_serial<T><<<1, 4, 0, s>>>(n, ZL, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow,
+                                                     p->pair_ptr, p->pik, p->pkj, p->sik, p->skj, A, LU, Dinv, flags);
+            LAUNCHED();
+        }
+        return ABILU_OK;
+    }
+
     if (mode == ABILU_ASYNC) {
         int q0 = 0;
         if (init == ABILU_INIT_FROM_A) {
@@ -205,7 +240,7 @@ extern "C" abilu_status abilu_factor(const abilu_pattern *p, const double *d_A, 
                                      void *d_work, size_t work_bytes, void *stream) {
     if (!p || nsweeps < 0) return ABILU_EINVAL;
     if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
-    if (mode != ABILU_SYNC && mode != ABILU_ASYNC) return ABILU_EINVAL;
+    if (mode != ABILU_SYNC && mode != ABILU_ASYNC && mode != ABILU_ASYNC_SERIAL) return ABILU_EINVAL;
     if (init != ABILU_INIT_FROM_A && init != ABILU_INIT_FROM_LU) return ABILU_EINVAL;
     if (!d_work) return ABILU_EINVAL;
     const Workspace W = layout(p, prec, 0);

@@ -51,18 +51,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ bool skipped(const int *guard) { return guard && *guard == 0; }
 
+// Forward sweep on rows ib and ib + stride (RPQ rows per quad; rows >= n are skipped).
 template <typename T, typename YI, bool EMIT_Z>
-__device__ __forceinline__ void fwd_body(int blk, int n, const int32_t *__restrict__ lrow, const int32_t *__restrict__ lcol,
-                                            const T *__restrict__ Lb, const double *__restrict__ rhs, const YI *yin,
-                                            T *yout, const T *__restrict__ Dinv, T *__restrict__ zout) {
-    const int ib = blk * ROWS_PER_WG2 + (threadIdx.x >> 2);
+__device__ __forceinline__ void fwd_rows(int ib, int stride, int n, const int32_t *__restrict__ lrow,
+                                         const int32_t *__restrict__ lcol, const T *__restrict__ Lb,
+                                         const double *__restrict__ rhs, const YI *yin, T *yout,
+                                         const T *__restrict__ Dinv, T *__restrict__ zout) {
     const int r = threadIdx.x & 3;
     if (ib >= n) return;
     int ii[RPQ], b0[RPQ], b1[RPQ];
     T acc[RPQ];
 #pragma unroll
     for (int h = 0; h < RPQ; ++h) {
-        ii[h] = ib + h * ROWS_PER_WG;
+        ii[h] = ib + h * stride;
         const int i = min(ii[h], n - 1);
         b0[h] = lrow[i];
         b1[h] = (ii[h] < n) ? lrow[i + 1] : b0[h];
@@ -110,18 +111,27 @@ __device__ __forceinline__ void fwd_body(int blk, int n, const int32_t *__restri
     }
 }
 
+template <typename T, typename YI, bool EMIT_Z>
+__device__ __forceinline__ void fwd_body(int blk, int n, const int32_t *__restrict__ lrow, const int32_t *__restrict__ lcol,
+                                            const T *__restrict__ Lb, const double *__restrict__ rhs, const YI *yin,
+                                            T *yout, const T *__restrict__ Dinv, T *__restrict__ zout) {
+    fwd_rows<T, YI, EMIT_Z>(blk * ROWS_PER_WG2 + (threadIdx.x >> 2), ROWS_PER_WG, n, lrow, lcol, Lb, rhs, yin, yout,
+                            Dinv, zout);
+}
+
+// Backward sweep on rows ib and ib + stride.
 template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
-__device__ __forceinline__ void bwd_body(int blk, int n, const int32_t *__restrict__ urow, const int32_t *__restrict__ ucol,
-                                            const T *__restrict__ Ub, const T *__restrict__ Dinv,
-                                            const YI *__restrict__ y, const T *zin, ZO *zout, T *zout2) {
-    const int ib = blk * ROWS_PER_WG2 + (threadIdx.x >> 2);
+__device__ __forceinline__ void bwd_rows(int ib, int stride, int n, const int32_t *__restrict__ urow,
+                                         const int32_t *__restrict__ ucol, const T *__restrict__ Ub,
+                                         const T *__restrict__ Dinv, const YI *__restrict__ y, const T *zin, ZO *zout,
+                                         T *zout2) {
     const int r = threadIdx.x & 3;
     if (ib >= n) return;
     int ii[RPQ], b0[RPQ], b1[RPQ];
     T acc[RPQ];
 #pragma unroll
     for (int h = 0; h < RPQ; ++h) {
-        ii[h] = ib + h * ROWS_PER_WG;
+        ii[h] = ib + h * stride;
         const int i = min(ii[h], n - 1);
         acc[h] = (T)y[(int64_t)i * 4 + r];
         if constexpr (OFFDIAG) {
@@ -170,6 +180,14 @@ __device__ __forceinline__ void bwd_body(int blk, int n, const int32_t *__restri
             if constexpr (DUAL) zout2[(int64_t)ii[h] * 4 + r] = z;
         }
     }
+}
+
+template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
+__device__ __forceinline__ void bwd_body(int blk, int n, const int32_t *__restrict__ urow, const int32_t *__restrict__ ucol,
+                                            const T *__restrict__ Ub, const T *__restrict__ Dinv,
+                                            const YI *__restrict__ y, const T *zin, ZO *zout, T *zout2) {
+    bwd_rows<T, YI, ZO, OFFDIAG, DUAL>(blk * ROWS_PER_WG2 + (threadIdx.x >> 2), ROWS_PER_WG, n, urow, ucol, Ub, Dinv, y,
+                                       zin, zout, zout2);
 }
 
 template <bool RESID>
@@ -402,14 +420,18 @@ __device__ __forceinline__ void factor_init_body(int blk, int n, int ZL, const i
     if (!ok && r == 0) atomicOr(flags, ABILU_FLAG_MODIFIED);
 }
 
-template <typename T, bool L_FROM_A, bool U_FROM_A>
-__device__ __forceinline__ void factor_sweep_body(int blk, 
+// One sweep over block row i (a quad of 4 lanes). The strictly lower blocks are computed in
+// chunks of CHL, each chunk's results stored together: with CHL = 2 a block whose update set
+// contains the column of the block just before it in the same chunk reads that block's previous
+// value (admissible staleness in the asynchronous iteration); CHL = 1 gives the strict
+// ascending-column order of a Gauss-Seidel sweep.
+template <typename T, bool L_FROM_A, bool U_FROM_A, int CHL = CH>
+__device__ __forceinline__ void factor_sweep_row(int i,
     int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
     const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
     const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
     const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
-    const int i = blk * ROWS_PER_WG + (threadIdx.x >> 2);
     const int r = threadIdx.x & 3;
     if (i >= n) return;
     const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
@@ -421,26 +443,26 @@ __device__ __forceinline__ void factor_sweep_body(int blk,
     unsigned fl = 0;
 
     // strictly lower blocks: L_ij = (A_ij - sum) U_jj^{-1}
-    for (int e0 = b0; e0 < d; e0 += CH) {
-        T t[CH][4], dr[CH][4];
-        int j[CH];
+    for (int e0 = b0; e0 < d; e0 += CHL) {
+        T t[CHL][4], dr[CHL][4];
+        int j[CHL];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
+        for (int u = 0; u < CHL; ++u) {
             const int e = min(e0 + u, d - 1);
             load_row(A + (int64_t)e * BB, r, t[u]);
             j[u] = colidx[e];
         }
 #pragma unroll
-        for (int u = 0; u < CH; ++u) load_row(Dp + (int64_t)j[u] * BB, r, dr[u]);
+        for (int u = 0; u < CHL; ++u) load_row(Dp + (int64_t)j[u] * BB, r, dr[u]);
         if (pd > pb0) {
 #pragma unroll
-            for (int u = 0; u < CH; ++u)
+            for (int u = 0; u < CHL; ++u)
                 if (e0 + u < d)
                     update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
                                                         skj, A, XL, XU, t[u]);
         }
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
+        for (int u = 0; u < CHL; ++u) {
             T x[4];
             row_times_block(t[u], dr[u], x);
             if (e0 + u < d) {
@@ -483,6 +505,17 @@ __device__ __forceinline__ void factor_sweep_body(int blk,
         }
     }
     if (fl) atomicOr(flags, fl);
+}
+
+template <typename T, bool L_FROM_A, bool U_FROM_A>
+__device__ __forceinline__ void factor_sweep_body(int blk,
+    int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+    const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
+    const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
+    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
+    factor_sweep_row<T, L_FROM_A, U_FROM_A>(blk * ROWS_PER_WG + (threadIdx.x >> 2), n, ZL, rowptr, colidx, diag_pos,
+                                            lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags);
 }
 
 }  // namespace abilu_k

@@ -464,3 +464,39 @@ def test_full_size_tri2000_f32():
     x = s.x.cpu().numpy()
     true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
     assert true <= 1e-2 and abs(true - res["rel_true_residual"]) <= 1e-10
+
+
+# ------------------------------------------------------------------ single-worker schedule (P8)
+@pytest.mark.parametrize("name", CASES)
+def test_factor_serial_equals_gauss_seidel(name):
+    """The asynchronous in-place sweep run by one worker over the rows in order is a Gauss-Seidel
+    sweep (oracle_factor_gs); from X0 = A one such sweep is the sequential block ILU(0)
+    (Sections 3.3, 4.2). Exercises the in-place reads of fresh L_ik, U_kj and Dinv_j exactly,
+    including off-diagonal update sets (nine-point and random patterns)."""
+    c = get(name)
+    s = DS(c, "f64")
+    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    for nsw in (1, 2):
+        s.factor(nsw, "serial")
+        X, D = s.factor_host()
+        Xg, Dg, _ = oracle.factor_gs(c.n, c.rowptr, c.colidx, c.vals, nsw)
+        assert rel(X, Xg) <= 1e-12 and rel(D, Dg) <= 1e-12, (nsw, rel(X, Xg), rel(D, Dg))
+        if nsw == 1:
+            assert rel(X, Xs) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["quad32", "tri40x30_rcm", "nine23x17", "random1000", "aniso50x20_line", "chain7"])
+def test_apply_serial_is_exact_substitution(name):
+    """One forward sweep by one worker in ascending row order is forward substitution, one
+    backward sweep in descending order back substitution: z = (LU)^{-1} r (Algorithm 1)."""
+    c = get(name)
+    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    r = np.random.default_rng(5).uniform(-1, 1, 4 * c.n)
+    ref = oracle.trisolve_exact(c.n, c.rowptr, c.colidx, Xs, Ds, r)
+    s = DS(c, "f64")
+    s.set_factor(Xs, Ds)
+    rt = torch.from_numpy(r).cuda()
+    for nsw in (1, 2):
+        zt = torch.zeros_like(rt)
+        s.apply(rt, zt, nsw, "serial")
+        assert rel(zt.cpu().numpy(), ref) <= 1e-12, nsw
