@@ -247,81 +247,83 @@ __device__ __forceinline__ void gather_vec(T v, T (&x)[4]) {
     x[0] = qb<0>(v); x[1] = qb<1>(v); x[2] = qb<2>(v); x[3] = qb<3>(v);
 }
 
-// Inverse of a 4x4 block by Gaussian elimination with partial pivoting and back substitution,
-// all indices static (row exchanges are selects). Returns false, with R = I, if a pivot is
-// exactly zero or the inverse is not finite (the modified iteration's replacement).
+// Row r (this lane's index in the quad) of the inverse of the 4x4 block M, which every lane of
+// the quad holds: Gaussian elimination with partial pivoting and back substitution, all indices
+// static (row exchanges are selects). Every lane eliminates on M but carries only column r of
+// the identity as right-hand side and back-substitutes only column r of the inverse; the quad
+// then exchanges columns for rows by DPP. Each element goes through the same operations, in the
+// same order, as in the elimination on the full [M | I] (10 instead of 22 divisions per lane).
+// Returns false for the whole quad, with the identity row, if a pivot is exactly zero or any
+// element of the inverse is not finite (the modified iteration's replacement).
 template <typename T>
-__device__ __forceinline__ bool inv4(T (&M)[16], T (&R)[16]) {
+__device__ __forceinline__ bool inv4_row(T (&M)[16], int r, T (&out)[4]) {
+    T x[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) R[q] = (q % 5 == 0) ? T(1) : T(0);
+    for (int q = 0; q < 4; ++q) x[q] = (q == r) ? T(1) : T(0);
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int p = k;
         T best = fabs(M[k * 4 + k]);
 #pragma unroll
-        for (int r = k + 1; r < 4; ++r) {
-            T a = fabs(M[r * 4 + k]);
+        for (int q = k + 1; q < 4; ++q) {
+            T a = fabs(M[q * 4 + k]);
             bool gt = a > best;
             best = gt ? a : best;
-            p = gt ? r : p;
+            p = gt ? q : p;
         }
 #pragma unroll
-        for (int r = k + 1; r < 4; ++r) {
-            bool s = (p == r);
+        for (int q = k + 1; q < 4; ++q) {
+            bool s = (p == q);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                T a = M[k * 4 + c], b = M[r * 4 + c];
+                T a = M[k * 4 + c], b = M[q * 4 + c];
                 M[k * 4 + c] = s ? b : a;
-                M[r * 4 + c] = s ? a : b;
-                T x = R[k * 4 + c], y = R[r * 4 + c];
-                R[k * 4 + c] = s ? y : x;
-                R[r * 4 + c] = s ? x : y;
+                M[q * 4 + c] = s ? a : b;
             }
+            T u = x[k], v = x[q];
+            x[k] = s ? v : u;
+            x[q] = s ? u : v;
         }
         T piv = M[k * 4 + k];
         ok = ok && (piv != T(0));
 #pragma unroll
-        for (int r = k + 1; r < 4; ++r) {
-            T f = M[r * 4 + k] / piv;
+        for (int q = k + 1; q < 4; ++q) {
+            T f = M[q * 4 + k] / piv;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                M[r * 4 + c] -= f * M[k * 4 + c];
-                R[r * 4 + c] -= f * R[k * 4 + c];
-            }
+            for (int c = 0; c < 4; ++c) M[q * 4 + c] -= f * M[k * 4 + c];
+            x[q] -= f * x[k];
         }
     }
 #pragma unroll
     for (int k = 3; k >= 0; --k) {
+        T s = x[k];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            T s = R[k * 4 + c];
-#pragma unroll
-            for (int m = k + 1; m < 4; ++m) s -= M[k * 4 + m] * R[m * 4 + c];
-            R[k * 4 + c] = s / M[k * 4 + k];
-        }
+        for (int m = k + 1; m < 4; ++m) s -= M[k * 4 + m] * x[m];
+        x[k] = s / M[k * 4 + k];
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) ok = ok && isfinite(R[q]);
-    if (!ok) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) R[q] = (q % 5 == 0) ? T(1) : T(0);
-    }
-    return ok;
-}
-
-// Row r of a register-held 4x4 block (r = lane index within the quad, a runtime value). Two
-// levels of selects on the bits of r: a flat select chain is rewritten by the compiler into a
-// dynamically indexed stack array for 16 doubles.
-template <typename T>
-__device__ __forceinline__ void pick_row(const T (&M)[16], int r, T (&out)[4]) {
+    for (int q = 0; q < 4; ++q) ok = ok && isfinite(x[q]);
+    // the block is replaced if any lane's column failed
+    const int okl = ok ? 1 : 0;
+    const int okq = __builtin_amdgcn_update_dpp(0, okl, 0x00, 0xF, 0xF, false) &
+                    __builtin_amdgcn_update_dpp(0, okl, 0x55, 0xF, 0xF, false) &
+                    __builtin_amdgcn_update_dpp(0, okl, 0xAA, 0xF, 0xF, false) &
+                    __builtin_amdgcn_update_dpp(0, okl, 0xFF, 0xF, 0xF, false);
+    // out[c] = inverse(r, c) = element r of lane c's column
     const bool b0 = (r & 1) != 0, b1 = (r & 2) != 0;
+    T col[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const T lo = b0 ? M[4 + c] : M[c];
-        const T hi = b0 ? M[12 + c] : M[8 + c];
-        out[c] = b1 ? hi : lo;
+        if (c == 0) { col[0] = qb<0>(x[0]); col[1] = qb<0>(x[1]); col[2] = qb<0>(x[2]); col[3] = qb<0>(x[3]); }
+        if (c == 1) { col[0] = qb<1>(x[0]); col[1] = qb<1>(x[1]); col[2] = qb<1>(x[2]); col[3] = qb<1>(x[3]); }
+        if (c == 2) { col[0] = qb<2>(x[0]); col[1] = qb<2>(x[1]); col[2] = qb<2>(x[2]); col[3] = qb<2>(x[3]); }
+        if (c == 3) { col[0] = qb<3>(x[0]); col[1] = qb<3>(x[1]); col[2] = qb<3>(x[2]); col[3] = qb<3>(x[3]); }
+        const T lo = b0 ? col[1] : col[0];
+        const T hi = b0 ? col[3] : col[2];
+        out[c] = okq ? (b1 ? hi : lo) : ((c == r) ? T(1) : T(0));
     }
+    return okq != 0;
 }
 
 template <typename T>

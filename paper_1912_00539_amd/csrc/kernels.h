@@ -411,11 +411,10 @@ __device__ __forceinline__ void factor_init_body(int blk, int n, int ZL, const i
         }
     }
     const int64_t dpos = SRC_CSR ? (int64_t)diag_pos[i] : (int64_t)ZL + i;
-    T u[4], M[16], R[16], out[4];
+    T u[4], M[16], out[4];
     load_row(X0 + dpos * BB, r, u);
     gather_block(u, M);
-    bool ok = inv4(M, R);
-    pick_row(R, r, out);
+    bool ok = inv4_row(M, r, out);
     store_row(D0 + (int64_t)i * BB, r, out);
     if (!ok && r == 0) atomicOr(flags, ABILU_FLAG_MODIFIED);
 }
@@ -478,10 +477,9 @@ __device__ __forceinline__ void factor_sweep_row(int i,
         update_terms<T, L_FROM_A, U_FROM_A>(pd, pd1, r, pik, pkj, sik, skj, A, XL, XU, t);
         fl |= nonfinite4(t);
         store_row(Xn + ((int64_t)ZL + i) * BB, r, t);
-        T M[16], R[16], out[4];
+        T M[16], out[4];
         gather_block(t, M);
-        if (!inv4(M, R)) fl |= ABILU_FLAG_MODIFIED;
-        pick_row(R, r, out);
+        if (!inv4_row(M, r, out)) fl |= ABILU_FLAG_MODIFIED;
         store_row(Dn + (int64_t)i * BB, r, out);
     }
     // strictly upper blocks: U_ij = A_ij - sum
