@@ -125,6 +125,16 @@ def test_factor_sync_f64(name, nsw):
     assert s.flags() == fo == 0
 
 
+def f64_tolerance(c, nsw):
+    """max(1e-12, 8 x sensitivity of the oracle's factor to a relative perturbation of A by one
+    unit in the last place): where U_ii = A_ii - sum L_ik U_ki cancels (the aspect-ratio-1000
+    layers at the wall), rounding-order differences alone move Dinv by that much."""
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, nsw)
+    d = np.random.default_rng(17).uniform(-1.0, 1.0, c.vals.shape) * 2.0 ** -53
+    Xr, Dr, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals * (1.0 + d), nsw)
+    return Xo, Do, max(1e-12, 8 * rel(Xr, Xo)), max(1e-12, 8 * rel(Dr, Do))
+
+
 def f32_tolerance(c, nsw):
     """max(1e-5, 8 x sensitivity of the oracle's factor to rounding A to float)."""
     Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, nsw)
@@ -464,6 +474,73 @@ def test_full_size_tri2000_f32():
     x = s.x.cpu().numpy()
     true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
     assert true <= 1e-2 and abs(true - res["rel_true_residual"]) <= 1e-10
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cfl", [10.0, 100.0, 1000.0])
+def test_full_size_tri300(cfl):
+    """The 180,000-triangle workload (300 x 300 split quads, random permutation + RCM) at CFL 10,
+    100 and 1000: synchronous FP64 sweeps 1, 2, 4 vs the oracle over every block; FP32 vs the FP64
+    oracle; two apply sweeps vs the oracle; FGMRES with the asynchronous FP32 preconditioner (1
+    build sweep, 2 apply sweeps) converges, true residual confirmed by the oracle SpMV."""
+    c = W.case("tri300", cfl=cfl)
+    s64 = DS(c, "f64", restart=30)
+    for nsw in (1, 2, 4):
+        s64.factor(nsw, "sync")
+        X, D = s64.factor_host()
+        Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, nsw)
+        assert rel(X, Xo) <= 1e-12 and rel(D, Do) <= 1e-12, (nsw, rel(X, Xo), rel(D, Do))
+    r = np.random.default_rng(1).uniform(-1, 1, 4 * c.n)
+    rt = torch.from_numpy(r).cuda()
+    zt = torch.zeros_like(rt)
+    s64.apply(rt, zt, 2, "sync")
+    assert rel(zt.cpu().numpy(), oracle.apply_sync(c.n, c.rowptr, c.colidx, X, D, r, 2)) <= 1e-12
+    s32 = DS(c, "f32", restart=30)
+    s32.factor(2, "sync")
+    X32, D32 = s32.factor_host()
+    Xo, Do, tx, td = f32_tolerance(c, 2)
+    print(f"tri300 CFL {cfl:g}: f32 vs f64 oracle X {rel(X32, Xo):.2e} (tol {tx:.1e}) Dinv {rel(D32, Do):.2e} "
+          f"(tol {td:.1e})")
+    assert rel(X32, Xo) <= tx and rel(D32, Do) <= td
+    s32.factor(1, "async")
+    st, res = s32.solve(apply_sweeps=2, mode="async", rtol=1e-2, maxit=300)
+    x = s32.x.cpu().numpy()
+    true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
+    print(f"tri300 CFL {cfl:g}: async FP32 FGMRES iters {res['iters']}, true residual {true:.2e}")
+    assert st == 0 and res["converged"] and true <= 1e-2 and abs(true - res["rel_true_residual"]) <= 1e-10
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("order", ["line", "rcm"])
+def test_full_size_aniso1000(order):
+    """The 500,000-cell anisotropic workload (1000 x 500, aspect ratio 1000 at the wall) in line
+    and RCM order: FP32 and FP64 synchronous sweeps (1 and 2) against the FP64 oracle, the error
+    of each stated; FGMRES with the asynchronous FP32 preconditioner converges in both orders."""
+    c = W.case("aniso1000", order=order)
+    out = []
+    for nsw in (1, 2):
+        Xo, Do, tx, td = f32_tolerance(c, nsw)
+        _, _, tx64, td64 = f64_tolerance(c, nsw)
+        for prec in ("f64", "f32"):
+            s = DS(c, prec, restart=30)
+            s.factor(nsw, "sync")
+            X, D = s.factor_host()
+            ex, ed = rel(X, Xo), rel(D, Do)
+            out.append((nsw, prec, ex, ed, tx64 if prec == "f64" else tx, td64 if prec == "f64" else td))
+            if prec == "f64":
+                assert ex <= tx64 and ed <= td64, (nsw, ex, tx64, ed, td64)
+            else:
+                assert ex <= tx and ed <= td, (nsw, ex, tx, ed, td)
+            del s
+    print(f"aniso1000 {order}: (sweeps, precision, X error / tolerance, Dinv error / tolerance) vs the FP64 oracle:",
+          [(n, p, f"{a:.1e}/{ta:.1e}", f"{b:.1e}/{tb:.1e}") for n, p, a, b, ta, tb in out])
+    s = DS(c, "f32", restart=30)
+    s.factor(1, "async")
+    st, res = s.solve(apply_sweeps=3, mode="async", rtol=1e-2, maxit=300)
+    x = s.x.cpu().numpy()
+    true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
+    print(f"aniso1000 {order}: async FP32 FGMRES iters {res['iters']}, true residual {true:.2e}")
+    assert st == 0 and res["converged"] and true <= 1e-2
 
 
 # ------------------------------------------------------------------ single-worker schedule (P8)
