@@ -11,9 +11,10 @@
 // alone. The host reads one 128-byte status header per slot after each tick to move every
 // request to its next step, as fgmres_solve does after each iteration.
 //
-// Admission runs on a second stream: device generation of the system and pattern analysis into
-// the request's block, then the slot descriptor; the compute stream waits on an event before the
-// request's first tick.
+// Admission runs on a second stream while the device works through the tick: device generation
+// of the systems and their pattern analysis, each step one launch for the whole admitted batch
+// (member tables over per-request setup descriptors, the bodies of the single-request kernels),
+// then the slot descriptors; the compute stream waits on an event before a request's first tick.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
