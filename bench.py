@@ -32,12 +32,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources of the single-system kernels the measured traffic belongs to (the serving, setup and
+# generator sources do not enter them).
+KERNEL_SOURCES = ("abilu_internal.h", "kernels.h", "apply.hip", "factor.hip", "krylov.hip", "api.hip")
+
+
 def source_hash():
+    """Hash of the measured kernels' sources with comments and blank lines removed."""
+    import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1912_00539_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        text = open(os.path.join(d, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(f.encode() + b"\0" + text.encode())
     return h.hexdigest()[:16]
 
 
@@ -156,6 +166,7 @@ def serving_bench(args):
                   maxit=300, rtol=args.rtol)
     forms = {"batched_f32": L.serve_config(prec="f32", max_active=args.serve_slots, **common),
              "one_at_a_time_f64": L.serve_config(prec="f64", max_active=1, **common)}
+    forms = {k: v for k, v in forms.items() if k in args.serve_forms.split(",")}
     pool = torch.empty(int(args.serve_pool_gib * 2**30) // 256 * 256, dtype=torch.uint8, device="cuda")
     warm = W.serving_requests(8, seed=args.serve_seed + 1)
     for cfg in forms.values():
@@ -185,10 +196,12 @@ def serving_bench(args):
         return out
 
     sat = {name: run(name, None) for name in forms}
-    lam = 0.8 * sat["one_at_a_time_f64"]["solves_per_s"]
-    u = W.uniform01(args.serve_seed, 14, np.arange(len(reqs), dtype=np.int64))
-    arrivals = np.cumsum(-np.log1p(-u) / lam)
-    poisson = {name: run(name, arrivals) for name in forms}
+    poisson, lam = {}, None
+    if "one_at_a_time_f64" in sat and not args.serve_saturation_only:
+        lam = 0.8 * sat["one_at_a_time_f64"]["solves_per_s"]
+        u = W.uniform01(args.serve_seed, 14, np.arange(len(reqs), dtype=np.int64))
+        arrivals = np.cumsum(-np.log1p(-u) / lam)
+        poisson = {name: run(name, arrivals) for name in forms}
     cells = [L.abilu_gen_sizes(r)[0] for r in reqs]
     del pool
     torch.cuda.empty_cache()
@@ -199,8 +212,9 @@ def serving_bench(args):
         "preconditioner": f"ASYNC, {args.build_sweeps} factor sweep(s), {args.apply_sweeps} apply sweep pairs",
         "pool_GiB": args.serve_pool_gib, "slots": args.serve_slots,
         "saturation": sat,
-        "poisson": {"rate_per_s": round(lam, 2), **poisson},
-        "speedup_solves_per_s": round(sat["batched_f32"]["solves_per_s"] / sat["one_at_a_time_f64"]["solves_per_s"], 3),
+        "poisson": {"rate_per_s": round(lam, 2), **poisson} if lam else None,
+        "speedup_solves_per_s": (round(sat["batched_f32"]["solves_per_s"] / sat["one_at_a_time_f64"]["solves_per_s"], 3)
+                                 if len(sat) == 2 else None),
     }
 
 
@@ -226,6 +240,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-pool-gib", type=float, default=64.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-forms", default="batched_f32,one_at_a_time_f64")
+    ap.add_argument("--serve-saturation-only", action="store_true")
     ap.add_argument("--only-serving", action="store_true", help="print the serving object alone (profiling)")
     args = ap.parse_args()
 
