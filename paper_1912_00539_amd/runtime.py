@@ -30,6 +30,13 @@ class DeviceSystem:
         self.work = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self.x = torch.zeros(max(4 * self.n, 1), dtype=torch.float64, device=dev)
 
+    def load_values(self, vals, b=None):
+        """Replace A (and b) by new values on the same pattern (the next Jacobian of a sequence)."""
+        t = self.torch
+        self.A.copy_(t.from_numpy(np.ascontiguousarray(vals, np.float64).reshape(-1)))
+        if b is not None:
+            self.b.copy_(t.from_numpy(np.ascontiguousarray(b, np.float64)))
+
     def factor(self, nsweeps: int, mode: str = "sync", init: str = "A", stream=None):
         return L.abilu_factor(self.pattern, self.A, self.LU, self.Dinv, self.prec, nsweeps, mode, self.work,
                               init=init, stream=stream)

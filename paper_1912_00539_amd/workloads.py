@@ -42,7 +42,7 @@ _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 
 # random streams
-S_FACE_W, S_OFFDIAG, S_DIAGPERT, S_RHS, S_SPLIT, S_PERM = 1, 2, 3, 4, 5, 6
+S_FACE_W, S_OFFDIAG, S_DIAGPERT, S_RHS, S_SPLIT, S_PERM, S_DRIFT = 1, 2, 3, 4, 5, 6, 7
 
 BS = 4  # block size b = d + 2 for d = 2
 
@@ -382,3 +382,46 @@ def request_case(req: dict, order: str = "device") -> BSRCase:
         return assemble(m, o, req["seed"], "cfl", cfl=req["cfl"])
     m = aniso_quad_mesh(req["nx"], req["ny"])
     return assemble(m, line_order(m), req["seed"], "cfl", cfl=req["cfl"])
+
+
+# --------------------------------------------------------------------------- pseudo-time sequences
+def cfl_ramp(steps: int, cfl0: float = 10.0, growth: float = 1.5, cfl_max: float = 1000.0) -> np.ndarray:
+    """CFL_t = min(cfl0 * growth^t, cfl_max): the geometric ramp of a pseudo-transient continuation
+    (Section 2, local time stepping with a growing CFL number)."""
+    return np.minimum(cfl0 * growth ** np.arange(steps, dtype=np.float64), cfl_max)
+
+
+def jacobian_sequence(case: BSRCase, cfls, drift: float = 0.01, seed: int = 0):
+    """Jacobians of successive pseudo-time steps on `case`'s pattern (yields (vals, b) per step).
+
+    Step 0 is `case` with its diagonal shift recomputed for cfls[0]. Each later step multiplies
+    every off-diagonal entry by (1 + drift u), u ~ U(-1,1) drawn per (step, entry) (a slowly
+    changing flow state), and recomputes the diagonal blocks for the new neighbours and CFL:
+    A_ii(t) = A_ii(0) + (c_i(t) - c_i(0)) I with c_i = sum_j ||A_ij||_1 (1 + 1/CFL). The right-hand
+    side is b(0) (1 + drift u) per step. Values only; the pattern never changes.
+    """
+    n, z = case.n, case.nnzb
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(case.rowptr.astype(np.int64)))
+    diag = case.colidx.astype(np.int64) == rows
+    off = ~diag
+    vals = case.vals.copy()
+
+    def row_norms(v):
+        return np.bincount(rows[off], weights=_block_1norm(v[off]), minlength=n)
+
+    nrm0 = row_norms(vals)
+    cfl0 = float(case.meta.get("cfl", 100.0)) if case.meta.get("shift") == "cfl" else None
+    # c_i of the case as generated (constant shift s when the case was not CFL-shifted)
+    c0 = nrm0 * (1.0 + 1.0 / cfl0) if cfl0 else nrm0 + float(case.meta.get("s", 1.0))
+    eye = np.eye(4)
+    ent = np.arange(16, dtype=np.uint64)
+    for t, cfl in enumerate(cfls):
+        if t > 0:
+            idx = (np.uint64(t) * np.uint64(z) + np.arange(z, dtype=np.uint64))[:, None] * np.uint64(16) + ent[None, :]
+            u = uniform(seed, S_DRIFT, idx.ravel(), -1.0, 1.0).reshape(z, 4, 4)
+            vals[off] *= 1.0 + drift * u[off]
+        ct = row_norms(vals) * (1.0 + 1.0 / float(cfl))
+        vt = vals.copy()
+        vt[diag] = case.vals[diag] + (ct - c0)[:, None, None] * eye[None]
+        rb = uniform(seed, S_DRIFT, (np.uint64(t) << np.uint64(40)) + np.arange(4 * n, dtype=np.uint64), -1.0, 1.0)
+        yield vt, case.b * (1.0 + drift * rb)
