@@ -217,7 +217,8 @@ abilu_status abilu_stream_copy(void *d_dst, const void *d_src, size_t bytes, voi
  * enable = 0 stops. abilu_profile_report waits for the recorded events and writes a JSON object
  * {"kernel": [launches, total_ms, algorithmic_bytes], ...} into buf (NUL-terminated, truncated
  * to len). Algorithmic bytes count every array element a launch must read or write once
- * (gathered blocks and vector entries once, as with perfect cache reuse). */
+ * (gathered blocks and vector entries once, as with perfect cache reuse). The recording state
+ * is process-wide and not thread-safe: enable, launch and report from one host thread. */
 abilu_status abilu_profile_enable(int32_t enable, int32_t max_launches);
 abilu_status abilu_profile_report(char *buf, size_t len);
 
