@@ -167,7 +167,8 @@ def serving_bench(args):
     common = dict(mode="async", factor_sweeps=args.build_sweeps, apply_sweeps=args.apply_sweeps, restart=30,
                   maxit=300, rtol=args.rtol)
     forms = {"batched_f32": L.serve_config(prec="f32", max_active=args.serve_slots, **common),
-             "one_at_a_time_f64": L.serve_config(prec="f64", max_active=1, **common)}
+             "one_at_a_time_f64": L.serve_config(prec="f64", max_active=1, **common),
+             "one_at_a_time_f32": L.serve_config(prec="f32", max_active=1, **common)}
     forms = {k: v for k, v in forms.items() if k in args.serve_forms.split(",")}
     pool = torch.empty(int(args.serve_pool_gib * 2**30) // 256 * 256, dtype=torch.uint8, device="cuda")
     warm = W.serving_requests(8, seed=args.serve_seed + 1)
@@ -203,7 +204,7 @@ def serving_bench(args):
         lam = 0.8 * sat["one_at_a_time_f64"]["solves_per_s"]
         u = W.uniform01(args.serve_seed, 14, np.arange(len(reqs), dtype=np.int64))
         arrivals = np.cumsum(-np.log1p(-u) / lam)
-        poisson = {name: run(name, arrivals) for name in forms}
+        poisson = {name: run(name, arrivals) for name in forms if name != "one_at_a_time_f32"}
     cells = [L.abilu_gen_sizes(r)[0] for r in reqs]
     del pool
     torch.cuda.empty_cache()
@@ -216,7 +217,9 @@ def serving_bench(args):
         "saturation": sat,
         "poisson": {"rate_per_s": round(lam, 2), **poisson} if lam else None,
         "speedup_solves_per_s": (round(sat["batched_f32"]["solves_per_s"] / sat["one_at_a_time_f64"]["solves_per_s"], 3)
-                                 if len(sat) == 2 else None),
+                                 if "batched_f32" in sat and "one_at_a_time_f64" in sat else None),
+        "speedup_from_batching_f32": (round(sat["batched_f32"]["solves_per_s"] / sat["one_at_a_time_f32"]["solves_per_s"], 3)
+                                      if "batched_f32" in sat and "one_at_a_time_f32" in sat else None),
     }
 
 
@@ -284,7 +287,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-pool-gib", type=float, default=64.0)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-forms", default="batched_f32,one_at_a_time_f64")
+    ap.add_argument("--serve-forms", default="batched_f32,one_at_a_time_f64,one_at_a_time_f32")
     ap.add_argument("--serve-saturation-only", action="store_true")
     ap.add_argument("--warm-steps", type=int, default=12)
     ap.add_argument("--no-warm-start", action="store_true")
