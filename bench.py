@@ -13,7 +13,8 @@ profiled run; the wall time is that of the same steps run again without the per-
 
 The "serving" object measures the continuous-batching server on a stream of independent solves
 (FP32 preconditioner, batched launches) against one-solve-at-a-time FP64 on the same stream:
-solves/s at saturation and p50/p99 latency under Poisson arrivals.
+solves/s at saturation and p50/p99 latency under Poisson arrivals. The "precision" object runs the
+same step with the preconditioner in FP64, and gives the distance between the FP32 and FP64 factors.
 Prints one JSON line.
 """
 import argparse
@@ -272,6 +273,52 @@ def warm_start_bench(args):
             "totals": tot, "steps": rows}
 
 
+def precision_bench(case, args):
+    """The precision boundary on the headline workload: the same step with the preconditioner in
+    FP64 (factor storage and sweep arithmetic) beside FP32, the Krylov solver being FP64 in both; and
+    the distance between the FP32 and FP64 factors after two synchronous sweeps."""
+    import torch
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    steps = {}
+    for prec in ("f32", "f64"):
+        s = DeviceSystem(case, prec=prec, restart=args.restart)
+        run_steps(s, args, args.mode, 1, profile=False)
+        nst = 3
+        secs, res, rep = run_steps(s, args, args.mode, nst, profile=True)
+        secs_np, res_np, _ = run_steps(s, args, args.mode, nst, profile=False)
+        same = [r["iters"] for _, r in res_np] == [r["iters"] for _, r in res]
+        t = secs_np if same else secs
+        by = sum(v[2] for k, v in rep.items() if not k.startswith("_"))
+        pre = {k: v for k, v in rep.items() if k.startswith(("factor_", "apply_"))}
+        steps[prec] = {"ms_per_step": round(t * 1e3 / nst, 3), "GBps": round(by / t / 1e9, 1),
+                       "preconditioner_bytes_per_step": round(sum(v[2] for v in pre.values()) / nst),
+                       "preconditioner_ms_per_step": round(sum(v[1] for v in pre.values()) / nst, 3),
+                       "fgmres_iters": [r["iters"] for _, r in res],
+                       "max_rel_true_residual": max(r["rel_true_residual"] for _, r in res),
+                       "ilu_residual": float(f"{s.ilu_residual():.4e}")}
+        s.factor(2, "sync")
+        torch.cuda.synchronize()
+        steps[prec]["_sys"] = s
+        log(f"precision {prec}: {steps[prec]['ms_per_step']} ms/step, iters {steps[prec]['fgmres_iters']}")
+    s32, s64 = steps["f32"].pop("_sys"), steps["f64"].pop("_sys")
+
+    def rel(a32, a64):
+        d = a32.double() - a64
+        return {"frobenius": float(f"{(d.norm() / a64.norm()).item():.3e}"),
+                "max_abs_over_max": float(f"{(d.abs().max() / a64.abs().max()).item():.3e}")}
+    dist = {"LU": rel(s32.LU, s64.LU), "Dinv": rel(s32.Dinv, s64.Dinv),
+            "ilu_residual_f32": float(f"{s32.ilu_residual():.4e}"),
+            "ilu_residual_f64": float(f"{s64.ilu_residual():.4e}")}
+    del s32, s64
+    torch.cuda.empty_cache()
+    f32, f64 = steps["f32"], steps["f64"]
+    return {"mode": args.mode, "build_sweeps": args.build_sweeps, "apply_sweeps": args.apply_sweeps,
+            "steps": steps,
+            "f32_speedup_step": round(f64["ms_per_step"] / f32["ms_per_step"], 3),
+            "f32_speedup_preconditioner": round(f64["preconditioner_ms_per_step"] / f32["preconditioner_ms_per_step"], 3),
+            "factor_distance_after_2_sync_sweeps": dist}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +345,7 @@ def main():
     ap.add_argument("--serve-saturation-only", action="store_true")
     ap.add_argument("--warm-steps", type=int, default=12)
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--only-serving", action="store_true", help="print the serving object alone (profiling)")
     args = ap.parse_args()
 
@@ -420,6 +468,7 @@ def main():
     }
     del sysm
     torch.cuda.empty_cache()
+    out["precision"] = None if args.no_precision else precision_bench(case, args)
     out["serving"] = None if args.no_serving else serving_bench(args)
     out["warm_start"] = None if args.no_warm_start else warm_start_bench(args)
     if not args.no_cpu_baseline:
