@@ -46,6 +46,10 @@ def _lib():
         for name in ("oracle_factor_sync", "oracle_factor_gs"):
             getattr(L, name).argtypes = [C.c_int, i32p, i32p, f64p, vp, C.c_int, f64p, f64p]
             getattr(L, name).restype = C.c_uint
+        L.oracle_factor_chunked.argtypes = [C.c_int, i32p, i32p, f64p, vp, C.c_int, C.c_int, C.c_int, f64p, f64p]
+        L.oracle_factor_chunked.restype = C.c_uint
+        L.oracle_apply_chunked.argtypes = [C.c_int, i32p, i32p, f64p, f64p, f64p, f64p, C.c_int, C.c_int, C.c_int]
+        L.oracle_apply_chunked.restype = None
         L.oracle_apply_sync.argtypes = [C.c_int, i32p, i32p, f64p, f64p, f64p, f64p, C.c_int]
         L.oracle_apply_sync.restype = None
         L.oracle_trisolve_exact.argtypes = [C.c_int, i32p, i32p, f64p, f64p, f64p, f64p]
@@ -156,6 +160,28 @@ def factor_sync(n, rowptr, colidx, A, nsw, X0=None):
 def factor_gs(n, rowptr, colidx, A, nsw, X0=None):
     """nsw in-place row-major sweeps (one worker): (X, Dinv, flags)."""
     return _factor(_lib().oracle_factor_gs, n, rowptr, colidx, A, nsw, X0)
+
+
+def factor_chunked(n, rowptr, colidx, A, nsw, R, X0=None, descending=False):
+    """nsw chunked sweeps (chunks of R rows, Gauss-Seidel within a chunk, other chunks read from
+    the previous sweep) from X0 (default A): (X, Dinv, flags)."""
+    rp, ci = _pat(rowptr, colidx); z = int(rp[n]) if n else 0
+    X, D = _out(n, z)
+    Af = _c(A, np.float64).reshape(-1) if z else np.zeros(16)
+    x0 = None
+    if X0 is not None:
+        X0 = _c(X0, np.float64).reshape(-1)
+        x0 = X0.ctypes.data_as(C.c_void_p)
+    f = _lib().oracle_factor_chunked(n, rp, ci, Af, x0, int(nsw), int(R), int(bool(descending)), X, D)
+    return (*_shape(X, D, n, z), int(f))
+
+
+def apply_chunked(n, rowptr, colidx, X, Dinv, r, nsw, R, descending=False):
+    rp, ci = _pat(rowptr, colidx)
+    z = np.zeros(max(4 * n, 1))
+    _lib().oracle_apply_chunked(n, rp, ci, _c(X, np.float64).reshape(-1), _c(Dinv, np.float64).reshape(-1),
+                                _c(r, np.float64), z, int(nsw), int(R), int(bool(descending)))
+    return z[: 4 * n]
 
 
 def apply_sync(n, rowptr, colidx, X, Dinv, r, nsw):

@@ -335,6 +335,64 @@ unsigned oracle_factor_gs(int n, const int *rowptr, const int *colidx, const dou
     return flags;
 }
 
+/*
+ * Chunked sweeps (Section 4.3: each OpenMP chunk of consecutive rows is run by one thread in the
+ * row-major order, so within a chunk the blocks are computed in a Gaussian-elimination ordering
+ * with respect to the chunk's own blocks). The row loop is cut into chunks of R consecutive block
+ * rows; a chunk's rows are processed in ascending order and every block of the chunk sees the
+ * values its chunk has already produced in this sweep (its own row's L_ik, the U_kj and U_jj^{-1}
+ * of earlier rows of the chunk).
+ * Deterministic reading of the reads across chunks: every chunk reads the blocks and diagonal
+ * inverses of other chunks from the iterate at the start of the sweep, as if all chunks ran at
+ * once. `descending` runs the chunks in the reverse order, which must not change the result.
+ * Starts from X0 (NULL: A) with Dinv = inverses of X0's diagonal blocks.
+ */
+unsigned oracle_factor_chunked(int n, const int *rowptr, const int *colidx, const double *A,
+                               const double *X0, int nsw, int R, int descending, double *X,
+                               double *Dinv) {
+    long Z = rowptr[n];
+    int nch = (n + R - 1) / R;
+    double *Xo = (double *)malloc(sizeof(double) * (Z * BB + 1));
+    double *Do = (double *)malloc(sizeof(double) * ((long)n * BB + 1));
+    unsigned flags = 0;
+    memcpy(X, X0 ? X0 : A, sizeof(double) * Z * BB);
+    for (int j = 0; j < n; ++j)
+        flags |= oracle_inv4(X + find_block(rowptr, colidx, j, j) * BB, Dinv + (long)j * BB);
+    for (int p = 0; p < nsw; ++p) {
+        memcpy(Xo, X, sizeof(double) * Z * BB);
+        memcpy(Do, Dinv, sizeof(double) * (long)n * BB);
+        for (int q = 0; q < nch; ++q) {
+            int c = descending ? nch - 1 - q : q;
+            int c0 = c * R, c1 = c0 + R < n ? c0 + R : n;
+            for (int i = c0; i < c1; ++i)
+                for (long e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                    int j = colidx[e];
+                    int lim = i < j ? i : j;
+                    double T[BB];
+                    memcpy(T, A + e * BB, sizeof T);
+                    for (long f = rowptr[i]; f < rowptr[i + 1]; ++f) {
+                        int k = colidx[f];
+                        if (k >= lim) continue;
+                        long g = find_block(rowptr, colidx, k, j);
+                        if (g < 0) continue;
+                        /* L_ik belongs to row i (this chunk); U_kj to row k */
+                        mat_sub_mul(T, X + f * BB, (k >= c0 ? X : Xo) + g * BB);
+                    }
+                    if (i > j) {
+                        mat_mul(X + e * BB, T, (j >= c0 ? Dinv : Do) + (long)j * BB);
+                    } else {
+                        memcpy(X + e * BB, T, sizeof T);
+                        if (i == j) flags |= oracle_inv4(T, Dinv + (long)i * BB);
+                    }
+                }
+        }
+    }
+    flags |= nonfinite_flag(Z * BB, X);
+    free(Xo);
+    free(Do);
+    return flags;
+}
+
 /* ------------------------------------------------------------------ triangular solves */
 
 /* y_i (4-vector) -= B_e * x_j */
@@ -391,6 +449,58 @@ void oracle_apply_sync(int n, const int *rowptr, const int *colidx, const double
         memcpy(zo, z, sizeof(double) * nv);
     }
     free(yo); free(yn); free(zo);
+}
+
+/*
+ * Chunked preconditioner application: the sweeps of oracle_apply_sync with the rows cut into
+ * chunks of R consecutive rows, each chunk run in order by one worker (Section 4.3 chunks), so
+ * that within a chunk the forward sweep is a forward substitution (ascending rows) and the
+ * backward sweep a backward substitution (descending rows); entries of other chunks are read from
+ * the previous sweep's vector (y^0 = z^0 = 0). nsw sweeps each; nsw == 0 means z = r.
+ */
+void oracle_apply_chunked(int n, const int *rowptr, const int *colidx, const double *X,
+                          const double *Dinv, const double *r, double *z, int nsw, int R,
+                          int descending) {
+    long nv = (long)n * BS;
+    int nch = (n + R - 1) / R;
+    if (nsw <= 0) { memcpy(z, r, sizeof(double) * nv); return; }
+    double *y = (double *)calloc(nv + 1, sizeof(double));
+    double *yo = (double *)calloc(nv + 1, sizeof(double));
+    double *zo = (double *)calloc(nv + 1, sizeof(double));
+    for (int s = 0; s < nsw; ++s) {
+        memcpy(yo, y, sizeof(double) * nv);
+        for (int q = 0; q < nch; ++q) {
+            int c = descending ? nch - 1 - q : q;
+            int c0 = c * R, c1 = c0 + R < n ? c0 + R : n;
+            for (int i = c0; i < c1; ++i) {
+                double acc[BS];
+                memcpy(acc, r + (long)i * BS, sizeof acc);
+                for (long e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                    int j = colidx[e];
+                    if (j < i) block_matvec_sub(acc, X + e * BB, (j >= c0 ? y : yo) + (long)j * BS);
+                }
+                memcpy(y + (long)i * BS, acc, sizeof acc);
+            }
+        }
+    }
+    memset(z, 0, sizeof(double) * nv);
+    for (int s = 0; s < nsw; ++s) {
+        memcpy(zo, z, sizeof(double) * nv);
+        for (int q = 0; q < nch; ++q) {
+            int c = descending ? nch - 1 - q : q;
+            int c0 = c * R, c1 = c0 + R < n ? c0 + R : n;
+            for (int i = c1 - 1; i >= c0; --i) {
+                double acc[BS];
+                memcpy(acc, y + (long)i * BS, sizeof acc);
+                for (long e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                    int j = colidx[e];
+                    if (j > i) block_matvec_sub(acc, X + e * BB, (j < c1 ? z : zo) + (long)j * BS);
+                }
+                block_matvec(z + (long)i * BS, Dinv + (long)i * BB, acc);
+            }
+        }
+    }
+    free(y); free(yo); free(zo);
 }
 
 /*

@@ -503,3 +503,84 @@ def test_fixed_point_residual_dense(name, c):
         total += np.abs(X[e] - h).sum()
     got = oracle.fixed_point_residual(c.n, c.rowptr, c.colidx, c.vals, X)
     assert abs(got - total) <= 1e-10 * total, (got, total)
+
+
+# ------------------------------------------------------------------ chunked (Gauss-Seidel within a chunk) sweeps
+@pytest.mark.parametrize("name,c", small_cases())
+def test_chunked_single_chunk_is_sequential(name, c):
+    """Section 4.3: a chunk is run in row-major order by one worker. With one chunk covering
+    every row, one factor sweep from A is the sequential block ILU(0) (Theorem 7 ordering) and one
+    apply sweep pair is the exact forward and backward substitution (Algorithm 1)."""
+    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    for R in (c.n, c.n + 5):
+        X, D, _ = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, 1, R)
+        assert rel(X, Xs) < 1e-15 and rel(D, Ds) < 1e-15
+    L, U = factors_dense(c.n, c.rowptr, c.colidx, Xs)
+    exact = np.linalg.solve(L @ U, c.b)
+    z = oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xs, Ds, c.b, 1, c.n)
+    assert rel(z, exact) < 1e-12
+
+
+def _chunk_rel(X, Xs, rowptr, rows):
+    """Relative error over the blocks of the given rows."""
+    e = np.concatenate([np.arange(rowptr[i], rowptr[i + 1]) for i in rows])
+    return rel(X[e], Xs[e])
+
+
+@pytest.mark.parametrize("mesh,R", [("nine", 5), ("chain", 2), ("random", 4)])
+def test_chunked_exact_one_chunk_per_sweep(mesh, R):
+    """Section 4.3: once the chunks before chunk p have their final values, chunk p gets its
+    final values in the next sweep, so the iteration is exact after as many sweeps as there are
+    chunks. Checked chunk by chunk: after s sweeps chunks 0..s-1 equal the sequential ILU(0), and
+    on the chain and the natural-order grid, where each chunk depends on the one before it, chunk s
+    does not yet (weakly dominant values keep the error visible)."""
+    m = {"nine": W.nine_point_mesh(5, 4), "chain": W.chain_mesh(8), "random": W.random_graph_mesh(16, 4.0, 3)}[mesh]
+    c = weak_case(m, seed=7, diag=2.5)
+    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    nch = (c.n + R - 1) // R
+    for s in range(1, nch + 1):
+        X, D, _ = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, s, R)
+        done = range(0, min(s * R, c.n))
+        assert _chunk_rel(X, Xs, c.rowptr, done) < 1e-14, s
+        assert rel(D[: min(s * R, c.n)], Ds[: min(s * R, c.n)]) < 1e-14
+        if s < nch and mesh != "random":   # the bound is tight where every chunk feeds the next
+            nxt = range(s * R, min((s + 1) * R, c.n))
+            assert _chunk_rel(X, Xs, c.rowptr, nxt) > 1e-8, s
+    assert rel(X, Xs) < 1e-14
+    # the apply: exact after nch sweeps, not after nch - 1 (chain: each chunk feeds the next)
+    exact = oracle.trisolve_exact(c.n, c.rowptr, c.colidx, Xs, Ds, c.b)
+    assert rel(oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xs, Ds, c.b, nch, R), exact) < 1e-13
+    if mesh == "chain":
+        assert rel(oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xs, Ds, c.b, nch - 1, R), exact) > 1e-8
+
+
+@pytest.mark.parametrize("name,c", small_cases())
+def test_chunked_reads_other_chunks_from_previous_sweep(name, c):
+    """The deterministic reading: every chunk reads other chunks from the iterate at the start of
+    the sweep, so the order in which chunks run cannot change the result."""
+    for R in (1, 3, 7):
+        a = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, 2, R)
+        b = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, 2, R, descending=True)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        za = oracle.apply_chunked(c.n, c.rowptr, c.colidx, a[0], a[1], c.b, 2, R)
+        zb = oracle.apply_chunked(c.n, c.rowptr, c.colidx, a[0], a[1], c.b, 2, R, descending=True)
+        np.testing.assert_array_equal(za, zb)
+
+
+@pytest.mark.parametrize("name,c", small_cases())
+def test_apply_chunked_single_rows_is_jacobi(name, c):
+    """With one row per chunk no row reads a value of its own chunk, so the chunked apply is the
+    Jacobi sweep apply (Algorithm 5), pinned by its closed forms."""
+    X, Dv, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 2)
+    for nsw in (1, 2, 3):
+        np.testing.assert_array_equal(oracle.apply_chunked(c.n, c.rowptr, c.colidx, X, Dv, c.b, nsw, 1),
+                                      oracle.apply_sync(c.n, c.rowptr, c.colidx, X, Dv, c.b, nsw))
+
+
+def test_chunked_fixed_point_is_stationary():
+    """Theorem 7: the sequential ILU(0) is a fixed point of the chunked sweep too."""
+    c = W.case("nine", seed=2, nx=5, ny=5)
+    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    X, D, _ = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, 1, 4, X0=Xs)
+    assert rel(X, Xs) < 1e-15 and rel(D, Ds) < 1e-15
