@@ -15,6 +15,8 @@ The "serving" object measures the continuous-batching server on a stream of inde
 (FP32 preconditioner, batched launches) against one-solve-at-a-time FP64 on the same stream:
 solves/s at saturation and p50/p99 latency under Poisson arrivals. The "precision" object runs the
 same step with the preconditioner in FP64, and gives the distance between the FP32 and FP64 factors.
+The "chunked" object compares the chunked (Gauss-Seidel within chunks) sweeps with the unchunked
+asynchronous ones on the same step, and on the line-ordered anisotropic mesh.
 Prints one JSON line.
 """
 import argparse
@@ -319,6 +321,50 @@ def precision_bench(case, args):
             "factor_distance_after_2_sync_sweeps": dist}
 
 
+def chunked_bench(args):
+    """Chunked sweeps (Gauss-Seidel within chunks of consecutive rows, the schedule of the paper's
+    OpenMP chunks) against the unchunked asynchronous sweeps, same step otherwise (FP32
+    preconditioner, 1 build sweep, 3 apply sweep pairs, FGMRES to rtol), on the headline 4M-cell
+    triangles (64-row chunks) and on the 500,000-cell anisotropic quads in line order, where each
+    chunk is a run of one wall-normal line (16-row chunks)."""
+    import torch
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    out = {}
+    for label, name, kw, R, restart in (("tri2000", args.workload, {}, 64, args.restart),
+                                        ("aniso1000_line", "aniso1000", {"order": "line"}, 16, 30)):
+        c = W.case(name, **kw)
+        s = DeviceSystem(c, prec=args.prec, restart=restart)
+        rows = {}
+        for mode in ("async", "chunk_async"):
+            info = s.set_chunks(R) if mode == "chunk_async" else None
+            run_steps(s, args, mode, 1, profile=False)
+            nst = 5
+            secs, res, rep = run_steps(s, args, mode, nst, profile=True)
+            secs_np, res_np, _ = run_steps(s, args, mode, nst, profile=False)
+            same = [r["iters"] for _, r in res_np] == [r["iters"] for _, r in res]
+            t = secs_np if same else secs
+            by = sum(v[2] for k, v in rep.items() if not k.startswith("_"))
+            fs = {k: v for k, v in rep.items() if k.startswith("factor_sweep")}
+            ap = {k: v for k, v in rep.items() if k.startswith("apply_")}
+            rows[mode] = {"ms_per_step": round(t * 1e3 / nst, 3), "GBps": round(by / t / 1e9, 1),
+                          "fgmres_iters": [r["iters"] for _, r in res],
+                          "max_rel_true_residual": max(r["rel_true_residual"] for _, r in res),
+                          "ilu_residual": float(f"{s.ilu_residual():.4e}"),
+                          "factor_sweep_ms": round(sum(v[1] for v in fs.values()) / max(1, sum(v[0] for v in fs.values())), 4),
+                          "factor_sweep_GBps": round(sum(v[2] for v in fs.values()) / (sum(v[1] for v in fs.values()) / 1e3) / 1e9, 1),
+                          "apply_GBps": round(sum(v[2] for v in ap.values()) / (sum(v[1] for v in ap.values()) / 1e3) / 1e9, 1)}
+            if info:
+                rows[mode]["chunks"] = {k: info[k] for k in ("rows_per_chunk", "nchunks", "runner", "max_levels_lower",
+                                                             "levels_lower")}
+            log(f"chunked {label} {mode}: {rows[mode]}")
+        rows["chunk_over_async_step_time"] = round(rows["chunk_async"]["ms_per_step"] / rows["async"]["ms_per_step"], 3)
+        out[label] = {"n": c.n, "nnzb": c.nnzb, **rows}
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +392,8 @@ def main():
     ap.add_argument("--warm-steps", type=int, default=12)
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-chunked", action="store_true")
+    ap.add_argument("--only-chunked", action="store_true", help="print the chunked object alone")
     ap.add_argument("--only-serving", action="store_true", help="print the serving object alone (profiling)")
     args = ap.parse_args()
 
@@ -364,6 +412,9 @@ def main():
     L.lib()
     if args.only_serving:
         print(json.dumps({"serving": serving_bench(args)}), flush=True)
+        return
+    if args.only_chunked:
+        print(json.dumps({"chunked": chunked_bench(args)}), flush=True)
         return
     t = time.perf_counter()
     case = W.case(args.workload)
@@ -469,6 +520,7 @@ def main():
     del sysm
     torch.cuda.empty_cache()
     out["precision"] = None if args.no_precision else precision_bench(case, args)
+    out["chunked"] = None if args.no_chunked else chunked_bench(args)
     out["serving"] = None if args.no_serving else serving_bench(args)
     out["warm_start"] = None if args.no_warm_start else warm_start_bench(args)
     if not args.no_cpu_baseline:

@@ -58,8 +58,26 @@ typedef enum {
  * the asynchronous iteration on one thread with the sequential algorithm (Sections 3.3, 4.2): a
  * factor sweep is then a Gauss-Seidel sweep (from X0 = A, one sweep gives the exact ILU(0)), a
  * forward apply sweep is forward substitution and a backward sweep (rows in descending order)
- * back substitution. It occupies one compute unit lane group: for verification, not speed. */
-typedef enum { ABILU_SYNC = 0, ABILU_ASYNC = 1, ABILU_ASYNC_SERIAL = 2 } abilu_mode;
+ * back substitution. It occupies one compute unit lane group: for verification, not speed.
+ *
+ * ABILU_CHUNK_SYNC, ABILU_CHUNK_ASYNC: the schedule of the paper's implementation (Section 4.3),
+ * where the row loop is cut into chunks of consecutive rows and a worker runs a whole chunk in
+ * row-major order, so that inside a chunk the factor sweep is a Gauss-Seidel sweep (each block
+ * sees the values its chunk has already computed in the sweep), the forward apply sweep a forward
+ * substitution and the backward apply sweep (rows descending) a backward substitution. One
+ * workgroup runs one chunk, its rows grouped by dependence level with a barrier between levels,
+ * which gives exactly the values of the row-major order. Needs the pattern's chunk schedule
+ * (abilu_pattern_set_chunks). The iteration is exact after as many sweeps as there are chunks.
+ *   ABILU_CHUNK_SYNC : rows of other chunks are read from the previous sweep (deterministic).
+ *   ABILU_CHUNK_ASYNC: in place; rows of other chunks are read as they are in memory.
+ * Every apply sweep is launched (no closed-form first sweep). Not accepted by the server. */
+typedef enum {
+    ABILU_SYNC = 0,
+    ABILU_ASYNC = 1,
+    ABILU_ASYNC_SERIAL = 2,
+    ABILU_CHUNK_SYNC = 3,
+    ABILU_CHUNK_ASYNC = 4
+} abilu_mode;
 typedef enum { ABILU_F64 = 0, ABILU_F32 = 1 } abilu_prec;
 typedef enum { ABILU_INIT_FROM_A = 0, ABILU_INIT_FROM_LU = 1 } abilu_init;
 
@@ -96,6 +114,50 @@ abilu_status abilu_pattern_info(const abilu_pattern *p, int32_t *nbrows, int64_t
  * d_pair_ptr int32[Z+1], d_pik int32[npairs], d_pkj int32[npairs]. Any pointer may be NULL. */
 abilu_status abilu_pattern_export(const abilu_pattern *p, int32_t *d_diag_pos, int32_t *d_pair_ptr,
                                   int32_t *d_pik, int32_t *d_pkj, void *stream);
+
+/*
+ * Build the chunk schedule used by the ABILU_CHUNK_* modes (the chunks of Section 4.3): block rows
+ * are cut into chunks of rows_per_chunk consecutive rows (the last one may be shorter). For each
+ * chunk the rows are grouped by level in the chunk's lower dependence graph (level 1: no strictly
+ * lower neighbour inside the chunk; otherwise one more than the largest level of its strictly
+ * lower neighbours inside the chunk), ascending row within a level; likewise by the strictly upper
+ * neighbours for the backward apply sweep. Replaces a previous schedule; the pattern owns the
+ * device memory (released by abilu_pattern_destroy). No work that uses the pattern may be in
+ * flight.
+ *   rows_per_chunk  1 .. 4096
+ *   runner          abilu_chunk_runner (below)
+ * Blocks on `stream`. Errors: ABILU_EINVAL (null pattern, rows_per_chunk or runner out of range),
+ * ABILU_ENOMEM, ABILU_EDEVICE (the pattern is then left with no schedule).
+ */
+abilu_status abilu_pattern_set_chunks(abilu_pattern *p, int32_t rows_per_chunk, int32_t runner,
+                                      void *stream);
+
+/* How the chunked sweeps run a chunk (both give the same values):
+ *   ABILU_CHUNK_BY_LEVELS: one workgroup per chunk, the rows of each dependence level in
+ *                          parallel (one quad per row), a workgroup barrier between levels;
+ *   ABILU_CHUNK_BY_ROWS  : one quad per chunk, the chunk's rows in order, no barrier (the
+ *                          worker-per-chunk form; fits chunks whose rows form chains);
+ *   ABILU_CHUNK_AUTO     : BY_ROWS when the chunks average fewer than 4 rows per level, else
+ *                          BY_LEVELS. */
+typedef enum { ABILU_CHUNK_AUTO = 0, ABILU_CHUNK_BY_LEVELS = 1, ABILU_CHUNK_BY_ROWS = 2 } abilu_chunk_runner;
+
+/* Chunk schedule sizes: rows per chunk (0: none built), number of chunks, the runner in use
+ * (ABILU_CHUNK_BY_LEVELS or ABILU_CHUNK_BY_ROWS), the largest number of levels in one chunk (lower
+ * graph, upper graph) and the number of levels summed over the chunks. Any output pointer may be
+ * NULL. */
+abilu_status abilu_pattern_chunk_info(const abilu_pattern *p, int32_t *rows_per_chunk, int32_t *nchunks,
+                                      int32_t *runner, int32_t *max_levels_lower, int32_t *max_levels_upper,
+                                      int64_t *levels_lower, int64_t *levels_upper);
+
+/* Copy one chunk schedule (upper = 0: lower graph, used by the factor and forward sweeps;
+ * upper = 1: upper graph, backward sweeps) to caller device buffers, for verification:
+ *   d_order    int32[N]            rows of each chunk grouped by level
+ *   d_lvptr    int32[nchunks+1]    chunk c owns entries [d_lvptr[c], d_lvptr[c+1]) of d_lvstart
+ *   d_lvstart  int32[levels+nchunks]  start of each level of the chunk in d_order, then the
+ *                                      chunk's end
+ * Any pointer may be NULL. ABILU_EINVAL when no schedule is built. Non-blocking. */
+abilu_status abilu_pattern_chunk_export(const abilu_pattern *p, int32_t upper, int32_t *d_order,
+                                        int32_t *d_lvptr, int32_t *d_lvstart, void *stream);
 
 /* Workspace bytes needed by abilu_factor, abilu_apply, abilu_ilu_residual and, when
  * fgmres_restart > 0, fgmres_solve with that restart length. */

@@ -15,14 +15,17 @@ LIB_PATH = os.path.join(HERE, "lib", "libabilu.so")
 
 ABILU_OK, ABILU_WARN_MODIFIED, ABILU_WARN_NOCONV = 0, 1, 2
 ABILU_EINVAL, ABILU_EPATTERN, ABILU_ENOMEM, ABILU_EDEVICE, ABILU_ENONFINITE = -1, -2, -3, -4, -5
-ABILU_SYNC, ABILU_ASYNC, ABILU_ASYNC_SERIAL = 0, 1, 2
+ABILU_SYNC, ABILU_ASYNC, ABILU_ASYNC_SERIAL, ABILU_CHUNK_SYNC, ABILU_CHUNK_ASYNC = 0, 1, 2, 3, 4
 ABILU_F64, ABILU_F32 = 0, 1
 ABILU_INIT_FROM_A, ABILU_INIT_FROM_LU = 0, 1
 ABILU_FLAG_MODIFIED, ABILU_FLAG_NONFINITE = 1, 2
 ABILU_FGMRES_ZERO_GUESS = 1
 
-MODES = {"sync": ABILU_SYNC, "async": ABILU_ASYNC, "serial": ABILU_ASYNC_SERIAL}
+MODES = {"sync": ABILU_SYNC, "async": ABILU_ASYNC, "serial": ABILU_ASYNC_SERIAL, "chunk_sync": ABILU_CHUNK_SYNC,
+         "chunk_async": ABILU_CHUNK_ASYNC}
 PRECS = {"f64": ABILU_F64, "f32": ABILU_F32}
+ABILU_CHUNK_AUTO, ABILU_CHUNK_BY_LEVELS, ABILU_CHUNK_BY_ROWS = 0, 1, 2
+CHUNK_RUNNERS = {"auto": ABILU_CHUNK_AUTO, "levels": ABILU_CHUNK_BY_LEVELS, "rows": ABILU_CHUNK_BY_ROWS}
 INITS = {"A": ABILU_INIT_FROM_A, "LU": ABILU_INIT_FROM_LU}
 
 
@@ -110,6 +113,10 @@ def lib():
             "abilu_pattern_destroy": ([vp], st),
             "abilu_pattern_info": ([vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)], st),
             "abilu_pattern_export": ([vp, vp, vp, vp, vp, vp], st),
+            "abilu_pattern_set_chunks": ([vp, i32, i32, vp], st),
+            "abilu_pattern_chunk_info": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                          C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)], st),
+            "abilu_pattern_chunk_export": ([vp, i32, vp, vp, vp, vp], st),
             "abilu_workspace_bytes": ([vp, st, i32], sz),
             "abilu_factor": ([vp, vp, vp, vp, st, i32, st, st, vp, sz, vp], st),
             "abilu_apply": ([vp, vp, vp, st, vp, vp, i32, st, vp, sz, vp], st),
@@ -209,6 +216,26 @@ def abilu_build_pattern(nbrows: int, rowptr, colidx, bs: int = 4, stream=None) -
 def abilu_pattern_export(p: Pattern, diag_pos=None, pair_ptr=None, pik=None, pkj=None, stream=None):
     _check(lib().abilu_pattern_export(p.handle, _ptr(diag_pos), _ptr(pair_ptr), _ptr(pik), _ptr(pkj),
                                       _stream(stream)), "abilu_pattern_export")
+
+
+def abilu_pattern_set_chunks(p: Pattern, rows_per_chunk: int, runner: str = "auto", stream=None):
+    _check(lib().abilu_pattern_set_chunks(p.handle, int(rows_per_chunk), CHUNK_RUNNERS[runner], _stream(stream)),
+           "abilu_pattern_set_chunks")
+
+
+def abilu_pattern_chunk_info(p: Pattern) -> dict:
+    v = [C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()]
+    _check(lib().abilu_pattern_chunk_info(p.handle, *[C.byref(x) for x in v]), "abilu_pattern_chunk_info")
+    keys = ("rows_per_chunk", "nchunks", "runner", "max_levels_lower", "max_levels_upper", "levels_lower",
+            "levels_upper")
+    out = {k: x.value for k, x in zip(keys, v)}
+    out["runner"] = {v: k for k, v in CHUNK_RUNNERS.items()}.get(out["runner"], None) if out["rows_per_chunk"] else None
+    return out
+
+
+def abilu_pattern_chunk_export(p: Pattern, upper: bool, order=None, lvptr=None, lvstart=None, stream=None):
+    _check(lib().abilu_pattern_chunk_export(p.handle, int(bool(upper)), _ptr(order), _ptr(lvptr), _ptr(lvstart),
+                                            _stream(stream)), "abilu_pattern_chunk_export")
 
 
 def abilu_workspace_bytes(p: Pattern, prec: str = "f32", fgmres_restart: int = 0) -> int:

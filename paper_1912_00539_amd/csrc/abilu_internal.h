@@ -30,6 +30,19 @@ struct abilu_pattern {
     int32_t *ucol = nullptr;      // device [ZU+1] columns of the upper part
     double *pinned = nullptr;     // host pinned, 64 doubles, for blocking scalar reads
     int device = 0;
+    // chunk schedule (abilu_pattern_set_chunks): chunks of chunk_rows consecutive rows; per chunk,
+    // the rows grouped by level in the chunk's lower (forward, factor) and upper (backward)
+    // dependence graphs. Schedule s (0 lower, 1 upper): order[s][N] rows, lvptr[s][nchunks+1]
+    // offsets into lvstart[s], whose entries for chunk c are the starts (positions in order[s])
+    // of its levels followed by the chunk's end.
+    int32_t chunk_rows = 0;
+    int32_t nchunks = 0;
+    int32_t chunk_runner = 0;     // ABILU_CHUNK_BY_LEVELS or ABILU_CHUNK_BY_ROWS (resolved, never AUTO)
+    int32_t max_levels[2] = {0, 0};
+    int64_t total_levels[2] = {0, 0};
+    int32_t *order[2] = {nullptr, nullptr};
+    int32_t *lvptr[2] = {nullptr, nullptr};
+    int32_t *lvstart[2] = {nullptr, nullptr};
 };
 
 namespace abilu {
@@ -150,6 +163,18 @@ abilu_status pattern_fill(int32_t n, int64_t Z, int64_t ZL, int64_t ZU, int64_t 
                           const int32_t *colidx, const int32_t *diag_pos, const int32_t *lrow, const int32_t *urow,
                           int32_t *lcol, int32_t *ucol, int32_t *pik, int32_t *pkj, int32_t *sik, int32_t *skj,
                           const void *scratch, hipStream_t s);
+
+// A mode the single-system entry points accept for this pattern (the chunked modes need the
+// pattern's chunk schedule).
+inline bool mode_ok(const abilu_pattern *p, abilu_mode m) {
+    if (m == ABILU_SYNC || m == ABILU_ASYNC || m == ABILU_ASYNC_SERIAL) return true;
+    return (m == ABILU_CHUNK_SYNC || m == ABILU_CHUNK_ASYNC) && p->chunk_rows > 0;
+}
+
+// Release a pattern's chunk schedule (chunks.hip).
+void free_chunks(abilu_pattern *p);
+int32_t chunk_runner_auto(int n, int nch, const int64_t *total_levels);
+constexpr int MAX_CHUNK_ROWS = 4096;
 
 // ------------------------------------------------------------------ entry points used across files
 abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv, abilu_prec prec,

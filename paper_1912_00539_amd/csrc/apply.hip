@@ -10,6 +10,8 @@
 // SYNC sweeps read the previous sweep's vector (ping-pong); ASYNC sweeps update in place.
 // From the zero initial guess the first SYNC forward sweep is y = r, so it is not launched; the
 // last forward sweep also produces the first backward sweep z = Dinv y (its rows are at hand).
+#include <type_traits>
+
 #include "kernels.h"
 
 using namespace abilu;
@@ -61,6 +63,141 @@ __global__ __launch_bounds__(64) void k_bwd_serial(int n, const int32_t *__restr
     }
 }
 
+// Chunked sweeps: workgroup c runs chunk c = rows [c0, c0 + R) level by level, one quad per row,
+// with a barrier after each level. Forward: y_i = r_i - sum_{j<i} L_ij y_j, where y_j comes from
+// this sweep (yn) for rows of the chunk and from the previous sweep (yo) for earlier rows; in the
+// first sweep (ZERO_OUT) the earlier rows contribute their initial value 0 and are not read.
+template <typename T, bool ZERO_OUT>
+__device__ __forceinline__ void fwd_chunk_row(int i, int c0, const int32_t *__restrict__ lrow,
+                                              const int32_t *__restrict__ lcol, const T *__restrict__ Lb,
+                                              const double *__restrict__ rhs, const T *yo, T *yn) {
+    const int r = threadIdx.x & 3;
+    const int b0 = lrow[i], b1 = lrow[i + 1];
+    T acc = (T)rhs[(int64_t)i * 4 + r];
+    for (int e0 = b0; e0 < b1; e0 += 2) {
+        int j[2];
+        T l[2][4], yv[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = min(e0 + u, b1 - 1);
+            j[u] = lcol[e];
+            load_row(Lb + (int64_t)e * BB, r, l[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (j[u] >= c0) yv[u] = yn[(int64_t)j[u] * 4 + r];
+            else if constexpr (ZERO_OUT) yv[u] = T(0);
+            else yv[u] = yo[(int64_t)j[u] * 4 + r];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            T yj[4];
+            gather_vec(yv[u], yj);
+            const T c = l[u][0] * yj[0] + l[u][1] * yj[1] + l[u][2] * yj[2] + l[u][3] * yj[3];
+            acc -= (e0 + u < b1) ? c : T(0);
+        }
+    }
+    yn[(int64_t)i * 4 + r] = acc;
+}
+
+// Backward: z_i = Dinv_i (y_i - sum_{j>i} U_ij z_j), z_j of this sweep (zn) for rows of the chunk
+// (j < c1), of the previous sweep (zo) for later rows, 0 in the first sweep (ZERO_OUT).
+template <typename T, typename ZN, bool ZERO_OUT>
+__device__ __forceinline__ void bwd_chunk_row(int i, int c1, const int32_t *__restrict__ urow,
+                                              const int32_t *__restrict__ ucol, const T *__restrict__ Ub,
+                                              const T *__restrict__ Dinv, const T *__restrict__ y, const T *zo,
+                                              ZN *zn) {
+    const int r = threadIdx.x & 3;
+    const int b0 = urow[i], b1 = urow[i + 1];
+    T acc = y[(int64_t)i * 4 + r];
+    for (int e0 = b0; e0 < b1; e0 += 2) {
+        int j[2];
+        T u4[2][4], zv[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = min(e0 + u, b1 - 1);
+            j[u] = ucol[e];
+            load_row(Ub + (int64_t)e * BB, r, u4[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (j[u] < c1) zv[u] = (T)zn[(int64_t)j[u] * 4 + r];
+            else if constexpr (ZERO_OUT) zv[u] = T(0);
+            else zv[u] = zo[(int64_t)j[u] * 4 + r];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            T zj[4];
+            gather_vec(zv[u], zj);
+            const T c = u4[u][0] * zj[0] + u4[u][1] * zj[1] + u4[u][2] * zj[2] + u4[u][3] * zj[3];
+            acc -= (e0 + u < b1) ? c : T(0);
+        }
+    }
+    T dr[4], a[4];
+    load_row(Dinv + (int64_t)i * BB, r, dr);
+    gather_vec(acc, a);
+    zn[(int64_t)i * 4 + r] = (ZN)(dr[0] * a[0] + dr[1] * a[1] + dr[2] * a[2] + dr[3] * a[3]);
+}
+
+template <typename T, bool ZERO_OUT>
+__global__ __launch_bounds__(WG) void k_fwd_chunk(int n, int R, const int32_t *__restrict__ order,
+                                                  const int32_t *__restrict__ lvptr,
+                                                  const int32_t *__restrict__ lvstart,
+                                                  const int32_t *__restrict__ lrow, const int32_t *__restrict__ lcol,
+                                                  const T *__restrict__ Lb, const double *__restrict__ rhs,
+                                                  const T *yo, T *yn) {
+    const int c = blockIdx.x, c0 = c * R;
+    const int b = lvptr[c], nl = lvptr[c + 1] - b - 1;
+    const int quad = threadIdx.x >> 2;
+    for (int l = 0; l < nl; ++l) {
+        const int p1 = lvstart[b + l + 1];
+        for (int q = lvstart[b + l] + quad; q < p1; q += ROWS_PER_WG)
+            fwd_chunk_row<T, ZERO_OUT>(order[q], c0, lrow, lcol, Lb, rhs, yo, yn);
+        __syncthreads();
+    }
+}
+
+template <typename T, typename ZN, bool ZERO_OUT>
+__global__ __launch_bounds__(WG) void k_bwd_chunk(int n, int R, const int32_t *__restrict__ order,
+                                                  const int32_t *__restrict__ lvptr,
+                                                  const int32_t *__restrict__ lvstart,
+                                                  const int32_t *__restrict__ urow, const int32_t *__restrict__ ucol,
+                                                  const T *__restrict__ Ub, const T *__restrict__ Dinv,
+                                                  const T *__restrict__ y, const T *zo, ZN *zn) {
+    const int c = blockIdx.x, c1 = min(n, c * R + R);
+    const int b = lvptr[c], nl = lvptr[c + 1] - b - 1;
+    const int quad = threadIdx.x >> 2;
+    for (int l = 0; l < nl; ++l) {
+        const int p1 = lvstart[b + l + 1];
+        for (int q = lvstart[b + l] + quad; q < p1; q += ROWS_PER_WG)
+            bwd_chunk_row<T, ZN, ZERO_OUT>(order[q], c1, urow, ucol, Ub, Dinv, y, zo, zn);
+        __syncthreads();
+    }
+}
+
+// The same sweeps with one quad per chunk running its rows in order (forward ascending, backward
+// descending); a lane only reads chunk values it stored itself.
+template <typename T, bool ZERO_OUT>
+__global__ __launch_bounds__(WG) void k_fwd_chunk_rows(int n, int R, int nch, const int32_t *__restrict__ lrow,
+                                                       const int32_t *__restrict__ lcol, const T *__restrict__ Lb,
+                                                       const double *__restrict__ rhs, const T *yo, T *yn) {
+    const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
+    if (c >= nch) return;
+    const int c0 = c * R, c1 = min(n, c0 + R);
+    for (int i = c0; i < c1; ++i) fwd_chunk_row<T, ZERO_OUT>(i, c0, lrow, lcol, Lb, rhs, yo, yn);
+}
+
+template <typename T, typename ZN, bool ZERO_OUT>
+__global__ __launch_bounds__(WG) void k_bwd_chunk_rows(int n, int R, int nch, const int32_t *__restrict__ urow,
+                                                       const int32_t *__restrict__ ucol, const T *__restrict__ Ub,
+                                                       const T *__restrict__ Dinv, const T *__restrict__ y,
+                                                       const T *zo, ZN *zn) {
+    const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
+    if (c >= nch) return;
+    const int c0 = c * R, c1 = min(n, c0 + R);
+    for (int i = c1 - 1; i >= c0; --i) bwd_chunk_row<T, ZN, ZERO_OUT>(i, c1, urow, ucol, Ub, Dinv, y, zo, zn);
+}
+
 // y = A x  (RESID: y = b - A x), double precision, CSR; one quad per block row, four blocks
 // loaded per step (clamped: rows always hold at least their diagonal block)
 template <bool RESID>
@@ -90,7 +227,11 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
     T *za = (T *)(work + W.za), *zb = (T *)(work + W.zb);
     char name[64];
     auto NAME = [&](const char *base) {
-        snprintf(name, sizeof name, "%s_%s_%s", base, tname<T>(), mode == ABILU_SYNC ? "sync" : (mode == ABILU_ASYNC ? "async" : "serial"));
+        const char *mn = mode == ABILU_SYNC ? "sync"
+                         : mode == ABILU_ASYNC ? "async"
+                         : mode == ABILU_ASYNC_SERIAL ? "serial"
+                         : mode == ABILU_CHUNK_SYNC ? "chunk_sync" : "chunk_async";
+        snprintf(name, sizeof name, "%s_%s_%s", base, tname<T>(), mn);
         return name;
     };
     const Sizes zz = sizes(p);
@@ -120,6 +261,64 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
                 k_bwd_serial<T, double, true><<<1, 4, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, z);
             else
                 k_bwd_serial<T, T, false><<<1, 4, 0, s>>>(n, urow, ucol, Ub, Dinv, ya, za, za);
+            LAUNCHED();
+        }
+        return ABILU_OK;
+    }
+    if (mode == ABILU_CHUNK_SYNC || mode == ABILU_CHUNK_ASYNC) {
+        // Chunked sweeps, every sweep launched (no closed form: the first sweep already substitutes
+        // within each chunk). CHUNK_SYNC: ping-pong ya/yb and za/zb; CHUNK_ASYNC: in place on ya
+        // and za; the last backward sweep writes z (double) and reads the chunk's rows from it.
+        const bool cs = mode == ABILU_CHUNK_SYNC;
+        const int nch = p->nchunks, R = p->chunk_rows;
+        const double sch[2] = {4.0 * zz.N + 4.0 * (nch + 1) + 4.0 * (double)(p->total_levels[0] + nch),
+                               4.0 * zz.N + 4.0 * (nch + 1) + 4.0 * (double)(p->total_levels[1] + nch)};
+        const int32_t *const *O = p->order, *const *LP = p->lvptr, *const *LS = p->lvstart;
+        const bool by_rows = p->chunk_runner == ABILU_CHUNK_BY_ROWS;
+        const int g = by_rows ? div_up(nch, ROWS_PER_WG) : nch;
+        // yo == nullptr: first sweep (earlier rows contribute their initial value 0)
+        auto fwd = [&](const T *yo, T *yn) {
+            if (by_rows) {
+                if (!yo) k_fwd_chunk_rows<T, true><<<g, WG, 0, s>>>(n, R, nch, lrow, lcol, Lb, r, yo, yn);
+                else k_fwd_chunk_rows<T, false><<<g, WG, 0, s>>>(n, R, nch, lrow, lcol, Lb, r, yo, yn);
+            } else {
+                if (!yo) k_fwd_chunk<T, true><<<g, WG, 0, s>>>(n, R, O[0], LP[0], LS[0], lrow, lcol, Lb, r, yo, yn);
+                else k_fwd_chunk<T, false><<<g, WG, 0, s>>>(n, R, O[0], LP[0], LS[0], lrow, lcol, Lb, r, yo, yn);
+            }
+        };
+        auto bwd = [&](const T *y, const T *zo, auto *zn) {
+            using ZN = std::remove_pointer_t<decltype(zn)>;
+            if (by_rows) {
+                if (!zo) k_bwd_chunk_rows<T, ZN, true><<<g, WG, 0, s>>>(n, R, nch, urow, ucol, Ub, Dinv, y, zo, zn);
+                else k_bwd_chunk_rows<T, ZN, false><<<g, WG, 0, s>>>(n, R, nch, urow, ucol, Ub, Dinv, y, zo, zn);
+            } else {
+                if (!zo)
+                    k_bwd_chunk<T, ZN, true><<<g, WG, 0, s>>>(n, R, O[1], LP[1], LS[1], urow, ucol, Ub, Dinv, y, zo, zn);
+                else
+                    k_bwd_chunk<T, ZN, false><<<g, WG, 0, s>>>(n, R, O[1], LP[1], LS[1], urow, ucol, Ub, Dinv, y, zo, zn);
+            }
+        };
+        const T *yo = nullptr;
+        T *yn = ya;
+        for (int q = 1; q <= nsw; ++q) {
+            yn = (!cs || q % 2 == 1) ? ya : yb;
+            ProfScope ps(NAME("apply_fwd"), s, bytes_fwd(zz, sF, sF, false) + sch[0]);
+            fwd(q == 1 ? nullptr : (cs ? yo : yn), yn);
+            LAUNCHED();
+            yo = yn;
+        }
+        const T *yfin = yn;
+        const T *zo = nullptr;
+        for (int q = 1; q <= nsw; ++q) {
+            const bool last = q == nsw;
+            ProfScope ps(NAME(last ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, last ? 8 : sF, false) + sch[1]);
+            if (last) {
+                bwd(yfin, zo, z);
+            } else {
+                T *zc = (!cs || q % 2 == 1) ? za : zb;
+                bwd(yfin, q == 1 ? nullptr : (cs ? zo : zc), zc);
+                zo = zc;
+            }
             LAUNCHED();
         }
         return ABILU_OK;
@@ -215,7 +414,7 @@ extern "C" abilu_status abilu_apply(const abilu_pattern *p, const void *d_LU, co
                                     size_t work_bytes, void *stream) {
     if (!p || nsweeps < 0) return ABILU_EINVAL;
     if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
-    if (mode != ABILU_SYNC && mode != ABILU_ASYNC && mode != ABILU_ASYNC_SERIAL) return ABILU_EINVAL;
+    if (!mode_ok(p, mode)) return ABILU_EINVAL;
     if (!d_work) return ABILU_EINVAL;
     const Workspace W = layout(p, prec, 0);
     if (work_bytes < W.total) return ABILU_EINVAL;

@@ -70,6 +70,49 @@ __global__ __launch_bounds__(64) void k_factor_sweep_serial(
     }
 }
 
+// One chunked sweep: workgroup c runs chunk c, level by level (lower schedule), one quad per row;
+// the barrier after each level makes the level's blocks and inverses visible to the next.
+template <typename T, bool OUT_FROM_A>
+__global__ __launch_bounds__(WG) void k_factor_sweep_chunk(
+    int n, int ZL, int R, const int32_t *__restrict__ order, const int32_t *__restrict__ lvptr,
+    const int32_t *__restrict__ lvstart, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+    const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pkj, const int32_t *__restrict__ sik,
+    const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XO, const T *DO, T *Xn, T *Dn,
+    unsigned *flags) {
+    const int c = blockIdx.x;
+    const int c0 = c * R;
+    const int ubound = ZL + n + urow[c0];
+    const int b = lvptr[c], nl = lvptr[c + 1] - b - 1;
+    const int quad = threadIdx.x >> 2;
+    for (int l = 0; l < nl; ++l) {
+        const int p1 = lvstart[b + l + 1];
+        for (int q = lvstart[b + l] + quad; q < p1; q += ROWS_PER_WG)
+            factor_chunk_row<T, OUT_FROM_A>(order[q], c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow,
+                                            pair_ptr, pkj, sik, skj, A, XO, DO, Xn, Dn, flags);
+        __syncthreads();
+    }
+}
+
+// One chunked sweep with one quad per chunk running the chunk's rows in ascending order (the
+// worker-per-chunk form of the same sweep). Every value of the chunk that a lane reads was stored
+// by that same lane (lane r owns row r of every block), so program order makes it visible.
+template <typename T, bool OUT_FROM_A>
+__global__ __launch_bounds__(WG) void k_factor_sweep_chunk_rows(
+    int n, int ZL, int R, int nch, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+    const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pkj, const int32_t *__restrict__ sik,
+    const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XO, const T *DO, T *Xn, T *Dn,
+    unsigned *flags) {
+    const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
+    if (c >= nch) return;
+    const int c0 = c * R, c1 = min(n, c0 + R);
+    const int ubound = ZL + n + urow[c0];
+    for (int i = c0; i < c1; ++i)
+        factor_chunk_row<T, OUT_FROM_A>(i, c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, pkj,
+                                        sik, skj, A, XO, DO, Xn, Dn, flags);
+}
+
 // Conversions between the factor layout and CSR order (one quad per block row).
 template <typename T, bool TO_CSR>
 __global__ __launch_bounds__(WG) void k_factor_permute(int n, int ZL, const int32_t *__restrict__ rowptr,
@@ -169,6 +212,71 @@ abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, i
         return ABILU_OK;
     }
 
+    if (mode == ABILU_CHUNK_SYNC || mode == ABILU_CHUNK_ASYNC) {
+        // Chunked sweeps. CHUNK_SYNC reads other chunks from the previous sweep (ping-pong as in
+        // SYNC); CHUNK_ASYNC works in place. The first sweep from A reads other chunks' blocks
+        // from A itself (X0) in both modes.
+        const bool cs = (mode == ABILU_CHUNK_SYNC);
+        const double sched = 4.0 * z.N + 4.0 * (p->nchunks + 1) + 4.0 * (double)(p->total_levels[0] + p->nchunks);
+        auto chunk_sweep = [&](bool fromA, const T *XO, const T *DO, T *Xn, T *Dn, const char *nm) -> abilu_status {
+            ProfScope ps(NAME("factor_sweep", nm), s, bytes_sweep(z, sF, false, fromA) + sched);
+            if (p->chunk_runner == ABILU_CHUNK_BY_ROWS) {
+                const int g = div_up(p->nchunks, ROWS_PER_WG);
+                if (fromA)
+                    k_factor_sweep_chunk_rows<T, true><<<g, WG, 0, s>>>(
+                        n, ZL, p->chunk_rows, p->nchunks, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow,
+                        p->pair_ptr, p->pkj, p->sik, p->skj, A, XO, DO, Xn, Dn, flags);
+                else
+                    k_factor_sweep_chunk_rows<T, false><<<g, WG, 0, s>>>(
+                        n, ZL, p->chunk_rows, p->nchunks, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow,
+                        p->pair_ptr, p->pkj, p->sik, p->skj, A, XO, DO, Xn, Dn, flags);
+            } else if (fromA)
+                k_factor_sweep_chunk<T, true><<<p->nchunks, WG, 0, s>>>(
+                    n, ZL, p->chunk_rows, p->order[0], p->lvptr[0], p->lvstart[0], p->rowptr, p->colidx, p->diag_pos,
+                    p->lrow, p->urow, p->pair_ptr, p->pkj, p->sik, p->skj, A, XO, DO, Xn, Dn, flags);
+            else
+                k_factor_sweep_chunk<T, false><<<p->nchunks, WG, 0, s>>>(
+                    n, ZL, p->chunk_rows, p->order[0], p->lvptr[0], p->lvstart[0], p->rowptr, p->colidx, p->diag_pos,
+                    p->lrow, p->urow, p->pair_ptr, p->pkj, p->sik, p->skj, A, XO, DO, Xn, Dn, flags);
+            LAUNCHED();
+            return ABILU_OK;
+        };
+        if (!cs) {
+            int q0 = 0;
+            if (init == ABILU_INIT_FROM_A) {
+                if ((st = init_dinv_A(Dinv)) != ABILU_OK) return st;
+                if ((st = chunk_sweep(true, (const T *)nullptr, Dinv, LU, Dinv, "_chunk_async_fromA")) != ABILU_OK)
+                    return st;
+                q0 = 1;
+            } else if ((st = init_dinv_X(LU, Dinv)) != ABILU_OK) {
+                return st;
+            }
+            for (int q = q0; q < nsw; ++q)
+                if ((st = chunk_sweep(false, LU, Dinv, LU, Dinv, "_chunk_async")) != ABILU_OK) return st;
+            return ABILU_OK;
+        }
+        auto cX = [&](int q) { return ((nsw - q) % 2 == 0) ? LU : X1; };
+        auto cD = [&](int q) { return ((nsw - q) % 2 == 0) ? Dinv : D1; };
+        if (init == ABILU_INIT_FROM_A) {
+            if ((st = init_dinv_A(cD(0))) != ABILU_OK) return st;
+            if ((st = chunk_sweep(true, (const T *)nullptr, cD(0), cX(1), cD(1), "_chunk_sync_fromA")) != ABILU_OK)
+                return st;
+        } else {
+            T *X0 = LU;
+            if (cX(1) == LU) {
+                if (!hip_ok(hipMemcpyAsync(X1, LU, sizeof(T) * BB * (size_t)p->nnzb, hipMemcpyDeviceToDevice, s),
+                            "warm-start copy"))
+                    return ABILU_EDEVICE;
+                X0 = X1;
+            }
+            if ((st = init_dinv_X(X0, cD(0))) != ABILU_OK) return st;
+            if ((st = chunk_sweep(false, X0, cD(0), cX(1), cD(1), "_chunk_sync")) != ABILU_OK) return st;
+        }
+        for (int q = 2; q <= nsw; ++q)
+            if ((st = chunk_sweep(false, cX(q - 1), cD(q - 1), cX(q), cD(q), "_chunk_sync")) != ABILU_OK) return st;
+        return ABILU_OK;
+    }
+
     if (mode == ABILU_ASYNC) {
         int q0 = 0;
         if (init == ABILU_INIT_FROM_A) {
@@ -240,7 +348,7 @@ extern "C" abilu_status abilu_factor(const abilu_pattern *p, const double *d_A, 
                                      void *d_work, size_t work_bytes, void *stream) {
     if (!p || nsweeps < 0) return ABILU_EINVAL;
     if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
-    if (mode != ABILU_SYNC && mode != ABILU_ASYNC && mode != ABILU_ASYNC_SERIAL) return ABILU_EINVAL;
+    if (!mode_ok(p, mode)) return ABILU_EINVAL;
     if (init != ABILU_INIT_FROM_A && init != ABILU_INIT_FROM_LU) return ABILU_EINVAL;
     if (!d_work) return ABILU_EINVAL;
     const Workspace W = layout(p, prec, 0);

@@ -505,6 +505,86 @@ __device__ __forceinline__ void factor_sweep_row(int i,
     if (fl) atomicOr(flags, fl);
 }
 
+// t -= sum over the update set [p0, p1) of X_ik X_kj for a row of a chunk (chunked sweeps).
+// X_ik is a block of this row and comes from Xn (this sweep). X_kj lies in the strictly upper part
+// of row k < i: rows of the chunk (factor-layout position >= ubound) come from Xn, earlier rows
+// from XO, or from A at CSR positions when OUT_FROM_A (the first sweep from X0 = A).
+template <typename T, bool OUT_FROM_A>
+__device__ __forceinline__ void update_terms_chunk(int p0, int p1, int r, int ubound, const int32_t *__restrict__ pkj,
+                                                   const int32_t *__restrict__ sik, const int32_t *__restrict__ skj,
+                                                   const double *__restrict__ A, const T *Xn, const T *XO,
+                                                   T (&t)[4]) {
+    for (int q = p0; q < p1; ++q) {
+        T l[4], u[4];
+        load_block_row(Xn, sik[q], r, l);
+        const int sp = skj[q];
+        if (sp >= ubound) load_block_row(Xn, sp, r, u);
+        else if constexpr (OUT_FROM_A) load_block_row(A, pkj[q], r, u);
+        else load_block_row(XO, sp, r, u);
+        row_times_block_sub(l, u, t);
+    }
+}
+
+// One chunked sweep over block row i of the chunk starting at row c0: the blocks of the row in
+// ascending column order, each stored before the next is computed (a Gauss-Seidel order within
+// the row), reading the chunk's rows from this sweep (Xn, Dn) and earlier rows from XO, DO.
+template <typename T, bool OUT_FROM_A>
+__device__ __forceinline__ void factor_chunk_row(int i, int c0, int ubound,
+    int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+    const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pkj, const int32_t *__restrict__ sik,
+    const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XO, const T *DO, T *Xn, T *Dn,
+    unsigned *flags) {
+    const int r = threadIdx.x & 3;
+    const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
+    T *XnL = Xn + (int64_t)lrow[i] * BB;
+    T *XnU = Xn + ((int64_t)ZL + n + urow[i]) * BB;
+    unsigned fl = 0;
+    // strictly lower blocks: L_ij = (A_ij - sum) U_jj^{-1}, U_jj^{-1} of this sweep if j is in the chunk
+    for (int e = b0; e < d; ++e) {
+        T t[4], dr[4];
+        load_row(A + (int64_t)e * BB, r, t);
+        const int j = colidx[e];
+        load_row((j >= c0 ? (const T *)Dn : DO) + (int64_t)j * BB, r, dr);
+        update_terms_chunk<T, OUT_FROM_A>(pair_ptr[e], pair_ptr[e + 1], r, ubound, pkj, sik, skj, A, Xn, XO, t);
+        T x[4];
+        row_times_block(t, dr, x);
+        fl |= nonfinite4(x);
+        store_row(XnL + (int64_t)(e - b0) * BB, r, x);
+    }
+    // diagonal block U_ii = A_ii - sum and its inverse
+    {
+        T t[4];
+        load_row(A + (int64_t)d * BB, r, t);
+        update_terms_chunk<T, OUT_FROM_A>(pair_ptr[d], pair_ptr[d + 1], r, ubound, pkj, sik, skj, A, Xn, XO, t);
+        fl |= nonfinite4(t);
+        store_row(Xn + ((int64_t)ZL + i) * BB, r, t);
+        T M[16], out[4];
+        gather_block(t, M);
+        if (!inv4_row(M, r, out)) fl |= ABILU_FLAG_MODIFIED;
+        store_row(Dn + (int64_t)i * BB, r, out);
+    }
+    // strictly upper blocks: U_ij = A_ij - sum (independent of each other)
+    for (int e0 = d + 1; e0 < b1; e0 += CH) {
+        T t[CH][4];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) load_row(A + (int64_t)min(e0 + u, b1 - 1) * BB, r, t[u]);
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if (e0 + u < b1)
+                update_terms_chunk<T, OUT_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, ubound, pkj, sik, skj,
+                                                  A, Xn, XO, t[u]);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (e0 + u < b1) {
+                fl |= nonfinite4(t[u]);
+                store_row(XnU + (int64_t)(e0 + u - d - 1) * BB, r, t[u]);
+            }
+        }
+    }
+    if (fl) atomicOr(flags, fl);
+}
+
 template <typename T, bool L_FROM_A, bool U_FROM_A>
 __device__ __forceinline__ void factor_sweep_body(int blk,
     int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,

@@ -227,7 +227,7 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
     if (!p || !out || !d_work) return ABILU_EINVAL;
     if (restart < 1 || restart > MAX_RESTART || maxit < 0 || !(rtol >= 0.0) || apply_sweeps < 0) return ABILU_EINVAL;
     if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
-    if (mode != ABILU_SYNC && mode != ABILU_ASYNC && mode != ABILU_ASYNC_SERIAL) return ABILU_EINVAL;
+    if (!mode_ok(p, mode)) return ABILU_EINVAL;
     *out = abilu_fgmres_result{0, 0, 0, 0u, 0, 0.0, 0.0};
     Ctx c;
     c.p = p;

@@ -54,6 +54,7 @@ void free_pattern(abilu_pattern *p) {
     (void)hipFree(p->urow);
     (void)hipFree(p->lcol);
     (void)hipFree(p->ucol);
+    abilu::free_chunks(p);
     if (p->pinned) (void)hipHostFree(p->pinned);
     delete p;
 }

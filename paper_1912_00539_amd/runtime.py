@@ -30,6 +30,11 @@ class DeviceSystem:
         self.work = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self.x = torch.zeros(max(4 * self.n, 1), dtype=torch.float64, device=dev)
 
+    def set_chunks(self, rows_per_chunk: int, runner: str = "auto"):
+        """Build the chunk schedule of the chunked modes ("chunk_sync", "chunk_async")."""
+        L.abilu_pattern_set_chunks(self.pattern, rows_per_chunk, runner)
+        return L.abilu_pattern_chunk_info(self.pattern)
+
     def load_values(self, vals, b=None):
         """Replace A (and b) by new values on the same pattern (the next Jacobian of a sequence)."""
         t = self.torch

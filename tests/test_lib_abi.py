@@ -56,6 +56,9 @@ def test_argument_checks_without_device():
     res = L.FgmresResult()
     assert lib.fgmres_solve(None, None, None, None, 30, 10, 1e-2, None, None, 0, 3, 0, 0, None, 0, None,
                             C.byref(res)) == L.ABILU_EINVAL
+    assert lib.abilu_pattern_set_chunks(None, 64, 0, None) == L.ABILU_EINVAL
+    assert lib.abilu_pattern_chunk_info(None, None, None, None, None, None, None, None) == L.ABILU_EINVAL
+    assert lib.abilu_pattern_chunk_export(None, 0, None, None, None, None) == L.ABILU_EINVAL
     assert lib.abilu_stream_copy(None, None, 7, None) == L.ABILU_EINVAL
     assert lib.abilu_profile_enable(1, 0) == L.ABILU_EINVAL
 
