@@ -331,10 +331,10 @@ def chunked_bench(args):
     from paper_1912_00539_amd import workloads as W
     from paper_1912_00539_amd.runtime import DeviceSystem
     out = {}
-    for label, name, kw, R, restart in (("tri2000", args.workload, {}, 64, args.restart),
-                                        ("aniso1000_line", "aniso1000", {"order": "line"}, 16, 30)):
+    for label, name, kw, R in (("tri2000", args.workload, {}, 64),
+                               ("aniso1000_line", "aniso1000", {"order": "line"}, 16)):
         c = W.case(name, **kw)
-        s = DeviceSystem(c, prec=args.prec, restart=restart)
+        s = DeviceSystem(c, prec=args.prec, restart=args.restart)
         rows = {}
         for mode in ("async", "chunk_async"):
             info = s.set_chunks(R) if mode == "chunk_async" else None

@@ -60,14 +60,15 @@ typedef enum {
  * forward apply sweep is forward substitution and a backward sweep (rows in descending order)
  * back substitution. It occupies one compute unit lane group: for verification, not speed.
  *
- * ABILU_CHUNK_SYNC, ABILU_CHUNK_ASYNC: the schedule of the paper's implementation (Section 4.3),
+ * ABILU_CHUNK_SYNC, ABILU_CHUNK_ASYNC: the schedule of the paper's implementation (Section 3.3),
  * where the row loop is cut into chunks of consecutive rows and a worker runs a whole chunk in
  * row-major order, so that inside a chunk the factor sweep is a Gauss-Seidel sweep (each block
  * sees the values its chunk has already computed in the sweep), the forward apply sweep a forward
- * substitution and the backward apply sweep (rows descending) a backward substitution. One
- * workgroup runs one chunk, its rows grouped by dependence level with a barrier between levels,
- * which gives exactly the values of the row-major order. Needs the pattern's chunk schedule
- * (abilu_pattern_set_chunks). The iteration is exact after as many sweeps as there are chunks.
+ * substitution and the backward apply sweep (rows descending) a backward substitution. A chunk is
+ * run either by a workgroup, its rows grouped by dependence level with a barrier between levels,
+ * or by one quad row after row (abilu_chunk_runner); both give exactly the values of the row-major
+ * order. Needs the pattern's chunk schedule (abilu_pattern_set_chunks). The iteration is exact after as many sweeps as there are chunks
+ * (Section 4.2).
  *   ABILU_CHUNK_SYNC : rows of other chunks are read from the previous sweep (deterministic).
  *   ABILU_CHUNK_ASYNC: in place; rows of other chunks are read as they are in memory.
  * Every apply sweep is launched (no closed-form first sweep). Not accepted by the server. */
@@ -116,7 +117,7 @@ abilu_status abilu_pattern_export(const abilu_pattern *p, int32_t *d_diag_pos, i
                                   int32_t *d_pik, int32_t *d_pkj, void *stream);
 
 /*
- * Build the chunk schedule used by the ABILU_CHUNK_* modes (the chunks of Section 4.3): block rows
+ * Build the chunk schedule used by the ABILU_CHUNK_* modes (the chunks of Section 3.3): block rows
  * are cut into chunks of rows_per_chunk consecutive rows (the last one may be shorter). For each
  * chunk the rows are grouped by level in the chunk's lower dependence graph (level 1: no strictly
  * lower neighbour inside the chunk; otherwise one more than the largest level of its strictly

@@ -336,7 +336,7 @@ unsigned oracle_factor_gs(int n, const int *rowptr, const int *colidx, const dou
 }
 
 /*
- * Chunked sweeps (Section 4.3: each OpenMP chunk of consecutive rows is run by one thread in the
+ * Chunked sweeps (Section 3.3: each OpenMP chunk of consecutive rows is run by one thread in the
  * row-major order, so within a chunk the blocks are computed in a Gaussian-elimination ordering
  * with respect to the chunk's own blocks). The row loop is cut into chunks of R consecutive block
  * rows; a chunk's rows are processed in ascending order and every block of the chunk sees the
@@ -453,7 +453,7 @@ void oracle_apply_sync(int n, const int *rowptr, const int *colidx, const double
 
 /*
  * Chunked preconditioner application: the sweeps of oracle_apply_sync with the rows cut into
- * chunks of R consecutive rows, each chunk run in order by one worker (Section 4.3 chunks), so
+ * chunks of R consecutive rows, each chunk run in order by one worker (Section 3.3 chunks), so
  * that within a chunk the forward sweep is a forward substitution (ascending rows) and the
  * backward sweep a backward substitution (descending rows); entries of other chunks are read from
  * the previous sweep's vector (y^0 = z^0 = 0). nsw sweeps each; nsw == 0 means z = r.

@@ -1,5 +1,5 @@
 // Chunk schedules for the chunked sweeps. The paper's implementation hands each worker a chunk of
-// consecutive rows, which it runs in row-major order (Section 4.3), so that within a chunk the
+// consecutive rows, which it runs in row-major order (Section 3.3), so that within a chunk the
 // blocks are computed in a Gaussian-elimination ordering. Here one workgroup runs one chunk: row i
 // of the chunk only reads values of the chunk's rows k < i that are its strictly lower neighbours
 // (the L_ik of its own row, and U_kj, U_kk^{-1} of rows k with (i,k) in S_B), so the rows can be

@@ -1,5 +1,5 @@
 """Chunked sweeps on the GPU (Gauss-Seidel within chunks of consecutive rows, the schedule of the
-paper's OpenMP chunks, Section 4.3) against the CPU FP64 oracle, through the C ABI.
+paper's OpenMP chunks, Section 3.3) against the CPU FP64 oracle, through the C ABI.
 
   * chunk schedules (integers): bit-exact against the oracle's dependence levels of each chunk's
     diagonal block of the pattern;
@@ -237,7 +237,7 @@ def test_factor_single_chunk_is_sequential_ilu(name, prec, runner):
 @pytest.mark.parametrize("name,R", [("nine23x17", 64), ("random1000", 128), ("chain7", 2),
                                     ("aniso50x20_line", 256), ("tri40x30_rcm", 512)])
 def test_factor_chunked_exact_after_one_sweep_per_chunk(name, R, runner):
-    """Section 4.3: exact after as many sweeps as chunks, whatever the order in which the chunks
+    """Section 4.2: exact after as many sweeps as chunks, whatever the order in which the chunks
     ran (CHUNK_ASYNC) -- and CHUNK_SYNC likewise."""
     c = get(name)
     nch = (c.n + R - 1) // R

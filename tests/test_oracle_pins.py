@@ -508,7 +508,7 @@ def test_fixed_point_residual_dense(name, c):
 # ------------------------------------------------------------------ chunked (Gauss-Seidel within a chunk) sweeps
 @pytest.mark.parametrize("name,c", small_cases())
 def test_chunked_single_chunk_is_sequential(name, c):
-    """Section 4.3: a chunk is run in row-major order by one worker. With one chunk covering
+    """Section 3.3: a chunk is run in row-major order by one worker. With one chunk covering
     every row, one factor sweep from A is the sequential block ILU(0) (Theorem 7 ordering) and one
     apply sweep pair is the exact forward and backward substitution (Algorithm 1)."""
     Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
@@ -529,7 +529,7 @@ def _chunk_rel(X, Xs, rowptr, rows):
 
 @pytest.mark.parametrize("mesh,R", [("nine", 5), ("chain", 2), ("random", 4)])
 def test_chunked_exact_one_chunk_per_sweep(mesh, R):
-    """Section 4.3: once the chunks before chunk p have their final values, chunk p gets its
+    """Section 4.2: once the chunks before chunk p have their final values, chunk p gets its
     final values in the next sweep, so the iteration is exact after as many sweeps as there are
     chunks. Checked chunk by chunk: after s sweeps chunks 0..s-1 equal the sequential ILU(0), and
     on the chain and the natural-order grid, where each chunk depends on the one before it, chunk s
