@@ -17,6 +17,8 @@ solves/s at saturation and p50/p99 latency under Poisson arrivals. The "precisio
 same step with the preconditioner in FP64, and gives the distance between the FP32 and FP64 factors.
 The "chunked" object compares the chunked (Gauss-Seidel within chunks) sweeps with the unchunked
 asynchronous ones on the same step, and on the line-ordered anisotropic mesh.
+The "configs" object gives factor and apply bandwidth on the 180,000-triangle and the
+500,000-cell anisotropic workloads (line and RCM order), SYNC/ASYNC, FP32/FP64.
 Prints one JSON line.
 """
 import argparse
@@ -128,7 +130,16 @@ def cpu_baseline(case, args):
         reps += 1
     t1 = time.perf_counter()
     by = reps * oracle_bytes_f64(n, Z, ZL, ZU, P, args.apply_sweeps)
+    cpu_model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(by / (t1 - t0) / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model, "host_cpus": os.cpu_count(),
             "sample": f"{reps} x (one synchronous FP64 factor sweep + {args.apply_sweeps} forward/backward sweep pairs "
                       f"+ one SpMV) on the full {n}-cell matrix ({t1 - t0:.1f} s); bytes from the same algorithmic "
                       "model as the GPU kernels, in FP64",
@@ -321,6 +332,54 @@ def precision_bench(case, args):
             "factor_distance_after_2_sync_sweeps": dist}
 
 
+def configs_bench(args):
+    """Factor and apply bandwidth on the other full-size workloads: one factor (init + 1 sweep) and
+    one application (3 sweep pairs), SYNC and ASYNC, FP32 and FP64. The 180,000-triangle case fits
+    the 256 MB Infinity Cache in part, so its figures are effective bandwidth, not HBM bandwidth."""
+    import torch
+    from paper_1912_00539_amd import abilu as L
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    out = {}
+    for label, name, kw in (("tri300_cfl100", "tri300", {"cfl": 100.0}), ("aniso1000_line", "aniso1000", {"order": "line"}),
+                            ("aniso1000_rcm", "aniso1000", {"order": "rcm"})):
+        c = W.case(name, **kw)
+        rows = {"n": c.n, "nnzb": c.nnzb}
+        for prec in ("f32", "f64"):
+            s = DeviceSystem(c, prec=prec, restart=1)
+            r = torch.rand(4 * c.n, dtype=torch.float64, device="cuda")
+            z = torch.zeros_like(r)
+            for mode in ("sync", "async"):
+                s.factor(1, mode)
+                s.apply(r, z, args.apply_sweeps, mode)
+                torch.cuda.synchronize()
+                L.abilu_profile_enable(True, 100000)
+                reps = 10
+                for _ in range(reps):
+                    s.factor(1, mode)
+                    s.apply(r, z, args.apply_sweeps, mode)
+                torch.cuda.synchronize()
+                rep = L.abilu_profile_report()
+                L.abilu_profile_enable(False)
+                k = {kk: v for kk, v in rep.items() if kk.startswith(("factor_", "apply_"))}
+                fb = sum(v[2] for kk, v in k.items() if kk.startswith("factor_"))
+                fm = sum(v[1] for kk, v in k.items() if kk.startswith("factor_"))
+                ab = sum(v[2] for kk, v in k.items() if kk.startswith("apply_"))
+                am = sum(v[1] for kk, v in k.items() if kk.startswith("apply_"))
+                rows[f"{prec}_{mode}"] = {
+                    "factor_apply_GBps": round((fb + ab) / ((fm + am) / 1e3) / 1e9, 1),
+                    "factor_ms": round(fm / reps, 4), "factor_GBps": round(fb / (fm / 1e3) / 1e9, 1),
+                    "apply_ms": round(am / reps, 4), "apply_GBps": round(ab / (am / 1e3) / 1e9, 1),
+                    "ilu_residual_1_sweep": float(f"{s.ilu_residual():.4e}")}
+            del s
+            torch.cuda.empty_cache()
+        rows["working_set_note"] = ("partly cache-resident (effective bandwidth)" if c.n < 300000
+                                    else "exceeds the 256 MB Infinity Cache")
+        log(f"config {label}: {rows}")
+        out[label] = rows
+    return out
+
+
 def chunked_bench(args):
     """Chunked sweeps (Gauss-Seidel within chunks of consecutive rows, the schedule of the paper's
     OpenMP chunks) against the unchunked asynchronous sweeps, same step otherwise (FP32
@@ -393,6 +452,7 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-chunked", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--only-chunked", action="store_true", help="print the chunked object alone")
     ap.add_argument("--only-serving", action="store_true", help="print the serving object alone (profiling)")
     args = ap.parse_args()
@@ -521,6 +581,7 @@ def main():
     torch.cuda.empty_cache()
     out["precision"] = None if args.no_precision else precision_bench(case, args)
     out["chunked"] = None if args.no_chunked else chunked_bench(args)
+    out["configs"] = None if args.no_configs else configs_bench(args)
     out["serving"] = None if args.no_serving else serving_bench(args)
     out["warm_start"] = None if args.no_warm_start else warm_start_bench(args)
     if not args.no_cpu_baseline:
