@@ -301,6 +301,24 @@ def assemble(mesh: Mesh, new_of_old: np.ndarray, seed: int, shift: str = "const"
                    dict(kind=mesh.kind, shape=mesh.shape, seed=seed, shift=shift, s=s, cfl=cfl))
 
 
+def block_face_weights(mesh: Mesh, new_of_old: np.ndarray, rowptr: np.ndarray, colidx: np.ndarray) -> np.ndarray:
+    """Geometric coupling of each block of a case assembled from `mesh` in the ordering
+    `new_of_old`: the face's anisotropy scale (1 for an isotropic face, sqrt(AR_k AR_{k+1}) for a
+    wall-normal face of the boundary-layer mesh), 0 on the diagonal. This is the cell-geometry
+    input of line finding (face area over centroid distance, up to a constant)."""
+    new = np.asarray(new_of_old, np.int64)
+    n = mesh.ncells
+    a = new[mesh.fa]; b = new[mesh.fb]
+    r = np.concatenate([a, b]); c = np.concatenate([b, a])
+    w = np.concatenate([mesh.fscale, mesh.fscale])
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    key_blk = rows * n + np.asarray(colidx, np.int64)
+    pos = np.searchsorted(key_blk, r * n + c)
+    out = np.zeros(colidx.size)
+    out[pos] = w
+    return out
+
+
 # --------------------------------------------------------------------------- named cases
 def case(name: str, seed: int = 0, **kw) -> BSRCase:
     """Named workloads.
