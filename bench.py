@@ -17,6 +17,8 @@ solves/s at saturation and p50/p99 latency under Poisson arrivals. The "precisio
 same step with the preconditioner in FP64, and gives the distance between the FP32 and FP64 factors.
 The "chunked" object compares the chunked (Gauss-Seidel within chunks) sweeps with the unchunked
 asynchronous ones on the same step, and on the line-ordered anisotropic mesh.
+The "orderings" object measures the step under the orderings of Section 5 (RCM, one-way
+dissection, lines of anisotropic cells, line and hybrid line-X orderings).
 The "configs" object gives factor and apply bandwidth on the 180,000-triangle and the
 500,000-cell anisotropic workloads (line and RCM order), SYNC/ASYNC, FP32/FP64.
 Prints one JSON line.
@@ -380,6 +382,62 @@ def configs_bench(args):
     return out
 
 
+def orderings_bench(args):
+    """Orderings of mesh cells (Section 5) computed by the library (host), the same seeded matrix
+    assembled in each, then the step (asynchronous FP32 preconditioner, 1 build sweep, 3 apply
+    sweep pairs, FGMRES to rtol): on the 500,000-cell boundary-layer mesh (lines found from the
+    geometric face couplings, anisotropy threshold 10, strong-link ratio 4) and on the
+    180,000-triangle mesh from a random numbering (RCM, 1WD)."""
+    import numpy as np
+    import torch
+    from paper_1912_00539_amd import abilu as L
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    out = {}
+    studies = (("aniso1000", W.aniso_quad_mesh(1000, 500), "natural", 100.0,
+                ("line_columns", "rcm", "1wd", "line", "line_rcm", "line_1wd")),
+               ("tri300", W.split_tri_mesh(300, 300, args.serve_seed), "random", 100.0, ("random", "rcm", "1wd")))
+    for label, m, start, cfl, names in studies:
+        seed = args.serve_seed
+        if start == "natural":
+            base = W.natural_order(m)
+        else:
+            base = np.argsort(np.argsort(W.uniform01(seed, W.S_PERM, np.arange(m.ncells)), kind="stable"),
+                              kind="stable")
+        c0 = W.assemble(m, base, seed, "cfl", cfl=cfl)
+        wgt = W.block_face_weights(m, base, c0.rowptr, c0.colidx)
+        t = time.perf_counter()
+        lo, lp, nl = L.abilu_find_lines(c0.n, c0.rowptr, c0.colidx, wgt, 10.0, 4.0)
+        t_lines = time.perf_counter() - t
+        rows = {"n": c0.n, "lines": nl, "cells_in_lines": int((lo >= 0).sum()),
+                "find_lines_ms": round(t_lines * 1e3, 1)}
+        for name in names:
+            t = time.perf_counter()
+            if name == "line_columns":
+                new = W.line_order(m)                       # whole wall-normal columns (generator)
+            elif name == "random":
+                new = np.arange(m.ncells)
+            else:
+                new_c = L.abilu_order(c0.n, c0.rowptr, c0.colidx, name, lo, lp).astype(np.int64)
+                new = new_c[base]                           # compose: natural -> base -> new
+            t_ord = time.perf_counter() - t
+            c = W.assemble(m, new if name != "random" else base, seed, "cfl", cfl=cfl)
+            s = DeviceSystem(c, prec="f32", restart=args.restart)
+            run_steps(s, args, "async", 1, profile=False)
+            nst = 3
+            secs, res = run_steps(s, args, "async", nst, profile=False)[:2]
+            rows[name] = {"ilu_residual": float(f"{s.ilu_residual():.4e}"),
+                          "fgmres_iters": [r["iters"] for _, r in res],
+                          "max_rel_true_residual": max(r["rel_true_residual"] for _, r in res),
+                          "ms_per_step": round(secs * 1e3 / nst, 3),
+                          "ordering_ms": None if name in ("line_columns", "random") else round(t_ord * 1e3, 1)}
+            log(f"ordering {label} {name}: {rows[name]}")
+            del s
+            torch.cuda.empty_cache()
+        out[label] = rows
+    return out
+
+
 def chunked_bench(args):
     """Chunked sweeps (Gauss-Seidel within chunks of consecutive rows, the schedule of the paper's
     OpenMP chunks) against the unchunked asynchronous sweeps, same step otherwise (FP32
@@ -453,6 +511,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-chunked", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--no-orderings", action="store_true")
+    ap.add_argument("--only-orderings", action="store_true", help="print the orderings object alone")
     ap.add_argument("--only-chunked", action="store_true", help="print the chunked object alone")
     ap.add_argument("--only-serving", action="store_true", help="print the serving object alone (profiling)")
     args = ap.parse_args()
@@ -472,6 +532,9 @@ def main():
     L.lib()
     if args.only_serving:
         print(json.dumps({"serving": serving_bench(args)}), flush=True)
+        return
+    if args.only_orderings:
+        print(json.dumps({"orderings": orderings_bench(args)}), flush=True)
         return
     if args.only_chunked:
         print(json.dumps({"chunked": chunked_bench(args)}), flush=True)
@@ -582,6 +645,7 @@ def main():
     out["precision"] = None if args.no_precision else precision_bench(case, args)
     out["chunked"] = None if args.no_chunked else chunked_bench(args)
     out["configs"] = None if args.no_configs else configs_bench(args)
+    out["orderings"] = None if args.no_orderings else orderings_bench(args)
     out["serving"] = None if args.no_serving else serving_bench(args)
     out["warm_start"] = None if args.no_warm_start else warm_start_bench(args)
     if not args.no_cpu_baseline:

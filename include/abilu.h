@@ -160,6 +160,58 @@ abilu_status abilu_pattern_chunk_info(const abilu_pattern *p, int32_t *rows_per_
 abilu_status abilu_pattern_chunk_export(const abilu_pattern *p, int32_t upper, int32_t *d_order,
                                         int32_t *d_lvptr, int32_t *d_lvstart, void *stream);
 
+/*
+ * Orderings of mesh cells (Section 5). Host functions on host arrays, run once per mesh before
+ * assembly, as the paper reorders the grid in preprocessing. The graph is the block pattern made
+ * symmetric, without its diagonal. Deterministic: every tie goes to the lower index.
+ *
+ * abilu_find_lines: lines of strongly coupled anisotropic cells (Section 5.1), from one coupling
+ * weight per block (for example face area over centroid distance; the paper takes them from the
+ * cell geometry). With c_ij = w_ij + w_ji, cell i is anisotropic when max_j c_ij / min_j c_ij >=
+ * threshold, and (i, j) is a strong link when c_ij >= max_k c_ik / strong_ratio and
+ * c_ij >= max_k c_jk / strong_ratio. Seeds are the anisotropic cells in decreasing anisotropy;
+ * a line grows from its seed at one end, then at the other, each step to the unassigned
+ * anisotropic neighbour with the strongest strong link. A one-cell line is dropped.
+ *   h_rowptr int32[N+1], h_colidx int32[Z]   pattern (host)
+ *   h_weight double[Z]                        coupling weight of each block (diagonal ignored)
+ *   threshold >= 1, strong_ratio >= 1
+ *   h_line_of int32[N]   line of each cell, -1 for a cell in no line (written)
+ *   h_line_pos int32[N]  position of the cell in its line from 0, -1 outside lines (written)
+ *   nlines               number of lines (written)
+ * Errors: ABILU_EINVAL (null pointers, threshold or ratio below 1), ABILU_EPATTERN (index out of
+ * range).
+ */
+abilu_status abilu_find_lines(int32_t n, const int32_t *h_rowptr, const int32_t *h_colidx,
+                              const double *h_weight, double threshold, double strong_ratio,
+                              int32_t *h_line_of, int32_t *h_line_pos, int32_t *nlines);
+
+/* Orderings (Section 5):
+ *   ABILU_ORDER_RCM      reverse Cuthill-McKee from a George-Liu pseudo-peripheral node,
+ *                        neighbours in increasing degree; each connected component in turn;
+ *   ABILU_ORDER_1WD      George's one-way dissection: separator levels of the level structure
+ *                        from a pseudo-peripheral node every delta = sqrt((3w + 13)/2) levels
+ *                        (w = vertices per level), the parts between them numbered first (each by
+ *                        RCM), the separators last;
+ *   ABILU_ORDER_LINE     the cells in their order, each line placed whole where its first cell
+ *                        comes (Section 5.1);
+ *   ABILU_ORDER_LINE_RCM, ABILU_ORDER_LINE_1WD  hybrid line-X (Section 5.2): RCM or 1WD of the
+ *                        graph whose vertices are the lines and the isotropic cells, joined when
+ *                        any of their cells are neighbours, each vertex expanded into its cells. */
+typedef enum {
+    ABILU_ORDER_RCM = 0,
+    ABILU_ORDER_1WD = 1,
+    ABILU_ORDER_LINE = 2,
+    ABILU_ORDER_LINE_RCM = 3,
+    ABILU_ORDER_LINE_1WD = 4
+} abilu_ordering;
+
+/* Compute an ordering: h_new_of_old int32[N] receives the new index of every cell (a
+ * permutation). h_line_of / h_line_pos (as written by abilu_find_lines) are required by the line
+ * orderings and ignored otherwise. Errors: ABILU_EINVAL (null pointers, bad ordering, inconsistent
+ * lines), ABILU_EPATTERN (index out of range). */
+abilu_status abilu_order(int32_t n, const int32_t *h_rowptr, const int32_t *h_colidx, const int32_t *h_line_of,
+                         const int32_t *h_line_pos, int32_t ordering, int32_t *h_new_of_old);
+
 /* Workspace bytes needed by abilu_factor, abilu_apply, abilu_ilu_residual and, when
  * fgmres_restart > 0, fgmres_solve with that restart length. */
 size_t abilu_workspace_bytes(const abilu_pattern *p, abilu_prec prec, int32_t fgmres_restart);

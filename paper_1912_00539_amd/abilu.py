@@ -117,6 +117,8 @@ def lib():
             "abilu_pattern_chunk_info": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                           C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)], st),
             "abilu_pattern_chunk_export": ([vp, i32, vp, vp, vp, vp], st),
+            "abilu_find_lines": ([i32, vp, vp, vp, C.c_double, C.c_double, vp, vp, C.POINTER(i32)], st),
+            "abilu_order": ([i32, vp, vp, vp, vp, i32, vp], st),
             "abilu_workspace_bytes": ([vp, st, i32], sz),
             "abilu_factor": ([vp, vp, vp, vp, st, i32, st, st, vp, sz, vp], st),
             "abilu_apply": ([vp, vp, vp, st, vp, vp, i32, st, vp, sz, vp], st),
@@ -236,6 +238,41 @@ def abilu_pattern_chunk_info(p: Pattern) -> dict:
 def abilu_pattern_chunk_export(p: Pattern, upper: bool, order=None, lvptr=None, lvstart=None, stream=None):
     _check(lib().abilu_pattern_chunk_export(p.handle, int(bool(upper)), _ptr(order), _ptr(lvptr), _ptr(lvstart),
                                             _stream(stream)), "abilu_pattern_chunk_export")
+
+
+ORDERINGS = {"rcm": 0, "1wd": 1, "line": 2, "line_rcm": 3, "line_1wd": 4}
+
+
+def _host_i32(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def abilu_find_lines(n: int, rowptr, colidx, weight, threshold: float = 10.0, strong_ratio: float = 4.0):
+    """Lines of anisotropic cells on host arrays: (line_of int32[n], line_pos int32[n], nlines)."""
+    import numpy as np
+    rp, ci = _host_i32(rowptr), _host_i32(colidx)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    lo = np.empty(max(n, 1), np.int32)
+    lp = np.empty(max(n, 1), np.int32)
+    nl = C.c_int32()
+    _check(lib().abilu_find_lines(int(n), rp.ctypes.data, ci.ctypes.data, w.ctypes.data, float(threshold),
+                                  float(strong_ratio), lo.ctypes.data, lp.ctypes.data, C.byref(nl)),
+           "abilu_find_lines")
+    return lo[:n], lp[:n], nl.value
+
+
+def abilu_order(n: int, rowptr, colidx, ordering: str, line_of=None, line_pos=None):
+    """new_of_old int32[n] of an ordering computed on host arrays."""
+    import numpy as np
+    rp, ci = _host_i32(rowptr), _host_i32(colidx)
+    lo = _host_i32(line_of) if line_of is not None else None
+    lp = _host_i32(line_pos) if line_pos is not None else None
+    out = np.empty(max(n, 1), np.int32)
+    _check(lib().abilu_order(int(n), rp.ctypes.data, ci.ctypes.data, None if lo is None else lo.ctypes.data,
+                             None if lp is None else lp.ctypes.data, ORDERINGS[ordering], out.ctypes.data),
+           "abilu_order")
+    return out[:n]
 
 
 def abilu_workspace_bytes(p: Pattern, prec: str = "f32", fgmres_restart: int = 0) -> int:

@@ -56,6 +56,14 @@ def build(verbose: bool = True, jobs: int = 8) -> str:
     for src0, p0 in procs:
         if p0.wait() != 0:
             raise RuntimeError(f"hipcc failed on {src0}")
+    # host-only C++ (orderings)
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.cpp"))):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-I", INCLUDE, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
     tl = torch_lib_dir()
     if tl:
         # link against torch's HIP runtime: NEEDED libamdhip64.so resolves to the copy torch loaded
