@@ -384,10 +384,12 @@ def configs_bench(args):
 
 def orderings_bench(args):
     """Orderings of mesh cells (Section 5) computed by the library (host), the same seeded matrix
-    assembled in each, then the step (asynchronous FP32 preconditioner, 1 build sweep, 3 apply
-    sweep pairs, FGMRES to rtol): on the 500,000-cell boundary-layer mesh (lines found from the
-    geometric face couplings, anisotropy threshold 10, strong-link ratio 4) and on the
-    180,000-triangle mesh from a random numbering (RCM, 1WD)."""
+    assembled in each, then the step (FP32 preconditioner, 1 build sweep, 3 apply sweep pairs,
+    FGMRES to rtol) with unchunked asynchronous sweeps and with chunked ones (Gauss-Seidel within
+    chunks of consecutive rows, where the ordering decides which dependencies fall inside a chunk):
+    on the 500,000-cell boundary-layer mesh (lines found from the geometric face couplings,
+    anisotropy threshold 10, strong-link ratio 4; 16-row chunks) and on the 180,000-triangle mesh
+    from a random numbering (RCM, 1WD; 64-row chunks)."""
     import numpy as np
     import torch
     from paper_1912_00539_amd import abilu as L
@@ -395,9 +397,9 @@ def orderings_bench(args):
     from paper_1912_00539_amd.runtime import DeviceSystem
     out = {}
     studies = (("aniso1000", W.aniso_quad_mesh(1000, 500), "natural", 100.0,
-                ("line_columns", "rcm", "1wd", "line", "line_rcm", "line_1wd")),
-               ("tri300", W.split_tri_mesh(300, 300, args.serve_seed), "random", 100.0, ("random", "rcm", "1wd")))
-    for label, m, start, cfl, names in studies:
+                ("line_columns", "rcm", "1wd", "line", "line_rcm", "line_1wd"), 16),
+               ("tri300", W.split_tri_mesh(300, 300, args.serve_seed), "random", 100.0, ("random", "rcm", "1wd"), 64))
+    for label, m, start, cfl, names, R in studies:
         seed = args.serve_seed
         if start == "natural":
             base = W.natural_order(m)
@@ -410,7 +412,7 @@ def orderings_bench(args):
         lo, lp, nl = L.abilu_find_lines(c0.n, c0.rowptr, c0.colidx, wgt, 10.0, 4.0)
         t_lines = time.perf_counter() - t
         rows = {"n": c0.n, "lines": nl, "cells_in_lines": int((lo >= 0).sum()),
-                "find_lines_ms": round(t_lines * 1e3, 1)}
+                "find_lines_ms": round(t_lines * 1e3, 1), "rows_per_chunk": R}
         for name in names:
             t = time.perf_counter()
             if name == "line_columns":
@@ -423,14 +425,17 @@ def orderings_bench(args):
             t_ord = time.perf_counter() - t
             c = W.assemble(m, new if name != "random" else base, seed, "cfl", cfl=cfl)
             s = DeviceSystem(c, prec="f32", restart=args.restart)
-            run_steps(s, args, "async", 1, profile=False)
-            nst = 3
-            secs, res = run_steps(s, args, "async", nst, profile=False)[:2]
-            rows[name] = {"ilu_residual": float(f"{s.ilu_residual():.4e}"),
-                          "fgmres_iters": [r["iters"] for _, r in res],
-                          "max_rel_true_residual": max(r["rel_true_residual"] for _, r in res),
-                          "ms_per_step": round(secs * 1e3 / nst, 3),
-                          "ordering_ms": None if name in ("line_columns", "random") else round(t_ord * 1e3, 1)}
+            rows[name] = {"ordering_ms": None if name in ("line_columns", "random") else round(t_ord * 1e3, 1)}
+            for mode in ("async", "chunk_async"):
+                if mode == "chunk_async":
+                    rows[name]["chunk_runner"] = s.set_chunks(R)["runner"]
+                run_steps(s, args, mode, 1, profile=False)
+                nst = 3
+                secs, res = run_steps(s, args, mode, nst, profile=False)[:2]
+                rows[name][mode] = {"ilu_residual": float(f"{s.ilu_residual():.4e}"),
+                                    "fgmres_iters": [r["iters"] for _, r in res],
+                                    "max_rel_true_residual": max(r["rel_true_residual"] for _, r in res),
+                                    "ms_per_step": round(secs * 1e3 / nst, 3)}
             log(f"ordering {label} {name}: {rows[name]}")
             del s
             torch.cuda.empty_cache()
