@@ -1,5 +1,6 @@
 // Exclusive prefix sums of int64 counts on the device (3 phases: per-tile scan, scan of the
-// tile totals in one workgroup, add), used by the pattern analysis and the request generator.
+// tile totals in one workgroup, add of each tile's offset), used by the pattern analysis, the
+// chunk schedules and the request generator.
 #include "setup_kernels.h"
 
 namespace {
@@ -16,7 +17,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_totals(int ntiles, int64_t *__r
     scan_totals_body(ntiles, tot, grand);
 }
 
-__global__ void k_scan_finish(int64_t len, const int64_t *__restrict__ scan, const int64_t *__restrict__ tot,
+__global__ __launch_bounds__(SCAN_T) void k_scan_finish(int64_t len, const int64_t *__restrict__ scan, const int64_t *__restrict__ tot,
                               const int64_t *__restrict__ grand, int64_t *__restrict__ ptr64,
                               int32_t *__restrict__ ptr32) {
     scan_finish_body(blockIdx.x, len, scan, tot, grand, ptr64, ptr32);
@@ -36,7 +37,7 @@ hipError_t scan_exclusive(int64_t len, const int64_t *in, int64_t *tmp, int64_t 
     if (e != hipSuccess) return e;
     k_scan_totals<<<1, SCAN_T, 0, s>>>(nt, tot, tot + nt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_scan_finish<<<div_up(len + 1, 256), 256, 0, s>>>(len, tmp, tot, tot + nt, out64, out32);
+    k_scan_finish<<<div_up(len + 1, SCAN_TILE), SCAN_T, 0, s>>>(len, tmp, tot, tot + nt, out64, out32);
     return hipGetLastError();
 }
 

@@ -271,13 +271,16 @@ __global__ __launch_bounds__(abilu_setup::SCAN_T) void kbs_scan_totals(const Set
     abilu_setup::scan_totals_body(nt, D.tot, D.tot + nt);
 }
 
-__global__ void kbs_scan_finish(const SetupDesc *sd, const Member *mem, int nmem, int which, int64_t *adm) {
+__global__ __launch_bounds__(abilu_setup::SCAN_T) void kbs_scan_finish(const SetupDesc *sd, const Member *mem,
+                                                                       int nmem, int which, int64_t *adm) {
     SMEMBER();
     const int64_t len = scan_len(D, which);
     const int nt = div_up(len > 0 ? len : 1, abilu_setup::SCAN_TILE);
     int32_t *out32 = which == SC_ROWPTR ? D.rowptr : (which == SC_LROW ? D.lrow : (which == SC_UROW ? D.urow : D.pair_ptr));
     abilu_setup::scan_finish_body(blk, len, D.tmp, D.tot, D.tot + nt, which == SC_PAIR ? D.ptr64 : nullptr, out32);
-    if (which != SC_ROWPTR && (int64_t)blk * blockDim.x + threadIdx.x == len) adm[4 * m_ + which] = D.tot[nt];
+    // the member's last workgroup (the one holding index len) records the total for admission
+    if (which != SC_ROWPTR && threadIdx.x == 0 && (int64_t)blk == len / abilu_setup::SCAN_TILE)
+        adm[4 * m_ + which] = D.tot[nt];
 }
 
 __global__ void kbs_pat_rows(const SetupDesc *sd, const Member *mem, int nmem, int64_t *adm) {
@@ -524,8 +527,8 @@ int setup_tiles(const Req &r, int shape) {
         case SS_ROW128: return div_up(n, 128);
         case SS_SCAN_N: return div_up(n > 0 ? n : 1, abilu_setup::SCAN_TILE);
         case SS_SCAN_Z: return div_up(Z > 0 ? Z : 1, abilu_setup::SCAN_TILE);
-        case SS_FIN_N: return div_up(n + 1, 256);
-        case SS_FIN_Z: return div_up(Z + 1, 256);
+        case SS_FIN_N: return div_up(n + 1, abilu_setup::SCAN_TILE);
+        case SS_FIN_Z: return div_up(Z + 1, abilu_setup::SCAN_TILE);
         default: return 1;
     }
 }
@@ -566,7 +569,7 @@ abilu_status launch_scan(abilu_server *s, const SetupTables &T, int which) {
     if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
     kbs_scan_totals<<<T.tiles[SS_ONE], abilu_setup::SCAN_T, 0, st>>>(s->d_sdesc, T.d[SS_ONE], T.count, which);
     if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
-    kbs_scan_finish<<<T.tiles[z ? SS_FIN_Z : SS_FIN_N], 256, 0, st>>>(s->d_sdesc, T.d[z ? SS_FIN_Z : SS_FIN_N],
+    kbs_scan_finish<<<T.tiles[z ? SS_FIN_Z : SS_FIN_N], abilu_setup::SCAN_T, 0, st>>>(s->d_sdesc, T.d[z ? SS_FIN_Z : SS_FIN_N],
                                                                       T.count, which, s->d_adm);
     return launch_status();
 }

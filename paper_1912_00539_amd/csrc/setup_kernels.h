@@ -73,14 +73,21 @@ __device__ __forceinline__ void scan_totals_body(int ntiles, int64_t *__restrict
 __device__ __forceinline__ void scan_finish_body(int blk, int64_t len, const int64_t *__restrict__ scan, const int64_t *__restrict__ tot,
                               const int64_t *__restrict__ grand, int64_t *__restrict__ ptr64,
                               int32_t *__restrict__ ptr32) {
-    int64_t e = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (e < len) {
-        int64_t v = scan[e] + tot[e / SCAN_TILE];
-        if (ptr64) ptr64[e] = v;
-        ptr32[e] = (int32_t)v;
-    } else if (e == len) {
-        if (ptr64) ptr64[len] = *grand;
-        ptr32[len] = (int32_t)*grand;
+    // one scan tile per workgroup (SCAN_T threads, SCAN_E elements each, strided for coalescing);
+    // the workgroup past the last full tile also writes the grand total at index len
+    const int64_t first = (int64_t)blk * SCAN_TILE;
+    const int64_t add = first < len ? tot[blk] : 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_E; ++q) {
+        const int64_t e = first + (int64_t)q * SCAN_T + threadIdx.x;
+        if (e < len) {
+            const int64_t v = scan[e] + add;
+            if (ptr64) ptr64[e] = v;
+            ptr32[e] = (int32_t)v;
+        } else if (e == len) {
+            if (ptr64) ptr64[len] = *grand;
+            ptr32[len] = (int32_t)*grand;
+        }
     }
 }
 
