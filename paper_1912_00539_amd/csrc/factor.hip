@@ -88,8 +88,8 @@ __global__ __launch_bounds__(WG) void k_factor_sweep_chunk(
     for (int l = 0; l < nl; ++l) {
         const int p1 = lvstart[b + l + 1];
         for (int q = lvstart[b + l] + quad; q < p1; q += ROWS_PER_WG)
-            factor_chunk_row<T, OUT_FROM_A>(order[q], c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow,
-                                            pair_ptr, pkj, sik, skj, A, XO, DO, Xn, Dn, flags);
+            factor_chunk_row<T, OUT_FROM_A, false>(order[q], c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow,
+                                                   pair_ptr, pkj, sik, skj, A, XO, DO, Xn, Dn, flags);
         __syncthreads();
     }
 }
@@ -109,8 +109,8 @@ __global__ __launch_bounds__(WG) void k_factor_sweep_chunk_rows(
     const int c0 = c * R, c1 = min(n, c0 + R);
     const int ubound = ZL + n + urow[c0];
     for (int i = c0; i < c1; ++i)
-        factor_chunk_row<T, OUT_FROM_A>(i, c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, pkj,
-                                        sik, skj, A, XO, DO, Xn, Dn, flags);
+        factor_chunk_row<T, OUT_FROM_A, true>(i, c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr,
+                                              pkj, sik, skj, A, XO, DO, Xn, Dn, flags);
 }
 
 // Conversions between the factor layout and CSR order (one quad per block row).

@@ -508,27 +508,50 @@ __device__ __forceinline__ void factor_sweep_row(int i,
 // t -= sum over the update set [p0, p1) of X_ik X_kj for a row of a chunk (chunked sweeps).
 // X_ik is a block of this row and comes from Xn (this sweep). X_kj lies in the strictly upper part
 // of row k < i: rows of the chunk (factor-layout position >= ubound) come from Xn, earlier rows
-// from XO, or from A at CSR positions when OUT_FROM_A (the first sweep from X0 = A).
+// from XO, or from A at CSR positions when OUT_FROM_A (the first sweep from X0 = A). PAIR2 takes
+// the pairs two at a time (clamped index loads, then the four block rows) so that a row's chain of
+// dependent loads is short, at the cost of registers; either way the products are subtracted in
+// the list's order, so both forms give the same values.
 template <typename T, bool OUT_FROM_A>
+__device__ __forceinline__ void load_u_chunk(int q, int sp, int ubound, int r, const int32_t *__restrict__ pkj,
+                                             const double *__restrict__ A, const T *Xn, const T *XO, T (&u)[4]) {
+    if (sp >= ubound) load_block_row(Xn, sp, r, u);
+    else if constexpr (OUT_FROM_A) load_block_row(A, pkj[q], r, u);
+    else load_block_row(XO, sp, r, u);
+}
+
+template <typename T, bool OUT_FROM_A, bool PAIR2>
 __device__ __forceinline__ void update_terms_chunk(int p0, int p1, int r, int ubound, const int32_t *__restrict__ pkj,
                                                    const int32_t *__restrict__ sik, const int32_t *__restrict__ skj,
                                                    const double *__restrict__ A, const T *Xn, const T *XO,
                                                    T (&t)[4]) {
-    for (int q = p0; q < p1; ++q) {
-        T l[4], u[4];
-        load_block_row(Xn, sik[q], r, l);
-        const int sp = skj[q];
-        if (sp >= ubound) load_block_row(Xn, sp, r, u);
-        else if constexpr (OUT_FROM_A) load_block_row(A, pkj[q], r, u);
-        else load_block_row(XO, sp, r, u);
-        row_times_block_sub(l, u, t);
+    if constexpr (PAIR2) {
+        for (int q0 = p0; q0 < p1; q0 += 2) {
+            const int qb = min(q0 + 1, p1 - 1);
+            const int sa = sik[q0], sb = sik[qb];
+            const int ka = skj[q0], kb = skj[qb];
+            T la[4], lb[4], ua[4], ub[4];
+            load_block_row(Xn, sa, r, la);
+            load_block_row(Xn, sb, r, lb);
+            load_u_chunk<T, OUT_FROM_A>(q0, ka, ubound, r, pkj, A, Xn, XO, ua);
+            load_u_chunk<T, OUT_FROM_A>(qb, kb, ubound, r, pkj, A, Xn, XO, ub);
+            row_times_block_sub(la, ua, t);
+            if (q0 + 1 < p1) row_times_block_sub(lb, ub, t);
+        }
+    } else {
+        for (int q = p0; q < p1; ++q) {
+            T l[4], u[4];
+            load_block_row(Xn, sik[q], r, l);
+            load_u_chunk<T, OUT_FROM_A>(q, skj[q], ubound, r, pkj, A, Xn, XO, u);
+            row_times_block_sub(l, u, t);
+        }
     }
 }
 
 // One chunked sweep over block row i of the chunk starting at row c0: the blocks of the row in
 // ascending column order, each stored before the next is computed (a Gauss-Seidel order within
 // the row), reading the chunk's rows from this sweep (Xn, Dn) and earlier rows from XO, DO.
-template <typename T, bool OUT_FROM_A>
+template <typename T, bool OUT_FROM_A, bool PAIR2>
 __device__ __forceinline__ void factor_chunk_row(int i, int c0, int ubound,
     int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
@@ -540,23 +563,46 @@ __device__ __forceinline__ void factor_chunk_row(int i, int c0, int ubound,
     T *XnL = Xn + (int64_t)lrow[i] * BB;
     T *XnU = Xn + ((int64_t)ZL + n + urow[i]) * BB;
     unsigned fl = 0;
-    // strictly lower blocks: L_ij = (A_ij - sum) U_jj^{-1}, U_jj^{-1} of this sweep if j is in the chunk
-    for (int e = b0; e < d; ++e) {
-        T t[4], dr[4];
-        load_row(A + (int64_t)e * BB, r, t);
-        const int j = colidx[e];
-        load_row((j >= c0 ? (const T *)Dn : DO) + (int64_t)j * BB, r, dr);
-        update_terms_chunk<T, OUT_FROM_A>(pair_ptr[e], pair_ptr[e + 1], r, ubound, pkj, sik, skj, A, Xn, XO, t);
-        T x[4];
-        row_times_block(t, dr, x);
-        fl |= nonfinite4(x);
-        store_row(XnL + (int64_t)(e - b0) * BB, r, x);
+    // strictly lower blocks: L_ij = (A_ij - sum) U_jj^{-1}, U_jj^{-1} of this sweep if j is in the
+    // chunk. With PAIR2 and no update terms in the row's lower part the blocks are independent and
+    // are computed two at a time; otherwise one at a time, each seeing the ones before it.
+    if (PAIR2 && pair_ptr[d] == pair_ptr[b0]) {
+        for (int e0 = b0; e0 < d; e0 += 2) {
+            const int eb = min(e0 + 1, d - 1);
+            T ta[4], tb[4], da[4], db[4];
+            load_row(A + (int64_t)e0 * BB, r, ta);
+            load_row(A + (int64_t)eb * BB, r, tb);
+            const int ja = colidx[e0], jb = colidx[eb];
+            load_row((ja >= c0 ? (const T *)Dn : DO) + (int64_t)ja * BB, r, da);
+            load_row((jb >= c0 ? (const T *)Dn : DO) + (int64_t)jb * BB, r, db);
+            T xa[4], xb[4];
+            row_times_block(ta, da, xa);
+            row_times_block(tb, db, xb);
+            fl |= nonfinite4(xa);
+            store_row(XnL + (int64_t)(e0 - b0) * BB, r, xa);
+            if (e0 + 1 < d) {
+                fl |= nonfinite4(xb);
+                store_row(XnL + (int64_t)(e0 + 1 - b0) * BB, r, xb);
+            }
+        }
+    } else {
+        for (int e = b0; e < d; ++e) {
+            T t[4], dr[4];
+            load_row(A + (int64_t)e * BB, r, t);
+            const int j = colidx[e];
+            load_row((j >= c0 ? (const T *)Dn : DO) + (int64_t)j * BB, r, dr);
+            update_terms_chunk<T, OUT_FROM_A, PAIR2>(pair_ptr[e], pair_ptr[e + 1], r, ubound, pkj, sik, skj, A, Xn, XO, t);
+            T x[4];
+            row_times_block(t, dr, x);
+            fl |= nonfinite4(x);
+            store_row(XnL + (int64_t)(e - b0) * BB, r, x);
+        }
     }
     // diagonal block U_ii = A_ii - sum and its inverse
     {
         T t[4];
         load_row(A + (int64_t)d * BB, r, t);
-        update_terms_chunk<T, OUT_FROM_A>(pair_ptr[d], pair_ptr[d + 1], r, ubound, pkj, sik, skj, A, Xn, XO, t);
+        update_terms_chunk<T, OUT_FROM_A, PAIR2>(pair_ptr[d], pair_ptr[d + 1], r, ubound, pkj, sik, skj, A, Xn, XO, t);
         fl |= nonfinite4(t);
         store_row(Xn + ((int64_t)ZL + i) * BB, r, t);
         T M[16], out[4];
@@ -572,7 +618,7 @@ __device__ __forceinline__ void factor_chunk_row(int i, int c0, int ubound,
 #pragma unroll
         for (int u = 0; u < CH; ++u)
             if (e0 + u < b1)
-                update_terms_chunk<T, OUT_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, ubound, pkj, sik, skj,
+                update_terms_chunk<T, OUT_FROM_A, PAIR2>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, ubound, pkj, sik, skj,
                                                   A, Xn, XO, t[u]);
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
