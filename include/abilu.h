@@ -225,6 +225,8 @@ size_t abilu_workspace_bytes(const abilu_pattern *p, abilu_prec prec, int32_t fg
  *                     overwritten as soon as they are computed and later updates read whatever
  *                     values are in memory; sums accumulate in registers only; no atomics on
  *                     values. One kernel launch per sweep bounds the delay by one sweep.
+ *   mode ABILU_ASYNC_SERIAL, ABILU_CHUNK_SYNC, ABILU_CHUNK_ASYNC: see abilu_mode (the chunked
+ *                     modes need the pattern's chunk schedule, else ABILU_EINVAL).
  *   init  ABILU_INIT_FROM_A : initial guess X0 = A (the paper's choice, Section 6 setup)
  *         ABILU_INIT_FROM_LU: warm start from the values already in d_LU (Section 3.3 notes the
  *                             previous time step's factors may serve as the initial guess)
@@ -249,8 +251,11 @@ abilu_status abilu_factor(const abilu_pattern *p, const double *d_A, void *d_LU,
  * nsweeps forward sweeps then nsweeps backward sweeps (nsweeps = 0: z = r, no preconditioning).
  * SYNC sweeps read the previous sweep's vector; ASYNC sweeps update the vector in place. From the
  * zero initial guess the first sweeps are y = r and z = U_ii^{-1} y and are taken in that closed
- * form (not launched) in both modes. ABILU_ASYNC_SERIAL runs every sweep, forward rows ascending
- * and backward rows descending, from zero vectors.
+ * form (not launched) in these two modes. ABILU_ASYNC_SERIAL runs every sweep, forward rows
+ * ascending and backward rows descending, from zero vectors. The chunked modes launch every sweep;
+ * within a chunk a forward sweep is a forward substitution and a backward sweep a backward
+ * substitution, entries of other chunks being those of the previous sweep (CHUNK_SYNC) or in memory
+ * (CHUNK_ASYNC), zero in the first sweep.
  *   d_r double[4N] (read), d_z double[4N] (written; must not alias d_r)
  *   intermediate vectors are stored in prec; d_r is rounded to prec on load.
  * Non-blocking. Errors: ABILU_EINVAL, ABILU_EDEVICE.
