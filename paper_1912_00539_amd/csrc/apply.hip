@@ -22,8 +22,8 @@ namespace {
 
 
 // Forward sweep over the strictly lower part of the factor layout (lrow/lcol/Lb).
-// Each quad owns rows ib and ib + 64 and loads two blocks of each per step (clamped, so the
-// loads are branch-free); a row with fewer blocks reads index 0 of the part, which exists
+// Each quad owns rpq<T>() rows (ib, ib + 64) and loads two blocks of each per step (clamped, so
+// the loads are branch-free); a row with fewer blocks reads index 0 of the part, which exists
 // whenever the loop runs, and discards the product.
 template <typename T, typename YI, bool EMIT_Z>
 __global__ __launch_bounds__(WG) void k_fwd(int n, const int32_t *__restrict__ lrow, const int32_t *__restrict__ lcol,
@@ -219,7 +219,7 @@ template <typename T>
 abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const double *r, double *z, int nsw,
                      abilu_mode mode, char *work, const Workspace &W, hipStream_t s) {
     const int n = p->n;
-    const int grid = div_up(n, ROWS_PER_WG2);
+    const int grid = div_up(n, rows_per_wg2<T>());
     const T *Lb = LU;                                              // strictly lower part
     const T *Ub = LU + ((int64_t)p->nnzb_lower + n) * BB;          // strictly upper part
     const int32_t *lrow = p->lrow, *lcol = p->lcol, *urow = p->urow, *ucol = p->ucol;

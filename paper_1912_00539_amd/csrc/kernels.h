@@ -11,8 +11,12 @@ using namespace abilu;
 using namespace abilu_dev;
 
 constexpr int CH = 2;                        // factor sweep: blocks of a row loaded together
-constexpr int RPQ = 2;                       // apply sweeps: block rows per quad
-constexpr int ROWS_PER_WG2 = RPQ * ROWS_PER_WG;
+// apply sweeps: block rows per quad (FP32: two rows keep enough loads in flight; FP64 rows carry
+// twice the bytes and run faster one per quad) and rows per workgroup
+template <typename T>
+constexpr int rpq() { return sizeof(T) == 8 ? 1 : 2; }
+template <typename T>
+constexpr int rows_per_wg2() { return rpq<T>() * ROWS_PER_WG; }
 constexpr int MAX_RESTART = 256;
 
 // status slots (double[8] in the workspace header, copied to the host)
@@ -51,12 +55,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ bool skipped(const int *guard) { return guard && *guard == 0; }
 
-// Forward sweep on rows ib and ib + stride (RPQ rows per quad; rows >= n are skipped).
+// Forward sweep on rows ib, ib + stride, ... (rpq<T>() rows per quad; rows >= n are skipped).
 template <typename T, typename YI, bool EMIT_Z>
 __device__ __forceinline__ void fwd_rows(int ib, int stride, int n, const int32_t *__restrict__ lrow,
                                          const int32_t *__restrict__ lcol, const T *__restrict__ Lb,
                                          const double *__restrict__ rhs, const YI *yin, T *yout,
                                          const T *__restrict__ Dinv, T *__restrict__ zout) {
+    constexpr int RPQ = rpq<T>();
     const int r = threadIdx.x & 3;
     if (ib >= n) return;
     int ii[RPQ], b0[RPQ], b1[RPQ];
@@ -115,16 +120,17 @@ template <typename T, typename YI, bool EMIT_Z>
 __device__ __forceinline__ void fwd_body(int blk, int n, const int32_t *__restrict__ lrow, const int32_t *__restrict__ lcol,
                                             const T *__restrict__ Lb, const double *__restrict__ rhs, const YI *yin,
                                             T *yout, const T *__restrict__ Dinv, T *__restrict__ zout) {
-    fwd_rows<T, YI, EMIT_Z>(blk * ROWS_PER_WG2 + (threadIdx.x >> 2), ROWS_PER_WG, n, lrow, lcol, Lb, rhs, yin, yout,
+    fwd_rows<T, YI, EMIT_Z>(blk * rows_per_wg2<T>() + (threadIdx.x >> 2), ROWS_PER_WG, n, lrow, lcol, Lb, rhs, yin, yout,
                             Dinv, zout);
 }
 
-// Backward sweep on rows ib and ib + stride.
+// Backward sweep on rows ib, ib + stride, ... (rpq<T>() rows per quad).
 template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
 __device__ __forceinline__ void bwd_rows(int ib, int stride, int n, const int32_t *__restrict__ urow,
                                          const int32_t *__restrict__ ucol, const T *__restrict__ Ub,
                                          const T *__restrict__ Dinv, const YI *__restrict__ y, const T *zin, ZO *zout,
                                          T *zout2) {
+    constexpr int RPQ = rpq<T>();
     const int r = threadIdx.x & 3;
     if (ib >= n) return;
     int ii[RPQ], b0[RPQ], b1[RPQ];
@@ -186,7 +192,7 @@ template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
 __device__ __forceinline__ void bwd_body(int blk, int n, const int32_t *__restrict__ urow, const int32_t *__restrict__ ucol,
                                             const T *__restrict__ Ub, const T *__restrict__ Dinv,
                                             const YI *__restrict__ y, const T *zin, ZO *zout, T *zout2) {
-    bwd_rows<T, YI, ZO, OFFDIAG, DUAL>(blk * ROWS_PER_WG2 + (threadIdx.x >> 2), ROWS_PER_WG, n, urow, ucol, Ub, Dinv, y,
+    bwd_rows<T, YI, ZO, OFFDIAG, DUAL>(blk * rows_per_wg2<T>() + (threadIdx.x >> 2), ROWS_PER_WG, n, urow, ucol, Ub, Dinv, y,
                                        zin, zout, zout2);
 }
 

@@ -763,17 +763,17 @@ abilu_status admit_queued(abilu_server *s, int64_t cell_budget) {
 }
 
 // ---- per-tick member tables
-enum Shape { SH_ROW64 = 0, SH_ROW128, SH_VEC, SH_COLSQ, SH_ONE, SH_COUNT };
+enum Shape { SH_ROW64 = 0, SH_APPLY, SH_VEC, SH_COLSQ, SH_ONE, SH_COUNT };   // SH_APPLY: rows_per_wg2<T>() rows
 
 struct Table {
     const Member *d = nullptr;
     int count = 0, tiles = 0;
 };
 
-int tiles_of(const Req &r, int shape, State g) {
+int tiles_of(const Req &r, int shape, State g, abilu_prec prec) {
     switch (shape) {
         case SH_ROW64: return div_up(r.n, ROWS_PER_WG);
-        case SH_ROW128: return div_up(r.n, ROWS_PER_WG2);
+        case SH_APPLY: return div_up(r.n, prec == ABILU_F32 ? rows_per_wg2<float>() : rows_per_wg2<double>());
         case SH_VEC: return r.L.nb_vec;
         case SH_COLSQ: return g == Q_ITER ? r.k + 2 : 1;
         default: return 1;
@@ -874,11 +874,11 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
     auto fwd = [&](const char *name, bool yin_f64, bool emit, int yin, int yout) -> abilu_status {
         ProfScope ps(name, st, B([&](const Sizes &z, const Req &) { return bytes_fwd(z, sF, yin_f64 ? 8 : sF, emit); }));
         if (yin_f64) {
-            if (emit) kb_fwd<T, double, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yin, yout);
-            else kb_fwd<T, double, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yin, yout);
+            if (emit) kb_fwd<T, double, true><<<L_(SH_APPLY)>>>(A_(SH_APPLY), yin, yout);
+            else kb_fwd<T, double, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), yin, yout);
         } else {
-            if (emit) kb_fwd<T, T, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yin, yout);
-            else kb_fwd<T, T, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), yin, yout);
+            if (emit) kb_fwd<T, T, true><<<L_(SH_APPLY)>>>(A_(SH_APPLY), yin, yout);
+            else kb_fwd<T, T, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), yin, yout);
         }
         CKL();
         return ABILU_OK;
@@ -949,7 +949,7 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
         } else if (nsw == 1) {
             ProfScope ps("serve_apply_diag", st,
                          B([&](const Sizes &z, const Req &) { return 32 * z.N + 16 * sF * z.N + 32 * z.N; }));
-            kb_bwd<T, double, double, false, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), R_VK, R_ZA, R_ZK);
+            kb_bwd<T, double, double, false, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), R_VK, R_ZA, R_ZK);
             CKL();
         } else {
             // sweep 1 forward is y = v_k and sweep 1 backward z = Dinv y (emitted by the last forward
@@ -969,11 +969,11 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
                 ProfScope ps(last ? "serve_apply_bwd_last" : "serve_apply_bwd", st,
                              B([&](const Sizes &z, const Req &) { return bytes_bwd(z, sF, last ? 8 : sF, dual); }));
                 if (last) {
-                    if (dual) kb_bwd<T, T, double, true, true><<<L_(SH_ROW128)>>>(A_(SH_ROW128), ycur, zprev, R_ZK);
-                    else kb_bwd<T, T, double, true, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), ycur, zprev, R_ZK);
+                    if (dual) kb_bwd<T, T, double, true, true><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, R_ZK);
+                    else kb_bwd<T, T, double, true, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, R_ZK);
                 } else {
                     const int zcur = sync ? ((zprev == R_ZA) ? R_ZB : R_ZA) : R_ZA;
-                    kb_bwd<T, T, T, true, false><<<L_(SH_ROW128)>>>(A_(SH_ROW128), ycur, zprev, zcur);
+                    kb_bwd<T, T, T, true, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, zcur);
                     zprev = zcur;
                 }
                 CKL();
@@ -1096,7 +1096,7 @@ abilu_status step_impl(abilu_server *s, hipStream_t st) {
             for (size_t q = 0; q < G.ids.size(); ++q) {
                 const Req &r = s->reqs[G.ids[q]];
                 s->h_tab[used + q] = Member{r.slot, tile, r.k, 0};
-                tile += tiles_of(r, sh, G.st);
+                tile += tiles_of(r, sh, G.st, (abilu_prec)s->cfg.prec);
             }
             T.tiles = tile;
             used += T.count;
