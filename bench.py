@@ -524,8 +524,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus} GPUs, WORLD_SIZE={world}); "
-              "the multi-GPU design is described but not built", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU (asked for {args.gpus} GPUs, WORLD_SIZE={world}); "
+              "a multi-GPU decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
