@@ -400,3 +400,39 @@ def test_full_size_aniso1000_line_chunk_sync():
     s32.factor(1, "chunk_async")
     st, res = s32.solve(apply_sweeps=3, mode="chunk_async", rtol=1e-2, maxit=300)
     assert st == 0 and res["converged"]
+
+
+# ------------------------------------------------------------------ orderings + chunked sweeps, end to end
+def test_line_ordering_then_chunked_sweeps():
+    """Section 5 with the chunk schedule of Section 3.3: the library finds lines on a boundary-layer
+    mesh from its geometric couplings, orders it line-RCM (and RCM for comparison), and the same
+    seeded matrix is assembled in each order. One CHUNK_SYNC FP64 sweep (16-row chunks) matches
+    the chunked oracle; under line-RCM each chunk runs along a wall-normal line and its ILU residual
+    is well below RCM's (2.3e-3 against 9.6e-3 in the oracle for this case). An asynchronous
+    chunked FP32 solve then converges, its true residual confirmed by the oracle SpMV."""
+    from paper_1912_00539_amd import abilu as L
+    m = W.aniso_quad_mesh(60, 40)
+    base = W.natural_order(m)
+    c0 = W.assemble(m, base, 3, "cfl", cfl=100.0)
+    w = W.block_face_weights(m, base, c0.rowptr, c0.colidx)
+    lo, lp, nl = L.abilu_find_lines(c0.n, c0.rowptr, c0.colidx, w, 10.0, 4.0)
+    assert nl == 60
+    res = {}
+    for name in ("rcm", "line_rcm"):
+        new = L.abilu_order(c0.n, c0.rowptr, c0.colidx, name, lo, lp).astype(np.int64)
+        c = W.assemble(m, new, 3, "cfl", cfl=100.0)
+        s = DS(c, "f64", R=16)
+        s.factor(1, "chunk_sync")
+        X, D = s.factor_host()
+        Xo, Do, tx, td = chunk_tolerance(c, 1, 16, "f64")
+        assert rel(X, Xo) <= tx and rel(D, Do) <= td, name
+        res[name] = s.ilu_residual()
+        assert abs(res[name] - oracle.ilu_residual(c.n, c.rowptr, c.colidx, c.vals, Xo)) <= 1e-10 * res[name]
+        s32 = DS(c, "f32", restart=30, R=16)
+        s32.factor(1, "chunk_async")
+        st, r = s32.solve(apply_sweeps=3, mode="chunk_async", rtol=1e-6, maxit=300)
+        x = s32.x.cpu().numpy()
+        true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
+        assert st == 0 and r["converged"] and true <= 1e-6, (name, r)
+    print("ILU residual after one chunked sweep:", res)
+    assert res["line_rcm"] < 0.5 * res["rcm"]
