@@ -614,3 +614,20 @@ def test_warm_start_sequence_async_f32():
         assert st == 0 and res["converged"] and true <= 1e-2
         out.append((t, rw, rc, res["iters"]))
     print("step, ILU residual warm, cold, FGMRES iterations:", out)
+
+
+def test_fgmres_degenerate_right_hand_sides():
+    """b = 0: converged at once with x = 0 and no iteration (||b|| = 0 is taken as 1 in the
+    tolerance). An initial guess that already solves the system (computed by dense LU on the host):
+    the first true residual meets the tolerance and no iteration runs."""
+    c = get("quad32")
+    s = DS(c, "f64", restart=30)
+    s.factor(2, "sync")
+    s.b.zero_()
+    st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-8, maxit=50)
+    assert st == 0 and res["converged"] and res["iters"] == 0
+    assert float(s.x.abs().max()) == 0.0
+    s.b.copy_(torch.from_numpy(c.b))
+    xs = np.linalg.solve(c.dense(), c.b)
+    st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-8, maxit=50, x0=torch.from_numpy(xs).cuda())
+    assert st == 0 and res["converged"] and res["iters"] == 0 and res["rel_true_residual"] <= 1e-8
