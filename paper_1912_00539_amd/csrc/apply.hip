@@ -4,12 +4,15 @@
 //   forward  y_i <- r_i - sum_{j<i} L_ij y_j          (unit block diagonal: no inverse)
 //   backward z_i <- U_ii^{-1} (y_i - sum_{j>i} U_ij z_j)
 //
-// Each sweep is one launch over all block rows; a quad of 4 lanes owns one block row, lane r
-// owns component r: it reads row r of each block (contiguous across the quad) and element r of
-// the gathered 4-vector, the other three elements coming from the quad by DPP broadcast.
-// SYNC sweeps read the previous sweep's vector (ping-pong); ASYNC sweeps update in place.
-// From the zero initial guess the first SYNC forward sweep is y = r, so it is not launched; the
+// Each sweep is one launch over all block rows; a quad of 4 lanes owns rpq<T>() block rows (two in
+// FP32, one in FP64), lane r owns component r: it reads row r of each block (contiguous across the
+// quad) and element r of the gathered 4-vector, the other three elements coming from the quad by
+// DPP broadcast. SYNC sweeps read the previous sweep's vector (ping-pong); ASYNC sweeps update in
+// place. From the zero initial guess the first forward sweep is y = r, so it is not launched; the
 // last forward sweep also produces the first backward sweep z = Dinv y (its rows are at hand).
+// The chunked sweeps (a forward or backward substitution inside each chunk of consecutive rows)
+// run a chunk per workgroup level by level, or a chunk per quad row by row; the single-worker
+// sweeps run all rows in one quad.
 #include <type_traits>
 
 #include "kernels.h"

@@ -24,6 +24,9 @@
 //        U_ii uses the L_ik this quad has just written. The first sweep from A reads the X_kj of
 //        other rows from A itself (the initial guess, the oldest admissible value) and so needs no
 //        copy of A into X. Sums are accumulated in registers and stored once; no atomics on values.
+// CHUNK_SYNC / CHUNK_ASYNC: a Gauss-Seidel sweep inside each chunk of consecutive rows (rows of
+//        other chunks from the previous sweep, or as in memory), run a chunk per workgroup level
+//        by level or a chunk per quad row by row. ASYNC_SERIAL: every row in order by one quad.
 #include "kernels.h"
 
 using namespace abilu;
