@@ -282,8 +282,57 @@ def warm_start_bench(args):
                "all_converged": all(r[k]["converged"] for r in rows)} for k in ("cold", "warm")}
     del sysm
     torch.cuda.empty_cache()
-    return {"workload": f"{c.n}-cell split-quad triangles, {len(rows)} pseudo-time steps, CFL {cfls[0]:g} -> "
-                        f"{cfls[-1]:g}, 1% off-diagonal drift per step; async FP32, {args.build_sweeps} build sweep(s), "
+    out = {"workload": f"{c.n}-cell split-quad triangles, {len(rows)} pseudo-time steps, CFL {cfls[0]:g} -> "
+                       f"{cfls[-1]:g}, 1% off-diagonal drift per step; async FP32, {args.build_sweeps} build sweep(s), "
+                       f"{args.apply_sweeps} apply sweep pairs, FGMRES(30) to {args.rtol}",
+           "totals": tot, "steps": rows}
+    out["aniso1000_line_chunked"] = None if args.warm_steps_line <= 0 else warm_chunked_line(args)
+    return out
+
+
+def warm_chunked_line(args):
+    """The same kind of sequence on the 500,000-cell boundary-layer mesh in line order: unchunked
+    asynchronous sweeps from A, against chunked asynchronous sweeps (16-row chunks) from A (cold)
+    and from the previous step's factor (warm). One FP32 factor sweep per step, FGMRES(30)."""
+    import numpy as np
+    import torch
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    c = W.case("aniso1000", order="line")
+    cfls = W.cfl_ramp(args.warm_steps_line, 10.0, 1.5, 1000.0)
+    forms = {"async_cold": ("async", "A"), "chunk_cold": ("chunk_async", "A"), "chunk_warm": ("chunk_async", "LU")}
+    sysm = {k: DeviceSystem(c, prec="f32", restart=30) for k in forms}
+    for k, (mode, _) in forms.items():
+        if mode == "chunk_async":
+            sysm[k].set_chunks(16)
+    rows = []
+    for t, (vals, b) in enumerate(W.jacobian_sequence(c, cfls, drift=0.01, seed=args.serve_seed)):
+        row = {"step": t, "cfl": round(float(cfls[t]), 2)}
+        for k, (mode, init) in forms.items():
+            s = sysm[k]
+            s.load_values(vals, b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.factor(args.build_sweeps, mode, init=init if t > 0 else "A")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, res = s.solve(apply_sweeps=args.apply_sweeps, mode=mode, rtol=args.rtol, maxit=300)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            row[k] = {"ilu_residual": float(f"{s.ilu_residual():.4e}"), "iters": res["iters"],
+                      "converged": res["converged"], "factor_ms": round((t1 - t0) * 1e3, 3),
+                      "solve_ms": round((t2 - t1) * 1e3, 3)}
+        rows.append(row)
+    log("warm start, line-ordered boundary layer:", rows)
+    tot = {k: {"iters": sum(r[k]["iters"] for r in rows),
+               "mean_ilu_residual": float(np.mean([r[k]["ilu_residual"] for r in rows[1:]])) if len(rows) > 1 else None,
+               "factor_ms": round(sum(r[k]["factor_ms"] for r in rows), 3),
+               "solve_ms": round(sum(r[k]["solve_ms"] for r in rows), 3),
+               "all_converged": all(r[k]["converged"] for r in rows)} for k in forms}
+    del sysm
+    torch.cuda.empty_cache()
+    return {"workload": f"{c.n}-cell boundary-layer quads in line order, {len(rows)} pseudo-time steps, CFL "
+                        f"{cfls[0]:g} -> {cfls[-1]:g}, 1% drift per step; FP32, {args.build_sweeps} build sweep(s), "
                         f"{args.apply_sweeps} apply sweep pairs, FGMRES(30) to {args.rtol}",
             "totals": tot, "steps": rows}
 
@@ -512,12 +561,14 @@ def main():
     ap.add_argument("--serve-forms", default="batched_f32,one_at_a_time_f64,one_at_a_time_f32")
     ap.add_argument("--serve-saturation-only", action="store_true")
     ap.add_argument("--warm-steps", type=int, default=12)
+    ap.add_argument("--warm-steps-line", type=int, default=8)
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-chunked", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-orderings", action="store_true")
     ap.add_argument("--only-orderings", action="store_true", help="print the orderings object alone")
+    ap.add_argument("--only-warm", action="store_true", help="print the warm_start object alone")
     ap.add_argument("--only-chunked", action="store_true", help="print the chunked object alone")
     ap.add_argument("--only-serving", action="store_true", help="print the serving object alone (profiling)")
     args = ap.parse_args()
@@ -537,6 +588,9 @@ def main():
     L.lib()
     if args.only_serving:
         print(json.dumps({"serving": serving_bench(args)}), flush=True)
+        return
+    if args.only_warm:
+        print(json.dumps({"warm_start": warm_start_bench(args)}), flush=True)
         return
     if args.only_orderings:
         print(json.dumps({"orderings": orderings_bench(args)}), flush=True)
