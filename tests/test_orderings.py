@@ -2,6 +2,7 @@
 bit-exact. No GPU needed: the orderings run on the host."""
 import numpy as np
 import pytest
+from hypothesis import given, settings, strategies as st
 
 from oracle import orderings as O
 from paper_1912_00539_amd import abilu as L
@@ -96,3 +97,46 @@ def test_order_argument_checks():
         L.abilu_order(c.n, c.rowptr, c.colidx, "line", lo, lp)
     with pytest.raises(L.AbiluError):
         L.abilu_find_lines(c.n, c.rowptr, c.colidx, np.ones(c.nnzb), 0.5, 4.0)
+
+
+# ------------------------------------------------------------------ randomized: any pattern, any weights
+
+
+def random_pattern(n, edges, unsym):
+    """A CSR block pattern with the diagonal, the given undirected edges (i != j), and optionally
+    only one direction of some edges (the library and the oracle both symmetrise)."""
+    rows = [set([i]) for i in range(n)]
+    for k, (a, b) in enumerate(edges):
+        if a == b:
+            continue
+        rows[a].add(b)
+        if not (unsym and k % 3 == 0):
+            rows[b].add(a)
+    rp = np.zeros(n + 1, np.int32)
+    for i in range(n):
+        rp[i + 1] = rp[i] + len(rows[i])
+    ci = np.concatenate([np.array(sorted(r), np.int32) for r in rows]) if n else np.zeros(0, np.int32)
+    return rp, ci
+
+
+@settings(max_examples=60, deadline=None)
+@given(n=st.integers(1, 60), data=st.data(), unsym=st.booleans())
+def test_orderings_random_graphs_bit_exact(n, data, unsym):
+    m = data.draw(st.integers(0, 3 * n))
+    edges = data.draw(st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), min_size=m, max_size=m))
+    rp, ci = random_pattern(n, edges, unsym)
+    np.testing.assert_array_equal(L.abilu_order(n, rp, ci, "rcm"), O.rcm(n, rp, ci))
+    np.testing.assert_array_equal(L.abilu_order(n, rp, ci, "1wd"), O.one_way_dissection(n, rp, ci))
+    w = np.asarray(data.draw(st.lists(st.sampled_from([0.5, 1.0, 2.0, 7.0, 40.0, 300.0]), min_size=len(ci),
+                                      max_size=len(ci))), np.float64)
+    theta = data.draw(st.sampled_from([1.0, 2.0, 10.0]))
+    rho = data.draw(st.sampled_from([1.5, 4.0]))
+    lo, lp, nl = L.abilu_find_lines(n, rp, ci, w, theta, rho)
+    olo, olp, onl = O.find_lines(n, rp, ci, w, theta, rho)
+    assert nl == onl
+    np.testing.assert_array_equal(lo, olo)
+    np.testing.assert_array_equal(lp, olp)
+    for x in ("rcm", "1wd"):
+        np.testing.assert_array_equal(L.abilu_order(n, rp, ci, f"line_{x}", lo, lp),
+                                      O.hybrid_line_order(n, rp, ci, lo, lp, x))
+    np.testing.assert_array_equal(L.abilu_order(n, rp, ci, "line", lo, lp), O.line_order(n, lo, lp))
