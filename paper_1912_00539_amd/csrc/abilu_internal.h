@@ -180,8 +180,12 @@ constexpr int MAX_CHUNK_ROWS = 4096;
 abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv, abilu_prec prec,
                         const double *r, double *z, int nsweeps, abilu_mode mode, char *work,
                         const Workspace &W, hipStream_t s);
+// Whether the last kernel of apply_impl(nsweeps, mode) ran its workgroups in descending row order.
+bool apply_ends_descending(int nsweeps, abilu_mode mode);
+// desc: run the workgroups in descending row order (the result does not depend on it; a kernel
+// that starts on the rows its predecessor touched last finds them in the Infinity Cache).
 abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x, double *y,
-                       const double *b, hipStream_t s);
+                       const double *b, bool desc, hipStream_t s);
 
 }  // namespace abilu
 

@@ -36,12 +36,14 @@ __global__ __launch_bounds__(WG) void k_fwd(int n, const int32_t *__restrict__ l
 }
 
 // Backward sweep over the strictly upper part (urow/ucol/Ub), then z_i = Dinv_i (y_i - sum).
-// OFFDIAG = false: z = Dinv y only. DUAL: also store z (precision T) into zout2.
+// OFFDIAG = false: z = Dinv y only. DUAL: also store z (precision T) into zout2. desc: workgroups
+// take the rows in descending order.
 template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
 __global__ __launch_bounds__(WG) void k_bwd(int n, const int32_t *__restrict__ urow, const int32_t *__restrict__ ucol,
                                             const T *__restrict__ Ub, const T *__restrict__ Dinv,
-                                            const YI *__restrict__ y, const T *zin, ZO *zout, T *zout2) {
-    bwd_body<T, YI, ZO, OFFDIAG, DUAL>(blockIdx.x, n, urow, ucol, Ub, Dinv, y, zin, zout, zout2);
+                                            const YI *__restrict__ y, const T *zin, ZO *zout, T *zout2, int desc) {
+    const int blk = desc ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+    bwd_body<T, YI, ZO, OFFDIAG, DUAL>(blk, n, urow, ucol, Ub, Dinv, y, zin, zout, zout2);
 }
 
 // Single-worker sweeps (ABILU_ASYNC_SERIAL): one quad, in place; forward rows ascending,
@@ -202,13 +204,15 @@ __global__ __launch_bounds__(WG) void k_bwd_chunk_rows(int n, int R, int nch, co
 }
 
 // y = A x  (RESID: y = b - A x), double precision, CSR; one quad per block row, four blocks
-// loaded per step (clamped: rows always hold at least their diagonal block)
+// loaded per step (clamped: rows always hold at least their diagonal block); desc: workgroups
+// take the rows in descending order
 template <bool RESID>
 __global__ __launch_bounds__(WG) void k_spmv(int n, const int32_t *__restrict__ rowptr,
                                              const int32_t *__restrict__ colidx, const double *__restrict__ A,
                                              const double *__restrict__ x, double *__restrict__ y,
-                                             const double *__restrict__ b) {
-    spmv_body<RESID>(blockIdx.x, n, rowptr, colidx, A, x, y, b);
+                                             const double *__restrict__ b, int desc) {
+    const int blk = desc ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+    spmv_body<RESID>(blk, n, rowptr, colidx, A, x, y, b);
 }
 
 template <typename T>
@@ -330,7 +334,7 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
     if (nsw == 1) {
         ProfScope ps(NAME("apply_diag"), s, 32 * zz.N + 16 * sF * zz.N + 32 * zz.N);
         k_bwd<T, double, double, false, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, r, (const T *)nullptr, z,
-                                                                   (T *)nullptr);
+                                                                   (T *)nullptr, 0);
         LAUNCHED();
         return ABILU_OK;
     }
@@ -355,20 +359,26 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
         yprev = ycur;
     }
     const T *yfin = ycur;
-    // backward sweeps 2..nsw (sweep 1 produced za)
+    // backward sweeps 2..nsw (sweep 1 produced za). Their workgroup order alternates, starting
+    // descending after the ascending forward sweeps, so that each sweep starts on the rows the
+    // previous kernel touched last (y, z, Dinv and U there are still in the Infinity Cache). A
+    // synchronous sweep's result does not depend on the order; an asynchronous one reads values of
+    // the same sweep in either order, and descending is the order of back substitution.
     T *zprev = za;
     for (int q = 2; q <= nsw; ++q) {
         const bool last = (q == nsw);
+        const int desc = (q % 2 == 0) ? 1 : 0;
         ProfScope ps(NAME(last ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, last ? 8 : sF, last && !sync));
         if (last) {
             // ASYNC: the in-place copy keeps rows updated later in this sweep reading fresh values
             if (sync)
-                k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, (T *)nullptr);
+                k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, (T *)nullptr,
+                                                                     desc);
             else
-                k_bwd<T, T, double, true, true><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, zprev);
+                k_bwd<T, T, double, true, true><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, zprev, desc);
         } else {
             T *zcur = sync ? ((zprev == za) ? zb : za) : za;
-            k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, zcur, (T *)nullptr);
+            k_bwd<T, T, T, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, zcur, (T *)nullptr, desc);
             zprev = zcur;
         }
         LAUNCHED();
@@ -395,17 +405,22 @@ abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv
     return apply_t<double>(p, (const double *)LU, (const double *)Dinv, r, z, nsweeps, mode, work, W, s);
 }
 
+bool apply_ends_descending(int nsweeps, abilu_mode mode) {
+    // the last backward sweep q = nsweeps >= 2 of the sweep modes runs descending for even q
+    return (mode == ABILU_SYNC || mode == ABILU_ASYNC) && nsweeps >= 2 && nsweeps % 2 == 0;
+}
+
 abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x, double *y, const double *b,
-                       hipStream_t s) {
+                       bool desc, hipStream_t s) {
     if (p->n == 0) return ABILU_OK;
     const int grid = div_up(p->n, ROWS_PER_WG);
     const Sizes z = sizes(p);
     if (b) {
         ProfScope ps("spmv_resid", s, bytes_spmv(z, true));
-        k_spmv<true><<<grid, WG, 0, s>>>(p->n, p->rowptr, p->colidx, A, x, y, b);
+        k_spmv<true><<<grid, WG, 0, s>>>(p->n, p->rowptr, p->colidx, A, x, y, b, desc ? 1 : 0);
     } else {
         ProfScope ps("spmv", s, bytes_spmv(z, false));
-        k_spmv<false><<<grid, WG, 0, s>>>(p->n, p->rowptr, p->colidx, A, x, y, nullptr);
+        k_spmv<false><<<grid, WG, 0, s>>>(p->n, p->rowptr, p->colidx, A, x, y, nullptr, desc ? 1 : 0);
     }
     return launch_status();
 }
@@ -432,5 +447,5 @@ extern "C" abilu_status abilu_spmv(const abilu_pattern *p, const double *d_A, co
     if (!p) return ABILU_EINVAL;
     if (p->n == 0) return ABILU_OK;
     if (!d_A || !d_x || !d_y || d_x == d_y) return ABILU_EINVAL;
-    return spmv_impl(p, d_A, d_x, d_y, nullptr, (hipStream_t)stream);
+    return spmv_impl(p, d_A, d_x, d_y, nullptr, false, (hipStream_t)stream);
 }

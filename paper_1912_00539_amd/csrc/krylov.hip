@@ -206,7 +206,7 @@ abilu_status readback(Ctx &c, double *h, uint32_t *flags) {
 
 // r = b - A x into V_0, beta = ||r|| into g[0], misc[MI_BETA] and status[ST_BETA]
 abilu_status true_residual(Ctx &c, const double *A, const double *b, const double *x, int m) {
-    abilu_status st = spmv_impl(c.p, A, x, c.V, b, c.s);
+    abilu_status st = spmv_impl(c.p, A, x, c.V, b, true, c.s);   // after ascending vector kernels
     if (st != ABILU_OK) return st;
     if ((st = mdot_reduce(c, c.V, 0, c.V, nullptr)) != ABILU_OK) return st;
     {
@@ -302,7 +302,9 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
             double *w = c.V + (int64_t)(k + 1) * c.nv;
             if ((st = apply_impl(p, d_LU, d_Dinv, prec, vk, zk, apply_sweeps, mode, c.work, c.W, c.s)) != ABILU_OK)
                 return st;
-            if ((st = spmv_impl(p, d_A, zk, w, nullptr, c.s)) != ABILU_OK) return st;
+            if ((st = spmv_impl(p, d_A, zk, w, nullptr, !apply_ends_descending(apply_sweeps, mode), c.s)) !=
+                ABILU_OK)
+                return st;
             // Gram-Schmidt pass 1
             if ((st = mdot_reduce(c, c.V, k + 1, w, nullptr)) != ABILU_OK) return st;
             {
