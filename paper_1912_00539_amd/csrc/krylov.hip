@@ -27,11 +27,13 @@ __global__ __launch_bounds__(WG) void k_mdot(int64_t len, const double *__restri
     mdot_body(blockIdx.x, len, V, ldv, q, w, partial, nb, guard);
 }
 
-// w[t] += alpha * sum_k c[k] V_k[t]; if partial: partial[b] = sum over tile of new w[t]^2
+// w[t] += alpha * sum_k c[k] V_k[t]; if partial: partial[b] = sum over tile of new w[t]^2. The
+// workgroups take the tiles in descending order: the dot products before it run ascending, so it
+// starts on the tiles they read last (the partials stay indexed by tile, so sums are unchanged).
 __global__ __launch_bounds__(WG) void k_update(int64_t len, const double *__restrict__ V, int64_t ldv, int q,
                                                const double *__restrict__ c, double alpha, double *__restrict__ w,
                                                double *__restrict__ partial, const int *guard) {
-    update_body(blockIdx.x, len, V, ldv, q, c, alpha, w, partial, guard);
+    update_body(gridDim.x - 1 - blockIdx.x, len, V, ldv, q, c, alpha, w, partial, guard);
 }
 
 // out[col] = sum_b partial[col*nb + b], one workgroup per column, fixed order
@@ -204,9 +206,10 @@ abilu_status readback(Ctx &c, double *h, uint32_t *flags) {
     return ABILU_OK;
 }
 
-// r = b - A x into V_0, beta = ||r|| into g[0], misc[MI_BETA] and status[ST_BETA]
+// r = b - A x into V_0, beta = ||r|| into g[0], misc[MI_BETA] and status[ST_BETA]. The SpMV runs
+// its workgroups descending (measured slightly faster than ascending after either predecessor).
 abilu_status true_residual(Ctx &c, const double *A, const double *b, const double *x, int m) {
-    abilu_status st = spmv_impl(c.p, A, x, c.V, b, true, c.s);   // after ascending vector kernels
+    abilu_status st = spmv_impl(c.p, A, x, c.V, b, true, c.s);
     if (st != ABILU_OK) return st;
     if ((st = mdot_reduce(c, c.V, 0, c.V, nullptr)) != ABILU_OK) return st;
     {
