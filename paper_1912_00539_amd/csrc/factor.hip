@@ -36,14 +36,17 @@ using namespace abilu_k;
 namespace {
 
 // X0 -> (optional) copy into Xout in factor layout, and D0 = inverses of X0's diagonal blocks.
-// SRC_CSR: X0 is A (CSR order, double); otherwise X0 is a factor-layout array of T.
+// SRC_CSR: X0 is A (CSR order, double); otherwise X0 is a factor-layout array of T. Rows are
+// independent; the workgroups take them in descending order so that the ascending sweep after it
+// starts on the rows whose inverses and diagonal blocks were touched last.
 template <typename T, typename S, bool SRC_CSR, bool COPY>
 __global__ __launch_bounds__(WG) void k_factor_init(int n, int ZL, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ diag_pos,
                                                     const int32_t *__restrict__ lrow,
                                                     const int32_t *__restrict__ urow, const S *X0, T *Xout, T *D0,
                                                     unsigned *flags) {
-    factor_init_body<T, S, SRC_CSR, COPY>(blockIdx.x, n, ZL, rowptr, diag_pos, lrow, urow, X0, Xout, D0, flags);
+    factor_init_body<T, S, SRC_CSR, COPY>(gridDim.x - 1 - blockIdx.x, n, ZL, rowptr, diag_pos, lrow, urow, X0, Xout,
+                                          D0, flags);
 }
 
 // One sweep.
