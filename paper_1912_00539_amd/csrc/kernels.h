@@ -306,8 +306,22 @@ __device__ __forceinline__ void reduce_cols_body(int blk, const double *__restri
     if (skipped(guard)) return;
     __shared__ double sh[WG / 64];
     const double *pc = partial + (int64_t)blk * nb;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += WG) s += pc[b];
+    // eight independent partial sums keep eight loads in flight per lane (fixed order: entry b
+    // goes to sum (b / WG) mod 8 while whole groups of 8 WG entries remain, the rest to sum 0)
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 7 * WG < nb; b += 8 * WG) {
+        a0 += pc[b];
+        a1 += pc[b + WG];
+        a2 += pc[b + 2 * WG];
+        a3 += pc[b + 3 * WG];
+        a4 += pc[b + 4 * WG];
+        a5 += pc[b + 5 * WG];
+        a6 += pc[b + 6 * WG];
+        a7 += pc[b + 7 * WG];
+    }
+    for (; b < nb; b += WG) a0 += pc[b];
+    double s = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
