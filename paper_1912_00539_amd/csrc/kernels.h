@@ -22,7 +22,7 @@ constexpr int MAX_RESTART = 256;
 // status slots (double[8] in the workspace header, copied to the host)
 enum { ST_EST = 0, ST_HN = 1, ST_BETA = 2, ST_NUM = 3, ST_GUARD = 4 };
 // misc slots (double[16])
-enum { MI_NRM0 = 0, MI_NRM1 = 1, MI_HN = 2, MI_BETA = 3, MI_GUARD = 15 };
+enum { MI_NRM0 = 0, MI_NRM1 = 1, MI_HN = 2, MI_BETA = 3, MI_DONE = 14, MI_GUARD = 15 };
 
 template <typename T, typename S>
 __device__ __forceinline__ void load_block_row(const S *base, int64_t pos, int r, T (&v)[4]) {

@@ -42,43 +42,72 @@ __global__ __launch_bounds__(WG) void k_reduce_cols(const double *__restrict__ p
     reduce_cols_body(blockIdx.x, partial, nb, out, guard);
 }
 
+// The single-lane steps that follow a column reduction, run by its last workgroup.
+enum { RS_BETA_START_ZERO = 0, RS_BETA_START_X, RS_BETA, RS_GS1, RS_GS1_DONE, RS_GS2, RS_GIVENS };
+
+struct KPtrs {
+    double *partials, *red, *H, *cs, *sn, *g, *coef, *misc, *status;
+    int *guard, *done;
+};
+
+// k_reduce_cols followed by single-lane step OP on the column sums, in one launch: each
+// workgroup reduces its column (or nothing when the guard says skip), then counts itself done;
+// the last one (agent-scope fences on both sides of the count, so the other columns' sums are
+// visible to it) runs the step and clears the count for the next launch. The step runs even when
+// the reduction was skipped (the Givens step needs it either way; the guarded steps check the
+// guard themselves).
+template <int OP>
+__global__ __launch_bounds__(WG) void k_reduce_step(KPtrs P, int nb, const int *guard, int k, int m) {
+    reduce_cols_body(blockIdx.x, P.partials, nb, P.red, guard);
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        int is_last = 1;
+        if (gridDim.x > 1) {
+            __threadfence();
+            is_last = atomicAdd(P.done, 1) == (int)gridDim.x - 1;
+            if (is_last) {
+                __threadfence();
+                *P.done = 0;
+            }
+        }
+        last = is_last;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    if constexpr (OP == RS_BETA_START_ZERO) {
+        beta_body(0, m, P.red, P.g, P.misc, P.status, ST_NUM);
+        beta_body(0, m, P.red, nullptr, P.misc, P.status, ST_BETA);
+    } else if constexpr (OP == RS_BETA_START_X) {
+        beta_body(0, m, P.red, nullptr, P.misc, P.status, ST_NUM);
+    } else if constexpr (OP == RS_BETA) {
+        beta_body(0, m, P.red, P.g, P.misc, P.status, ST_BETA);
+    } else if constexpr (OP == RS_GS1) {
+        gs1_body(0, k, m, P.red, P.H, P.coef, P.misc);
+    } else if constexpr (OP == RS_GS1_DONE) {
+        gs1_done_body(0, P.red, P.misc, P.guard);
+    } else if constexpr (OP == RS_GS2) {
+        gs2_body(0, k, m, P.red, P.H, P.coef, P.guard);
+    } else {
+        givens_body(0, k, m, P.red, P.guard, P.H, P.cs, P.sn, P.g, P.misc, P.status);
+    }
+}
+
 // v = w / h (h read from device memory; left unchanged if h == 0)
 __global__ __launch_bounds__(WG) void k_scale(int64_t len, const double *w, double *v, const double *h) {
     scale_body(blockIdx.x, len, w, v, h);
 }
 
-// ---- single-lane kernels on the small dense Hessenberg problem (column-major, ld = m+1)
-
-// After the first Gram-Schmidt pass: H(0:k,k) = dots, coef = dots, nrm0 = ||w|| before.
-__global__ void k_gs1(int k, int m, const double *__restrict__ red, double *H, double *coef, double *misc) {
-    gs1_body(blockIdx.x, k, m, red, H, coef, misc);
-}
-
-// After the first update: decide on a second pass (guard = 1) if ||w'|| < ||w|| / sqrt(2).
-__global__ void k_gs1_done(const double *__restrict__ nrm2, double *misc, int *guard) {
-    gs1_done_body(blockIdx.x, nrm2, misc, guard);
-}
-
-// After the second dot pass (only if guard): H(0:k,k) += dots2, coef = dots2.
-__global__ void k_gs2(int k, int m, const double *__restrict__ red, double *H, double *coef, const int *guard) {
-    gs2_body(blockIdx.x, k, m, red, H, coef, guard);
-}
-
-// Final norm, Givens rotations, residual estimate.
-__global__ void k_givens(int k, int m, const double *__restrict__ nrm2_pass2, const int *guard, double *H,
-                         double *cs, double *sn, double *g, double *misc, double *status) {
-    givens_body(blockIdx.x, k, m, nrm2_pass2, guard, H, cs, sn, g, misc, status);
-}
+// ---- single-lane steps on the small dense Hessenberg problem (column-major, ld = m+1). After the
+// first Gram-Schmidt pass: H(0:k,k) = dots, coef = dots, nrm0 = ||w|| before (gs1). After the
+// first update: a second pass (guard = 1) if ||w'|| < ||w|| / sqrt(2) (gs1_done). After the second
+// dot pass, only if guard: H(0:k,k) += dots2, coef = dots2 (gs2). Final norm, Givens rotations,
+// residual estimate (givens). All run fused into the reduction before them (k_reduce_step).
 
 // Back substitution on the k x k upper triangle: coef = y.
 __global__ void k_solve(int k, int m, const double *__restrict__ H, const double *__restrict__ g, double *coef) {
     solve_body(blockIdx.x, k, m, H, g, coef);
 }
 
-// beta = sqrt(red[0]); g = [beta, 0, ...]; status[slot] = beta
-__global__ void k_beta(int m, const double *__restrict__ red, double *g, double *misc, double *status, int slot) {
-    beta_body(blockIdx.x, m, red, g, misc, status, slot);
-}
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
@@ -153,7 +182,9 @@ struct Ctx {
     hipStream_t s;
     int64_t nv;
     double *partials, *H, *cs, *sn, *g, *coef, *misc, *status, *red, *V, *Zb;
-    int *guard;
+    int *guard, *done;
+    int m;
+    KPtrs ptrs() const { return KPtrs{partials, red, H, cs, sn, g, coef, misc, status, guard, done}; }
 };
 
 #define CKL()                                                     \
@@ -161,8 +192,26 @@ struct Ctx {
         if (launch_status() != ABILU_OK) return ABILU_EDEVICE;    \
     } while (0)
 
-// c.red[0..q] <- dots of w with V_0..V_{q-1}, then ||w||^2
-abilu_status mdot_reduce(Ctx &c, const double *Vb, int q, const double *w, const int *guard) {
+// Column sums of the partials into c.red (ncols columns), then single-lane step op.
+abilu_status reduce_step(Ctx &c, int ncols, const int *guard, int op, int k) {
+    const int nb = c.W.nb_vec;
+    ProfScope ps("fgmres_reduce", c.s, 8.0 * ncols * nb);
+    const KPtrs P = c.ptrs();
+    switch (op) {
+        case RS_BETA_START_ZERO: k_reduce_step<RS_BETA_START_ZERO><<<ncols, WG, 0, c.s>>>(P, nb, guard, k, c.m); break;
+        case RS_BETA_START_X: k_reduce_step<RS_BETA_START_X><<<ncols, WG, 0, c.s>>>(P, nb, guard, k, c.m); break;
+        case RS_BETA: k_reduce_step<RS_BETA><<<ncols, WG, 0, c.s>>>(P, nb, guard, k, c.m); break;
+        case RS_GS1: k_reduce_step<RS_GS1><<<ncols, WG, 0, c.s>>>(P, nb, guard, k, c.m); break;
+        case RS_GS1_DONE: k_reduce_step<RS_GS1_DONE><<<ncols, WG, 0, c.s>>>(P, nb, guard, k, c.m); break;
+        case RS_GS2: k_reduce_step<RS_GS2><<<ncols, WG, 0, c.s>>>(P, nb, guard, k, c.m); break;
+        default: k_reduce_step<RS_GIVENS><<<ncols, WG, 0, c.s>>>(P, nb, guard, k, c.m); break;
+    }
+    CKL();
+    return ABILU_OK;
+}
+
+// c.red[0..q] <- dots of w with V_0..V_{q-1}, then ||w||^2; then step op
+abilu_status mdot_reduce(Ctx &c, const double *Vb, int q, const double *w, const int *guard, int op, int k) {
     const int nb = c.W.nb_vec;
     const double n8 = 8.0 * (double)c.nv;
     {
@@ -170,30 +219,20 @@ abilu_status mdot_reduce(Ctx &c, const double *Vb, int q, const double *w, const
         k_mdot<<<nb, WG, 0, c.s>>>(c.nv, Vb, c.nv, q, w, c.partials, nb, guard);
     }
     CKL();
-    {
-        ProfScope ps("fgmres_reduce", c.s, 8.0 * (q + 1) * nb);
-        k_reduce_cols<<<q + 1, WG, 0, c.s>>>(c.partials, nb, c.red, guard);
-    }
-    CKL();
-    return ABILU_OK;
+    return reduce_step(c, q + 1, guard, op, k);
 }
 
-// w += alpha * sum_k coef[k] Vb_k; with_norm: c.red[0] <- ||w||^2 afterwards
-abilu_status update_reduce(Ctx &c, const double *Vb, int q, double alpha, double *w, bool with_norm,
-                           const int *guard) {
+// w += alpha * sum_k coef[k] Vb_k; with a step op (>= 0): c.red[0] <- ||w||^2 afterwards, then the step
+abilu_status update_reduce(Ctx &c, const double *Vb, int q, double alpha, double *w, const int *guard, int op, int k) {
     const int nb = c.W.nb_vec;
     const double n8 = 8.0 * (double)c.nv;
+    const bool with_norm = op >= 0;
     {
         ProfScope ps("fgmres_update", c.s, (q + 2) * n8);
         k_update<<<nb, WG, 0, c.s>>>(c.nv, Vb, c.nv, q, c.coef, alpha, w, with_norm ? c.partials : nullptr, guard);
     }
     CKL();
-    if (with_norm) {
-        ProfScope ps("fgmres_reduce", c.s, 8.0 * nb);
-        k_reduce_cols<<<1, WG, 0, c.s>>>(c.partials, nb, c.red, guard);
-        CKL();
-    }
-    return ABILU_OK;
+    return with_norm ? reduce_step(c, 1, guard, op, k) : ABILU_OK;
 }
 
 // copies the flag word and the status scalars to the host
@@ -208,16 +247,10 @@ abilu_status readback(Ctx &c, double *h, uint32_t *flags) {
 
 // r = b - A x into V_0, beta = ||r|| into g[0], misc[MI_BETA] and status[ST_BETA]. The SpMV runs
 // its workgroups descending (measured slightly faster than ascending after either predecessor).
-abilu_status true_residual(Ctx &c, const double *A, const double *b, const double *x, int m) {
+abilu_status true_residual(Ctx &c, const double *A, const double *b, const double *x) {
     abilu_status st = spmv_impl(c.p, A, x, c.V, b, true, c.s);
     if (st != ABILU_OK) return st;
-    if ((st = mdot_reduce(c, c.V, 0, c.V, nullptr)) != ABILU_OK) return st;
-    {
-        ProfScope ps("fgmres_small", c.s);
-        k_beta<<<1, 1, 0, c.s>>>(m, c.red, c.g, c.misc, c.status, ST_BETA);
-    }
-    CKL();
-    return ABILU_OK;
+    return mdot_reduce(c, c.V, 0, c.V, nullptr, RS_BETA, 0);
 }
 
 }  // namespace
@@ -258,19 +291,22 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
     c.V = (double *)(c.work + c.W.V);
     c.Zb = (double *)(c.work + c.W.Z);
     c.guard = (int *)(c.misc + MI_GUARD);
+    c.done = (int *)(c.misc + MI_DONE);
+    c.m = m;
     double h[8];
     uint32_t flags = 0;
     abilu_status st;
 
     // ||b|| and the initial residual (b itself for a zero initial guess)
     const bool zero_guess = (options & ABILU_FGMRES_ZERO_GUESS) != 0;
-    if ((st = mdot_reduce(c, c.V, 0, d_b, nullptr)) != ABILU_OK) return st;
     {
         ProfScope ps("fgmres_small", c.s);
-        k_beta<<<1, 1, 0, c.s>>>(m, c.red, zero_guess ? c.g : nullptr, c.misc, c.status, ST_NUM);
-        if (zero_guess) k_beta<<<1, 1, 0, c.s>>>(m, c.red, nullptr, c.misc, c.status, ST_BETA);
+        k_set_int<<<1, 1, 0, c.s>>>(c.done, 0);   // completion count of the fused reductions
     }
     CKL();
+    if ((st = mdot_reduce(c, c.V, 0, d_b, nullptr, zero_guess ? RS_BETA_START_ZERO : RS_BETA_START_X, 0)) !=
+        ABILU_OK)
+        return st;
     const double *first_v0 = c.V;   // the vector the first cycle normalises into V_0
     if (zero_guess) {
         {
@@ -279,7 +315,7 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
         }
         CKL();
         first_v0 = d_b;
-    } else if ((st = true_residual(c, d_A, d_b, d_x, m)) != ABILU_OK) {
+    } else if ((st = true_residual(c, d_A, d_b, d_x)) != ABILU_OK) {
         return st;
     }
     if ((st = readback(c, h, &flags)) != ABILU_OK) return st;
@@ -309,33 +345,15 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
                 ABILU_OK)
                 return st;
             // Gram-Schmidt pass 1
-            if ((st = mdot_reduce(c, c.V, k + 1, w, nullptr)) != ABILU_OK) return st;
-            {
-                ProfScope ps("fgmres_small", c.s);
-                k_gs1<<<1, 1, 0, c.s>>>(k, m, c.red, c.H, c.coef, c.misc);
-            }
-            CKL();
-            if ((st = update_reduce(c, c.V, k + 1, -1.0, w, true, nullptr)) != ABILU_OK) return st;
-            {
-                ProfScope ps("fgmres_small", c.s);
-                k_gs1_done<<<1, 1, 0, c.s>>>(c.red, c.misc, c.guard);
-            }
-            CKL();
-            // pass 2, executed by the device only when the guard is set
+            // pass 1: dots, H(0:k,k); update, then the decision on a second pass
+            if ((st = mdot_reduce(c, c.V, k + 1, w, nullptr, RS_GS1, k)) != ABILU_OK) return st;
+            if ((st = update_reduce(c, c.V, k + 1, -1.0, w, nullptr, RS_GS1_DONE, k)) != ABILU_OK) return st;
+            // pass 2, executed by the device only when the guard is set; the Givens step after its
+            // update runs either way
             const int pass2_begin = prof_mark();
-            if ((st = mdot_reduce(c, c.V, k + 1, w, c.guard)) != ABILU_OK) return st;
-            {
-                ProfScope ps("fgmres_small", c.s);
-                k_gs2<<<1, 1, 0, c.s>>>(k, m, c.red, c.H, c.coef, c.guard);
-            }
-            CKL();
-            if ((st = update_reduce(c, c.V, k + 1, -1.0, w, true, c.guard)) != ABILU_OK) return st;
+            if ((st = mdot_reduce(c, c.V, k + 1, w, c.guard, RS_GS2, k)) != ABILU_OK) return st;
+            if ((st = update_reduce(c, c.V, k + 1, -1.0, w, c.guard, RS_GIVENS, k)) != ABILU_OK) return st;
             const int pass2_end = prof_mark();
-            {
-                ProfScope ps("fgmres_small", c.s);
-                k_givens<<<1, 1, 0, c.s>>>(k, m, c.red, c.guard, c.H, c.cs, c.sn, c.g, c.misc, c.status);
-            }
-            CKL();
             {
                 ProfScope ps("fgmres_scale", c.s, 16.0 * (double)c.nv);
                 k_scale<<<c.W.nb_vec, WG, 0, c.s>>>(c.nv, w, w, c.misc + MI_HN);
@@ -362,8 +380,8 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
             k_solve<<<1, 1, 0, c.s>>>(k, m, c.H, c.g, c.coef);
         }
         CKL();
-        if ((st = update_reduce(c, c.Zb, k, 1.0, d_x, false, nullptr)) != ABILU_OK) return st;
-        if ((st = true_residual(c, d_A, d_b, d_x, m)) != ABILU_OK) return st;
+        if ((st = update_reduce(c, c.Zb, k, 1.0, d_x, nullptr, -1, 0)) != ABILU_OK) return st;
+        if ((st = true_residual(c, d_A, d_b, d_x)) != ABILU_OK) return st;
         if ((st = readback(c, h, &flags)) != ABILU_OK) return st;
         ++restarts;
         beta = h[ST_BETA];
