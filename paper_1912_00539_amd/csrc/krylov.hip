@@ -2,11 +2,12 @@
 // sweep apply, entirely in double precision on the device: Arnoldi basis V and preconditioned
 // basis Z in the workspace, classical Gram-Schmidt with a second pass when the norm falls below
 // 1/sqrt(2) of its value before orthogonalisation ("twice is enough"), Givens rotations on the
-// Hessenberg matrix by a single-lane kernel, x update and true residual at each cycle end.
-// The host loop reads back a few scalars per iteration to decide when to stop.
+// Hessenberg matrix by one lane of the reduction before them, x update and true residual at each
+// cycle end. The host loop reads back a few scalars per iteration to decide when to stop.
 //
 // All reductions are fixed-order (per-workgroup partials, then one workgroup per column in
-// index order), so results do not depend on scheduling.
+// index order), so results do not depend on scheduling. The only atomic is the completion count
+// that picks the last workgroup of a reduction; it orders work, not values.
 #include <cmath>
 
 #include "kernels.h"
