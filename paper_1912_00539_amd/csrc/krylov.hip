@@ -75,11 +75,13 @@ __global__ __launch_bounds__(WG) void k_reduce_step(KPtrs P, int nb, const int *
     }
     __syncthreads();
     if (!last || threadIdx.x != 0) return;
-    if constexpr (OP == RS_BETA_START_ZERO) {
-        beta_body(0, m, P.red, P.g, P.misc, P.status, ST_NUM);
+    if constexpr (OP == RS_BETA_START_ZERO) {   // the solve's first reduction (one column): also
+        beta_body(0, m, P.red, P.g, P.misc, P.status, ST_NUM);   // clears the completion count
         beta_body(0, m, P.red, nullptr, P.misc, P.status, ST_BETA);
+        *P.done = 0;
     } else if constexpr (OP == RS_BETA_START_X) {
         beta_body(0, m, P.red, nullptr, P.misc, P.status, ST_NUM);
+        *P.done = 0;
     } else if constexpr (OP == RS_BETA) {
         beta_body(0, m, P.red, P.g, P.misc, P.status, ST_BETA);
     } else if constexpr (OP == RS_GS1) {
@@ -109,8 +111,6 @@ __global__ void k_solve(int k, int m, const double *__restrict__ H, const double
     solve_body(blockIdx.x, k, m, H, g, coef);
 }
 
-
-__global__ void k_set_int(int *p, int v) { *p = v; }
 
 __global__ __launch_bounds__(WG) void k_zero(int64_t len, double *v) {
     zero_body(blockIdx.x, len, v);
@@ -300,11 +300,6 @@ extern "C" abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, 
 
     // ||b|| and the initial residual (b itself for a zero initial guess)
     const bool zero_guess = (options & ABILU_FGMRES_ZERO_GUESS) != 0;
-    {
-        ProfScope ps("fgmres_small", c.s);
-        k_set_int<<<1, 1, 0, c.s>>>(c.done, 0);   // completion count of the fused reductions
-    }
-    CKL();
     if ((st = mdot_reduce(c, c.V, 0, d_b, nullptr, zero_guess ? RS_BETA_START_ZERO : RS_BETA_START_X, 0)) !=
         ABILU_OK)
         return st;
