@@ -97,6 +97,15 @@ __device__ __forceinline__ void *role(const Slot &S, int k, int code) {
     const Slot &S = slots[M.slot];                        \
     const int blk = blockIdx.x - M.tile0
 
+// The same with the launch's tiles taken in descending order when desc is set (as the
+// single-system kernels do, so that a kernel starts on the tiles its predecessor touched last).
+#define MEMBER_DIR(desc)                                                            \
+    const int bid_ = (desc) ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x; \
+    const int mi_ = find_member(mem, nmem, bid_);                                   \
+    const Member M = mem[mi_];                                                      \
+    const Slot &S = slots[M.slot];                                                  \
+    const int blk = bid_ - M.tile0
+
 // factor buffers: bit 0 X input is X1, bit 1 D input is D1, bit 2 X output is X1, bit 3 D output is D1
 template <typename T>
 __device__ __forceinline__ T *fbuf_x(const Slot &S, bool one) { return (T *)(one ? S.X1 : S.LU); }
@@ -105,7 +114,7 @@ __device__ __forceinline__ T *fbuf_d(const Slot &S, bool one) { return (T *)(one
 
 template <typename T, bool COPY>
 __global__ __launch_bounds__(WG) void kb_factor_init(const Slot *slots, const Member *mem, int nmem, int sel) {
-    MEMBER();
+    MEMBER_DIR(true);
     factor_init_body<T, double, true, COPY>(blk, S.n, S.ZL, S.rowptr, S.diag_pos, S.lrow, S.urow, S.A,
                                             COPY ? (T *)S.LU : (T *)nullptr, fbuf_d<T>(S, sel & 8), S.flags);
 }
@@ -127,8 +136,9 @@ __global__ __launch_bounds__(WG) void kb_fwd(const Slot *slots, const Member *me
 }
 
 template <typename T, typename YI, typename ZO, bool OFFDIAG, bool DUAL>
-__global__ __launch_bounds__(WG) void kb_bwd(const Slot *slots, const Member *mem, int nmem, int y, int zin, int zout) {
-    MEMBER();
+__global__ __launch_bounds__(WG) void kb_bwd(const Slot *slots, const Member *mem, int nmem, int y, int zin, int zout,
+                                             int desc) {
+    MEMBER_DIR(desc);
     const T *Ub = (const T *)S.LU + ((int64_t)S.ZL + S.n) * BB;
     bwd_body<T, YI, ZO, OFFDIAG, DUAL>(blk, S.n, S.urow, S.ucol, Ub, (const T *)S.Dinv, (const YI *)role(S, M.k, y),
                                        (const T *)role(S, M.k, zin), (ZO *)role(S, M.k, zout), (T *)S.za);
@@ -147,8 +157,9 @@ __global__ __launch_bounds__(WG) void kb_copy(const Slot *slots, const Member *m
 }
 
 template <bool RESID>
-__global__ __launch_bounds__(WG) void kb_spmv(const Slot *slots, const Member *mem, int nmem, int xin, int yout) {
-    MEMBER();
+__global__ __launch_bounds__(WG) void kb_spmv(const Slot *slots, const Member *mem, int nmem, int xin, int yout,
+                                              int desc) {
+    MEMBER_DIR(desc);
     spmv_body<RESID>(blk, S.n, S.rowptr, S.colidx, S.A, (const double *)role(S, M.k, xin),
                      (double *)role(S, M.k, yout), S.b);
 }
@@ -164,7 +175,7 @@ __global__ __launch_bounds__(WG) void kb_mdot(const Slot *slots, const Member *m
 
 __global__ __launch_bounds__(WG) void kb_update(const Slot *slots, const Member *mem, int nmem, int base, int q_plus,
                                                 double alpha, int w, int with_norm, int use_guard) {
-    MEMBER();
+    MEMBER_DIR(true);
     update_body(blk, S.nv, (const double *)role(S, M.k, base), S.nv, M.k + q_plus, S.coef, alpha,
                 (double *)role(S, M.k, w), with_norm ? S.partials : nullptr,
                 use_guard ? (const int *)(S.misc + MI_GUARD) : nullptr);
@@ -883,13 +894,16 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
         CKL();
         return ABILU_OK;
     };
+    // the Arnoldi SpMV runs opposite to the last backward sweep (descending for even q), the
+    // residual SpMV descending
+    const bool spmv_desc = !(nsw >= 2 && nsw % 2 == 0);
     auto spmv = [&](bool resid, int xin, int yout) -> abilu_status {
         ProfScope ps(resid ? "serve_spmv_resid" : "serve_spmv", st,
                      B([&](const Sizes &z, const Req &) { return bytes_spmv(z, resid); }));
         if (resid)
-            kb_spmv<true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), xin, yout);
+            kb_spmv<true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), xin, yout, 1);
         else
-            kb_spmv<false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), xin, yout);
+            kb_spmv<false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), xin, yout, spmv_desc ? 1 : 0);
         CKL();
         return ABILU_OK;
     };
@@ -949,7 +963,7 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
         } else if (nsw == 1) {
             ProfScope ps("serve_apply_diag", st,
                          B([&](const Sizes &z, const Req &) { return 32 * z.N + 16 * sF * z.N + 32 * z.N; }));
-            kb_bwd<T, double, double, false, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), R_VK, R_ZA, R_ZK);
+            kb_bwd<T, double, double, false, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), R_VK, R_ZA, R_ZK, 0);
             CKL();
         } else {
             // sweep 1 forward is y = v_k and sweep 1 backward z = Dinv y (emitted by the last forward
@@ -969,11 +983,13 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
                 ProfScope ps(last ? "serve_apply_bwd_last" : "serve_apply_bwd", st,
                              B([&](const Sizes &z, const Req &) { return bytes_bwd(z, sF, last ? 8 : sF, dual); }));
                 if (last) {
-                    if (dual) kb_bwd<T, T, double, true, true><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, R_ZK);
-                    else kb_bwd<T, T, double, true, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, R_ZK);
+                    if (dual)
+                        kb_bwd<T, T, double, true, true><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, R_ZK, q % 2 == 0);
+                    else
+                        kb_bwd<T, T, double, true, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, R_ZK, q % 2 == 0);
                 } else {
                     const int zcur = sync ? ((zprev == R_ZA) ? R_ZB : R_ZA) : R_ZA;
-                    kb_bwd<T, T, T, true, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, zcur);
+                    kb_bwd<T, T, T, true, false><<<L_(SH_APPLY)>>>(A_(SH_APPLY), ycur, zprev, zcur, q % 2 == 0);
                     zprev = zcur;
                 }
                 CKL();
