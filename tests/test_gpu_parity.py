@@ -342,6 +342,29 @@ def test_fgmres_f64_matches_oracle(name):
         assert rel(x, ref["x"]) <= 1e-10
 
 
+@pytest.mark.parametrize("apply_sweeps", [2, 4])
+@pytest.mark.parametrize("name", ["quad32", "nine23x17"])
+def test_fgmres_even_apply_sweeps(name, apply_sweeps):
+    """With an even number of apply sweeps the last backward sweep runs its workgroups descending
+    and the Arnoldi SpMV ascending (the opposite of 3 sweeps). Same checks as the odd case:
+    iteration count within one of the oracle, true residual confirmed by the oracle SpMV, x within
+    1e-10 when the counts agree."""
+    c = get(name)
+    s = DS(c, "f64", restart=30)
+    s.factor(3, "sync")
+    X, D = s.factor_host()
+    st, res = s.solve(apply_sweeps=apply_sweeps, mode="sync", rtol=1e-6, maxit=300)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, X, D, restart=30, maxit=300, rtol=1e-6,
+                        apply_nsw=apply_sweeps)
+    assert st == 0 and res["converged"] and ref["converged"]
+    assert abs(res["iters"] - ref["iters"]) <= 1
+    x = s.x.cpu().numpy()
+    true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / np.linalg.norm(c.b)
+    assert true <= 1e-6 and abs(true - res["rel_true_residual"]) <= 1e-10
+    if res["iters"] == ref["iters"]:
+        assert rel(x, ref["x"]) <= 1e-10
+
+
 def test_fgmres_second_gram_schmidt_pass():
     """A = I + 1e-3 B with the identity preconditioner (no apply sweeps): each new Arnoldi vector
     A v_k lies almost in the span of the basis, so the first classical Gram-Schmidt pass cancels
