@@ -10,6 +10,8 @@
 // DPP broadcast. SYNC sweeps read the previous sweep's vector (ping-pong); ASYNC sweeps update in
 // place. From the zero initial guess the first forward sweep is y = r, so it is not launched; the
 // last forward sweep also produces the first backward sweep z = Dinv y (its rows are at hand).
+// Forward sweeps take the rows in ascending workgroup order; backward sweeps and the SpMV may run
+// descending, so that a kernel starts on the rows the one before it touched last.
 // The chunked sweeps (a forward or backward substitution inside each chunk of consecutive rows)
 // run a chunk per workgroup level by level, or a chunk per quad row by row; the single-worker
 // sweeps run all rows in one quad.
