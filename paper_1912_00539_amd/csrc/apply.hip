@@ -370,10 +370,13 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
     for (int q = 2; q <= nsw; ++q) {
         const bool last = (q == nsw);
         const int desc = (q % 2 == 0) ? 1 : 0;
-        ProfScope ps(NAME(last ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, last ? 8 : sF, last && !sync));
+        // ASYNC, last sweep descending: an in-place FP32 copy of z lets the rows updated later in
+        // this sweep (the lower ones) read this sweep's values. Ascending, those reads go to rows
+        // updated later still, so the copy would serve no read and is not written.
+        const bool dual = last && !sync && desc;
+        ProfScope ps(NAME(last ? "apply_bwd_last" : "apply_bwd"), s, bytes_bwd(zz, sF, last ? 8 : sF, dual));
         if (last) {
-            // ASYNC: the in-place copy keeps rows updated later in this sweep reading fresh values
-            if (sync)
+            if (!dual)
                 k_bwd<T, T, double, true, false><<<grid, WG, 0, s>>>(n, urow, ucol, Ub, Dinv, yfin, zprev, z, (T *)nullptr,
                                                                      desc);
             else

@@ -979,7 +979,7 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
             int zprev = R_ZA;
             for (int q = 2; q <= nsw; ++q) {
                 const bool last = q == nsw;
-                const bool dual = last && !sync;
+                const bool dual = last && !sync && q % 2 == 0;   // the in-place copy serves only a descending sweep
                 ProfScope ps(last ? "serve_apply_bwd_last" : "serve_apply_bwd", st,
                              B([&](const Sizes &z, const Req &) { return bytes_bwd(z, sF, last ? 8 : sF, dual); }));
                 if (last) {
