@@ -18,9 +18,6 @@ using namespace abilu_k;
 
 namespace {
 
-
-
-
 // partial[k*nb + b] = sum_{t in tile b} V_k[t] w[t] for k < q;  partial[q*nb + b] = sum w[t]^2
 __global__ __launch_bounds__(WG) void k_mdot(int64_t len, const double *__restrict__ V, int64_t ldv, int q,
                                              const double *__restrict__ w, double *__restrict__ partial, int nb,
@@ -110,7 +107,6 @@ __global__ __launch_bounds__(WG) void k_scale(int64_t len, const double *w, doub
 __global__ void k_solve(int k, int m, const double *__restrict__ H, const double *__restrict__ g, double *coef) {
     solve_body(blockIdx.x, k, m, H, g, coef);
 }
-
 
 __global__ __launch_bounds__(WG) void k_zero(int64_t len, double *v) {
     zero_body(blockIdx.x, len, v);
