@@ -75,7 +75,31 @@ def build(verbose: bool = True, jobs: int = 8) -> str:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)
     os.replace(OUT + ".tmp", OUT)
+    build_c_solve(tl, verbose)
     return OUT
+
+
+C_SOLVE = os.path.join(OUTDIR, "abilu_c_solve")
+
+
+def build_c_solve(tl, verbose: bool = True) -> str:
+    """The C-only user of the ABI (tests/c_abi/solve.c): plain C, linked against libabilu.so
+    (found next to it) and the same HIP runtime."""
+    src = os.path.join(ROOT, "tests", "c_abi", "solve.c")
+    if not os.path.exists(src):
+        return ""
+    rocm_inc = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "include")
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__", "-I", rocm_inc, "-I", INCLUDE,
+           src, "-o", C_SOLVE + ".tmp", f"-L{OUTDIR}", "-labilu", "-Wl,-rpath,$ORIGIN", "-lm"]
+    if tl:
+        cmd[-1:-1] = [f"-L{tl}", "-l:libamdhip64.so", f"-Wl,-rpath,{tl}"]
+    else:
+        cmd[-1:-1] = ["-L/opt/rocm/lib", "-lamdhip64"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(C_SOLVE + ".tmp", C_SOLVE)
+    return C_SOLVE
 
 
 if __name__ == "__main__":
