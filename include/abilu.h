@@ -93,11 +93,11 @@ typedef struct abilu_pattern abilu_pattern;
  * blocks, and build for every block (i,j) the update set of the block ILU equations (equation
  * bilu), K(i,j) = { k < min(i,j) : (i,k) in S_B, (k,j) in S_B }, as a CSR list of position
  * pairs (pos(i,k), pos(k,j)) ascending in k.
- *   nbrows     N >= 0 block rows (cells)
+ *   nbrows     N block rows (cells), 0 <= N < 2^31 - 1 (so that N + 1 fits in int32)
  *   d_rowptr   device int32[N+1]; d_colidx device int32[Z] (copied; caller keeps ownership)
  *   bs         block size, must be 4
  *   out        receives the pattern handle (release with abilu_pattern_destroy)
- * Blocks on `stream`. Errors: ABILU_EINVAL (bs != 4, N < 0, null pointers), ABILU_EPATTERN
+ * Blocks on `stream`. Errors: ABILU_EINVAL (bs != 4, N out of range, null pointers), ABILU_EPATTERN
  * (invalid pattern; *out is left NULL), ABILU_ENOMEM, ABILU_EDEVICE.
  */
 abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_rowptr, const int32_t *d_colidx,

@@ -167,7 +167,7 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
     using namespace abilu;
     if (!out) return ABILU_EINVAL;
     *out = nullptr;
-    if (bs != 4 || nbrows < 0 || !d_rowptr) return ABILU_EINVAL;
+    if (bs != 4 || nbrows < 0 || nbrows == INT32_MAX || !d_rowptr) return ABILU_EINVAL;   // N + 1 fits int32
     hipStream_t s = (hipStream_t)stream;
     const int n = nbrows;
 

@@ -48,6 +48,7 @@ def test_argument_checks_without_device():
     # bad block size / negative size / null output are rejected before any HIP call
     assert lib.abilu_build_pattern(4, None, None, 3, None, C.byref(out)) == L.ABILU_EINVAL
     assert lib.abilu_build_pattern(-1, None, None, 4, None, C.byref(out)) == L.ABILU_EINVAL
+    assert lib.abilu_build_pattern(2**31 - 1, None, None, 4, None, C.byref(out)) == L.ABILU_EINVAL
     assert lib.abilu_build_pattern(4, None, None, 4, None, None) == L.ABILU_EINVAL
     assert lib.abilu_workspace_bytes(None, L.ABILU_F32, 30) == 0
     assert lib.abilu_factor(None, None, None, None, L.ABILU_F32, 1, 0, 0, None, 0, None) == L.ABILU_EINVAL
