@@ -295,8 +295,10 @@ def test_apply_chunk_sync_f64(name, R, nsw, runner):
 def test_apply_chunk_sync_f32(name, nsw, runner):
     c = get(name)
     s = DS(c, "f32", R=64, runner=runner)
-    s.factor(1, "sync")
-    X, D = s.factor_host()                  # the f32 factor, exactly representable in f64
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    X = Xo.astype(np.float32).astype(np.float64)   # the oracle factor as FP32 storage holds it
+    D = Do.astype(np.float32).astype(np.float64)
+    s.set_factor(X, D)
     r = np.random.default_rng(10 + nsw).uniform(-1, 1, 4 * c.n)
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
@@ -377,11 +379,14 @@ def test_full_size_tri300_chunk_sync(prec):
         tol = 1e-12 if prec == "f64" else 1e-5
         print(f"{prec} nsw {nsw}: X {rel(X, Xo):.2e} Dinv {rel(D, Do):.2e}")
         assert rel(X, Xo) <= tol and rel(D, Do) <= tol
+    if prec == "f32":   # the oracle factor as FP32 storage holds it
+        Xo, Do = Xo.astype(np.float32).astype(np.float64), Do.astype(np.float32).astype(np.float64)
+    s.set_factor(Xo, Do)
     r = np.random.default_rng(5).uniform(-1, 1, 4 * c.n)
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
     s.apply(rt, zt, 2, "chunk_sync")
-    ref = oracle.apply_chunked(c.n, c.rowptr, c.colidx, X, D, r, 2, 64)
+    ref = oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xo, Do, r, 2, 64)
     assert rel(zt.cpu().numpy(), ref) <= (1e-12 if prec == "f64" else 1e-5)
 
 
@@ -405,8 +410,9 @@ def test_full_size_aniso1000_line_chunk_sync():
 # ------------------------------------------------------------------ orderings + chunked sweeps, end to end
 def test_line_ordering_then_chunked_sweeps():
     """Section 5 with the chunk schedule of Section 3.3: the library finds lines on a boundary-layer
-    mesh from its geometric couplings, orders it line-RCM (and RCM for comparison), and the same
-    seeded matrix is assembled in each order. One CHUNK_SYNC FP64 sweep (16-row chunks) matches
+    mesh from its geometric couplings and orders it line-RCM (and RCM for comparison), both equal
+    to the ordering oracle's bit for bit; the same seeded matrix is assembled in each of the
+    oracle's orders. One CHUNK_SYNC FP64 sweep (16-row chunks) matches
     the chunked oracle; under line-RCM each chunk runs along a wall-normal line and its ILU residual
     is well below RCM's (2.3e-3 against 9.6e-3 in the oracle for this case). An asynchronous
     chunked FP32 solve then converges, its true residual confirmed by the oracle SpMV."""
@@ -415,12 +421,19 @@ def test_line_ordering_then_chunked_sweeps():
     base = W.natural_order(m)
     c0 = W.assemble(m, base, 3, "cfl", cfl=100.0)
     w = W.block_face_weights(m, base, c0.rowptr, c0.colidx)
+    from oracle import orderings as O
     lo, lp, nl = L.abilu_find_lines(c0.n, c0.rowptr, c0.colidx, w, 10.0, 4.0)
-    assert nl == 60
+    olo, olp, onl = O.find_lines(c0.n, c0.rowptr, c0.colidx, w, 10.0, 4.0)
+    assert nl == onl == 60
+    np.testing.assert_array_equal(lo, olo)
+    np.testing.assert_array_equal(lp, olp)
     res = {}
     for name in ("rcm", "line_rcm"):
         new = L.abilu_order(c0.n, c0.rowptr, c0.colidx, name, lo, lp).astype(np.int64)
-        c = W.assemble(m, new, 3, "cfl", cfl=100.0)
+        onew = O.rcm(c0.n, c0.rowptr, c0.colidx) if name == "rcm" else \
+            O.hybrid_line_order(c0.n, c0.rowptr, c0.colidx, olo, olp, "rcm")
+        np.testing.assert_array_equal(new, onew)
+        c = W.assemble(m, onew, 3, "cfl", cfl=100.0)   # the oracle's ordering feeds both sides
         s = DS(c, "f64", R=16)
         s.factor(1, "chunk_sync")
         X, D = s.factor_host()

@@ -200,9 +200,9 @@ def test_factor_async_residual_reported(name):
 def test_ilu_residual_matches_oracle(name):
     c = get(name)
     s = DS(c, "f64")
-    s.factor(1, "sync")
-    X, _ = s.factor_host()
-    ref = oracle.ilu_residual(c.n, c.rowptr, c.colidx, c.vals, X)
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    s.set_factor(Xo, Do)
+    ref = oracle.ilu_residual(c.n, c.rowptr, c.colidx, c.vals, Xo)
     assert abs(s.ilu_residual() - ref) <= 1e-12 * ref
 
 
@@ -262,8 +262,10 @@ def test_apply_sync_f64(name, nsw):
 def test_apply_sync_f32(name, nsw):
     c = get(name)
     s = DS(c, "f32")
-    s.factor(1, "sync")
-    X, D = s.factor_host()                  # the f32 factor, exactly representable in f64
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    X = Xo.astype(np.float32).astype(np.float64)   # the oracle factor as FP32 storage holds it
+    D = Do.astype(np.float32).astype(np.float64)
+    s.set_factor(X, D)
     r = np.random.default_rng(10 + nsw).uniform(-1, 1, 4 * c.n)
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
@@ -329,9 +331,9 @@ def test_fgmres_f64_matches_oracle(name):
     c = get(name)
     s = DS(c, "f64", restart=30)
     s.factor(3, "sync")
-    X, D = s.factor_host()
     st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-6, maxit=300)
-    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, X, D, restart=30, maxit=300, rtol=1e-6, apply_nsw=3)
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 3)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, Xo, Do, restart=30, maxit=300, rtol=1e-6, apply_nsw=3)
     assert st == 0 and res["converged"] and ref["converged"]
     assert abs(res["iters"] - ref["iters"]) <= 1
     assert res["rel_true_residual"] <= 1e-6 and ref["rel_true_residual"] <= 1e-6
@@ -352,9 +354,9 @@ def test_fgmres_even_apply_sweeps(name, apply_sweeps):
     c = get(name)
     s = DS(c, "f64", restart=30)
     s.factor(3, "sync")
-    X, D = s.factor_host()
     st, res = s.solve(apply_sweeps=apply_sweeps, mode="sync", rtol=1e-6, maxit=300)
-    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, X, D, restart=30, maxit=300, rtol=1e-6,
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 3)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, Xo, Do, restart=30, maxit=300, rtol=1e-6,
                         apply_nsw=apply_sweeps)
     assert st == 0 and res["converged"] and ref["converged"]
     assert abs(res["iters"] - ref["iters"]) <= 1
@@ -442,9 +444,9 @@ def test_fgmres_restarts_and_noconv():
     c = W.case("quad", seed=6, nx=30, ny=30, s=0.05)
     s = DS(c, "f64", restart=4)
     s.factor(1, "sync")
-    X, D = s.factor_host()
     st, res = s.solve(apply_sweeps=1, mode="sync", rtol=1e-8, maxit=400)
-    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, X, D, restart=4, maxit=400, rtol=1e-8, apply_nsw=1)
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, Xo, Do, restart=4, maxit=400, rtol=1e-8, apply_nsw=1)
     assert res["converged"] and ref["converged"] and res["restarts"] >= 2
     assert abs(res["iters"] - ref["iters"]) <= 1
     from paper_1912_00539_amd import abilu as L
@@ -457,10 +459,10 @@ def test_fgmres_nonzero_initial_guess():
     c = get("tri40x30_rcm")
     s = DS(c, "f64", restart=30)
     s.factor(2, "sync")
-    X, D = s.factor_host()
     x0 = np.random.default_rng(9).uniform(-1, 1, 4 * c.n)
     st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-6, maxit=300, x0=torch.from_numpy(x0).cuda())
-    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, X, D, restart=30, maxit=300, rtol=1e-6, apply_nsw=3,
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 2)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, Xo, Do, restart=30, maxit=300, rtol=1e-6, apply_nsw=3,
                         x0=x0)
     assert st == 0 and res["converged"] and abs(res["iters"] - ref["iters"]) <= 1
     if res["iters"] == ref["iters"]:
@@ -500,8 +502,9 @@ def test_profile_records_launches():
 @pytest.mark.slow
 def test_full_size_tri2000_f32():
     """The benchmark workload at full size, in the benchmark's launch configuration: 1 sync FP32
-    factor sweep vs the FP64 oracle over every block; 3 apply sweeps vs the oracle on the GPU's own
-    factor; SpMV; FGMRES(50) true residual checked by an oracle SpMV on the returned x."""
+    factor sweep vs the FP64 oracle over every block; 3 apply sweeps vs the oracle, both on the
+    oracle's factor rounded to FP32 on the host; SpMV; FGMRES(50) true residual checked by an
+    oracle SpMV on the returned x."""
     c = W.case("tri2000")
     s = DS(c, "f32", restart=50)
     s.factor(1, "sync")
@@ -509,12 +512,16 @@ def test_full_size_tri2000_f32():
     Xo, Do, tx, td = f32_tolerance(c, 1)
     print(f"full size f32 factor vs oracle: X {rel(X, Xo):.2e} (tol {tx:.1e}) Dinv {rel(D, Do):.2e} (tol {td:.1e})")
     assert rel(X, Xo) <= tx and rel(D, Do) <= td
-    del Xo, Do
+    del X, D
+    Xo = Xo.astype(np.float32).astype(np.float64)   # what the FP32 factor storage holds
+    Do = Do.astype(np.float32).astype(np.float64)
+    s.set_factor(Xo, Do)
     r = np.random.default_rng(0).uniform(-1, 1, 4 * c.n)
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
     s.apply(rt, zt, 3, "sync")
-    ref = oracle.apply_sync(c.n, c.rowptr, c.colidx, X, D, r, 3)
+    ref = oracle.apply_sync(c.n, c.rowptr, c.colidx, Xo, Do, r, 3)
+    del Xo, Do
     assert rel(zt.cpu().numpy(), ref) <= 1e-5
     s.spmv(rt, zt)
     assert rel(zt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r)) <= 1e-13
@@ -545,8 +552,9 @@ def test_full_size_tri300(cfl):
     r = np.random.default_rng(1).uniform(-1, 1, 4 * c.n)
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
+    s64.set_factor(Xo, Do)
     s64.apply(rt, zt, 2, "sync")
-    assert rel(zt.cpu().numpy(), oracle.apply_sync(c.n, c.rowptr, c.colidx, X, D, r, 2)) <= 1e-12
+    assert rel(zt.cpu().numpy(), oracle.apply_sync(c.n, c.rowptr, c.colidx, Xo, Do, r, 2)) <= 1e-12
     s32 = DS(c, "f32", restart=30)
     s32.factor(2, "sync")
     X32, D32 = s32.factor_host()

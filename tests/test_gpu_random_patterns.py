@@ -98,3 +98,28 @@ def test_random_pattern_parity(n, deg, order, seed):
     yt = torch.zeros_like(rt)
     s.spmv(rt, yt)
     assert rel(yt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r)) <= 1e-13
+
+
+@pytest.mark.parametrize("runner", ["levels", "rows"])
+@pytest.mark.parametrize("R", [3, 16])
+@pytest.mark.parametrize("n,deg,order,seed", PATTERNS, ids=lambda v: str(v))
+def test_random_pattern_chunked_parity(n, deg, order, seed, R, runner):
+    """Chunked synchronous sweeps (Gauss-Seidel within chunks of R consecutive rows, other chunks
+    read from the previous sweep, Section 3.3): two factor sweeps and two apply sweep pairs in
+    FP64 within 1e-12 of the oracle's chunked iteration, with both chunk runners."""
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    c = W.case("random", seed=seed, n=n, deg=deg, order=order)
+    print(f"random pattern n={n} deg={deg} order={order} seed={seed} R={R} runner={runner}", flush=True)
+    s = DeviceSystem(c, prec="f64", restart=10)
+    s.set_chunks(R, runner)
+    s.factor(2, "chunk_sync")
+    X, D = s.factor_host()
+    Xo, Do, fo = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, 2, R)
+    assert rel(X, Xo) <= 1e-12 and rel(D, Do) <= 1e-12
+    assert s.flags() == fo == 0
+    s.set_factor(Xo, Do)
+    r = np.random.default_rng(seed + 1).uniform(-1, 1, 4 * c.n)
+    rt = torch.from_numpy(r).cuda()
+    zt = torch.zeros_like(rt)
+    s.apply(rt, zt, 2, "chunk_sync")
+    assert rel(zt.cpu().numpy(), oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xo, Do, r, 2, R)) <= 1e-12

@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_1912_00539_amd import workloads as W
 from tests.dense_ref import rel
 
 pytestmark = pytest.mark.gpu
@@ -110,9 +111,9 @@ def single_path(req, prec, mode, fsw, nsw=3, restart=10, maxit=60, rtol=1e-6):
 
 
 def host_system(req):
-    n, z, rowptr, colidx, A, b = generated(req)
-    torch.cuda.synchronize()
-    return (n, rowptr.cpu().numpy(), colidx.cpu().numpy(), A.cpu().numpy().reshape(z, 4, 4), b.cpu().numpy())
+    """The request's system from the host twin of the device generator (the oracle's input)."""
+    c = W.request_case(req)
+    return c.n, c.rowptr, c.colidx, c.vals, c.b
 
 
 KEYS = ("status", "iters", "restarts", "converged", "reorth", "flags", "rel_true_residual")

@@ -54,10 +54,10 @@ def test_lines_and_line_orderings_bit_exact(name, theta, rho, order):
     assert nl == onl
     np.testing.assert_array_equal(lo, olo)
     np.testing.assert_array_equal(lp, olp)
-    np.testing.assert_array_equal(L.abilu_order(c.n, c.rowptr, c.colidx, "line", lo, lp), O.line_order(c.n, lo, lp))
+    np.testing.assert_array_equal(L.abilu_order(c.n, c.rowptr, c.colidx, "line", lo, lp), O.line_order(c.n, olo, olp))
     for x in ("rcm", "1wd"):
         np.testing.assert_array_equal(L.abilu_order(c.n, c.rowptr, c.colidx, f"line_{x}", lo, lp),
-                                      O.hybrid_line_order(c.n, c.rowptr, c.colidx, lo, lp, x))
+                                      O.hybrid_line_order(c.n, c.rowptr, c.colidx, olo, olp, x))
 
 
 def test_full_size_orderings_are_permutations_with_lines_contiguous():
@@ -138,5 +138,5 @@ def test_orderings_random_graphs_bit_exact(n, data, unsym):
     np.testing.assert_array_equal(lp, olp)
     for x in ("rcm", "1wd"):
         np.testing.assert_array_equal(L.abilu_order(n, rp, ci, f"line_{x}", lo, lp),
-                                      O.hybrid_line_order(n, rp, ci, lo, lp, x))
-    np.testing.assert_array_equal(L.abilu_order(n, rp, ci, "line", lo, lp), O.line_order(n, lo, lp))
+                                      O.hybrid_line_order(n, rp, ci, olo, olp, x))
+    np.testing.assert_array_equal(L.abilu_order(n, rp, ci, "line", lo, lp), O.line_order(n, olo, olp))
