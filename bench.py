@@ -132,6 +132,13 @@ def cpu_baseline(case, args):
         reps += 1
     t1 = time.perf_counter()
     by = reps * oracle_bytes_f64(n, Z, ZL, ZU, P, args.apply_sweeps)
+    # the sequential reference: traditional block ILU(0) and exact block substitutions, one thread
+    s0 = time.perf_counter()
+    Xs, Ds, _ = oracle.ilu0_seq(n, rp, ci, A)
+    s1 = time.perf_counter()
+    oracle.trisolve_exact(n, rp, ci, Xs, Ds, case.b)
+    s2 = time.perf_counter()
+    del Xs, Ds
     cpu_model = None
     try:
         for line in open("/proc/cpuinfo"):
@@ -145,7 +152,10 @@ def cpu_baseline(case, args):
             "sample": f"{reps} x (one synchronous FP64 factor sweep + {args.apply_sweeps} forward/backward sweep pairs "
                       f"+ one SpMV) on the full {n}-cell matrix ({t1 - t0:.1f} s); bytes from the same algorithmic "
                       "model as the GPU kernels, in FP64",
-            "seconds": round(t1 - t0, 2)}
+            "seconds": round(t1 - t0, 2),
+            "sequential": {"ilu0_ms": round((s1 - s0) * 1e3, 1), "exact_substitution_ms": round((s2 - s1) * 1e3, 1),
+                           "threads": 1, "what": "traditional block ILU(0) (row by row) and the exact forward and "
+                                                 "backward block substitutions, once each, on the full matrix"}}
 
 
 def load_traffic(kernel, shash):
