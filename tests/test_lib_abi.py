@@ -119,3 +119,13 @@ def test_serve_rejects_bad_arguments():
     done = C.c_int32()
     assert lib.abilu_serve_poll(None, 0, C.byref(done), None) == L.ABILU_EINVAL
     assert lib.abilu_serve_run(None, None, 0, None, None, None) == L.ABILU_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback: without the built HIP library every entry point raises."""
+    import pytest
+    from paper_1912_00539_amd import abilu
+    monkeypatch.setattr(abilu, "_lib", None)
+    monkeypatch.setattr(abilu, "LIB_PATH", "/nonexistent/libabilu.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        abilu.lib()
