@@ -438,6 +438,34 @@ def configs_bench(args):
                                     else "exceeds the 256 MB Infinity Cache")
         log(f"config {label}: {rows}")
         out[label] = rows
+    out["tri300_cfl_sweep"] = tri300_sweep_bench()
+    return out
+
+
+def tri300_sweep_bench():
+    """The 180,000-triangle workload at CFL 10, 100 and 1000: ILU residual after 1 to 4 FP32 factor
+    sweeps, SYNC and ASYNC, and the FGMRES(30) iterations to 1e-2 with 2 apply sweep pairs."""
+    import torch
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    out = {}
+    for cfl in (10.0, 100.0, 1000.0):
+        c = W.case("tri300", cfl=cfl)
+        s = DeviceSystem(c, prec="f32", restart=30)
+        rows = []
+        for nsw in (1, 2, 3, 4):
+            row = {"factor_sweeps": nsw}
+            for mode in ("sync", "async"):
+                s.factor(nsw, mode)
+                ilu = s.ilu_residual()
+                st, res = s.solve(apply_sweeps=2, mode=mode, rtol=1e-2, maxit=300)
+                row[mode] = {"ilu_residual": float(f"{ilu:.4e}"), "fgmres_iters": res["iters"],
+                             "converged": bool(res["converged"])}
+            rows.append(row)
+        log(f"tri300 CFL {cfl:g}: {rows}")
+        out[f"cfl{cfl:g}"] = rows
+        del s
+        torch.cuda.empty_cache()
     return out
 
 
