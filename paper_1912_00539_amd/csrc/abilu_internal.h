@@ -43,6 +43,10 @@ struct abilu_pattern {
     int32_t *order[2] = {nullptr, nullptr};
     int32_t *lvptr[2] = {nullptr, nullptr};
     int32_t *lvstart[2] = {nullptr, nullptr};
+    // dependency analysis (abilu_pattern_depth): depth D and the lower/upper level counts, -1 until
+    // computed
+    int32_t depth_D = -1;
+    int32_t levels[2] = {-1, -1};
 };
 
 namespace abilu {
@@ -94,6 +98,8 @@ abilu_status launch_status();   // hipGetLastError -> status (records the error 
 
 // Record a failed HIP call (text returned by abilu_last_error); true if e == hipSuccess.
 bool hip_ok(hipError_t e, const char *what);
+// Record an error text of the library's own (returned by abilu_last_error).
+void note_error(const char *what);
 
 // Algorithmic-byte model inputs of a pattern (doubles to avoid overflow in byte formulas).
 struct Sizes {
@@ -212,6 +218,42 @@ __device__ __forceinline__ double qb(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned long long)(unsigned)lo);
 }
 
+// Arithmetic of the block products. In double precision every product is rounded before it is
+// added and the terms are added left to right, with no fused multiply-add: the evaluation of a
+// plain loop over the terms, so that each double-precision result is reproducible operation for
+// operation. In single precision the compiler fuses products into the sums.
+template <typename T>
+__device__ __forceinline__ T dot4(T a0, T b0, T a1, T b1, T a2, T b2, T a3, T b3) {
+    if constexpr (sizeof(T) == 8) {
+#pragma clang fp contract(off)
+        return ((a0 * b0 + a1 * b1) + a2 * b2) + a3 * b3;
+    } else {
+        return a0 * b0 + a1 * b1 + a2 * b2 + a3 * b3;
+    }
+}
+
+// (((acc + a0 b0) + a1 b1) + a2 b2) + a3 b3: the products added to the accumulator one by one.
+template <typename T>
+__device__ __forceinline__ T acc_dot4(T acc, T a0, T b0, T a1, T b1, T a2, T b2, T a3, T b3) {
+    if constexpr (sizeof(T) == 8) {
+#pragma clang fp contract(off)
+        return (((acc + a0 * b0) + a1 * b1) + a2 * b2) + a3 * b3;
+    } else {
+        return (((acc + a0 * b0) + a1 * b1) + a2 * b2) + a3 * b3;
+    }
+}
+
+// a - b c (the product rounded first in double precision).
+template <typename T>
+__device__ __forceinline__ T sub_prod(T a, T b, T c) {
+    if constexpr (sizeof(T) == 8) {
+#pragma clang fp contract(off)
+        return a - b * c;
+    } else {
+        return a - b * c;
+    }
+}
+
 // Row r (this lane's row) of a 4x4 block at `blk` (row-major), converted to T.
 template <typename T, typename S>
 __device__ __forceinline__ void load_row(const S *blk, int r, T (&v)[4]) {
@@ -256,7 +298,7 @@ __device__ __forceinline__ void row_times_block(const T (&a)[4], const T (&brow)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         T b0 = qb<0>(brow[c]), b1 = qb<1>(brow[c]), b2 = qb<2>(brow[c]), b3 = qb<3>(brow[c]);
-        out[c] = a[0] * b0 + a[1] * b1 + a[2] * b2 + a[3] * b3;
+        out[c] = dot4(a[0], b0, a[1], b1, a[2], b2, a[3], b3);
     }
 }
 
@@ -266,7 +308,7 @@ __device__ __forceinline__ void row_times_block_sub(const T (&a)[4], const T (&b
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         T b0 = qb<0>(brow[c]), b1 = qb<1>(brow[c]), b2 = qb<2>(brow[c]), b3 = qb<3>(brow[c]);
-        acc[c] -= a[0] * b0 + a[1] * b1 + a[2] * b2 + a[3] * b3;
+        acc[c] -= dot4(a[0], b0, a[1], b1, a[2], b2, a[3], b3);
     }
 }
 
@@ -320,15 +362,15 @@ __device__ __forceinline__ bool inv4_row(T (&M)[16], int r, T (&out)[4]) {
         for (int q = k + 1; q < 4; ++q) {
             T f = M[q * 4 + k] / piv;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) M[q * 4 + c] -= f * M[k * 4 + c];
-            x[q] -= f * x[k];
+            for (int c = 0; c < 4; ++c) M[q * 4 + c] = sub_prod(M[q * 4 + c], f, M[k * 4 + c]);
+            x[q] = sub_prod(x[q], f, x[k]);
         }
     }
 #pragma unroll
     for (int k = 3; k >= 0; --k) {
         T s = x[k];
 #pragma unroll
-        for (int m = k + 1; m < 4; ++m) s -= M[k * 4 + m] * x[m];
+        for (int m = k + 1; m < 4; ++m) s = sub_prod(s, M[k * 4 + m], x[m]);
         x[k] = s / M[k * 4 + k];
     }
 #pragma unroll

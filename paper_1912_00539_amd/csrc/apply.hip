@@ -70,6 +70,15 @@ __global__ __launch_bounds__(64) void k_bwd_serial(int n, const int32_t *__restr
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(WG) void k_zero2(int64_t len, T *a, T *b) {
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t < len) {
+        a[t] = T(0);
+        b[t] = T(0);
+    }
+}
+
 // Chunked sweeps: workgroup c runs chunk c = rows [c0, c0 + R) level by level, one quad per row,
 // with a barrier after each level. Forward: y_i = r_i - sum_{j<i} L_ij y_j, where y_j comes from
 // this sweep (yn) for rows of the chunk and from the previous sweep (yo) for earlier rows; in the
@@ -100,7 +109,7 @@ __device__ __forceinline__ void fwd_chunk_row(int i, int c0, const int32_t *__re
         for (int u = 0; u < 2; ++u) {
             T yj[4];
             gather_vec(yv[u], yj);
-            const T c = l[u][0] * yj[0] + l[u][1] * yj[1] + l[u][2] * yj[2] + l[u][3] * yj[3];
+            const T c = dot4(l[u][0], yj[0], l[u][1], yj[1], l[u][2], yj[2], l[u][3], yj[3]);
             acc -= (e0 + u < b1) ? c : T(0);
         }
     }
@@ -136,14 +145,14 @@ __device__ __forceinline__ void bwd_chunk_row(int i, int c1, const int32_t *__re
         for (int u = 0; u < 2; ++u) {
             T zj[4];
             gather_vec(zv[u], zj);
-            const T c = u4[u][0] * zj[0] + u4[u][1] * zj[1] + u4[u][2] * zj[2] + u4[u][3] * zj[3];
+            const T c = dot4(u4[u][0], zj[0], u4[u][1], zj[1], u4[u][2], zj[2], u4[u][3], zj[3]);
             acc -= (e0 + u < b1) ? c : T(0);
         }
     }
     T dr[4], a[4];
     load_row(Dinv + (int64_t)i * BB, r, dr);
     gather_vec(acc, a);
-    zn[(int64_t)i * 4 + r] = (ZN)(dr[0] * a[0] + dr[1] * a[1] + dr[2] * a[2] + dr[3] * a[3]);
+    zn[(int64_t)i * 4 + r] = (ZN)dot4(dr[0], a[0], dr[1], a[1], dr[2], a[2], dr[3], a[3]);
 }
 
 template <typename T, bool ZERO_OUT>
@@ -254,10 +263,10 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
     // a value written in the same sweep; sweeps 2..nsw then update y and z in place. SYNC sweeps
     // read the previous sweep's vector (ping-pong ya/yb, za/zb).
     if (mode == ABILU_ASYNC_SERIAL) {
+        // zero initial guesses, cleared by a kernel (no memset node if the caller captures a graph)
         const int64_t nv = 4 * (int64_t)n;
-        if (!hip_ok(hipMemsetAsync(ya, 0, sizeof(T) * nv, s), "serial apply clear") ||
-            !hip_ok(hipMemsetAsync(za, 0, sizeof(T) * nv, s), "serial apply clear"))
-            return ABILU_EDEVICE;
+        k_zero2<T><<<div_up(nv, WG), WG, 0, s>>>(nv, ya, za);
+        LAUNCHED();
         for (int q = 1; q <= nsw; ++q) {
             ProfScope ps(NAME("apply_fwd"), s, bytes_fwd(zz, sF, sF, false));
             k_fwd_serial<T><<<1, 4, 0, s>>>(n, lrow, lcol, Lb, r, ya);

@@ -98,7 +98,7 @@ __device__ __forceinline__ void fwd_rows(int ib, int stride, int n, const int32_
             for (int u = 0; u < 2; ++u) {
                 T yj[4];
                 gather_vec(yv[h][u], yj);
-                const T c = l[h][u][0] * yj[0] + l[h][u][1] * yj[1] + l[h][u][2] * yj[2] + l[h][u][3] * yj[3];
+                const T c = dot4(l[h][u][0], yj[0], l[h][u][1], yj[1], l[h][u][2], yj[2], l[h][u][3], yj[3]);
                 acc[h] -= (b0[h] + t0 + u < b1[h]) ? c : T(0);
             }
     }
@@ -110,7 +110,7 @@ __device__ __forceinline__ void fwd_rows(int ib, int stride, int n, const int32_
                 T dr[4], yi[4];
                 load_row(Dinv + (int64_t)ii[h] * BB, r, dr);
                 gather_vec(acc[h], yi);
-                zout[(int64_t)ii[h] * 4 + r] = dr[0] * yi[0] + dr[1] * yi[1] + dr[2] * yi[2] + dr[3] * yi[3];
+                zout[(int64_t)ii[h] * 4 + r] = dot4(dr[0], yi[0], dr[1], yi[1], dr[2], yi[2], dr[3], yi[3]);
             }
         }
     }
@@ -170,7 +170,7 @@ __device__ __forceinline__ void bwd_rows(int ib, int stride, int n, const int32_
                 for (int u = 0; u < 2; ++u) {
                     T zj[4];
                     gather_vec(zv[h][u], zj);
-                    const T c = u4[h][u][0] * zj[0] + u4[h][u][1] * zj[1] + u4[h][u][2] * zj[2] + u4[h][u][3] * zj[3];
+                    const T c = dot4(u4[h][u][0], zj[0], u4[h][u][1], zj[1], u4[h][u][2], zj[2], u4[h][u][3], zj[3]);
                     acc[h] -= (b0[h] + t0 + u < b1[h]) ? c : T(0);
                 }
         }
@@ -181,7 +181,7 @@ __device__ __forceinline__ void bwd_rows(int ib, int stride, int n, const int32_
             T dr[4], a[4];
             load_row(Dinv + (int64_t)ii[h] * BB, r, dr);
             gather_vec(acc[h], a);
-            const T z = dr[0] * a[0] + dr[1] * a[1] + dr[2] * a[2] + dr[3] * a[3];
+            const T z = dot4(dr[0], a[0], dr[1], a[1], dr[2], a[2], dr[3], a[3]);
             zout[(int64_t)ii[h] * 4 + r] = (ZO)z;
             if constexpr (DUAL) zout2[(int64_t)ii[h] * 4 + r] = z;
         }
@@ -222,8 +222,8 @@ __device__ __forceinline__ void spmv_body(int blk, int n, const int32_t *__restr
         for (int u = 0; u < SCH; ++u) {
             double xj[4];
             gather_vec(xv[u], xj);
-            const double c = a[u][0] * xj[0] + a[u][1] * xj[1] + a[u][2] * xj[2] + a[u][3] * xj[3];
-            acc += (e0 + u < b1) ? c : 0.0;
+            const double t = acc_dot4(acc, a[u][0], xj[0], a[u][1], xj[1], a[u][2], xj[2], a[u][3], xj[3]);
+            acc = (e0 + u < b1) ? t : acc;
         }
     }
     y[(int64_t)i * 4 + r] = RESID ? b[(int64_t)i * 4 + r] - acc : acc;

@@ -65,3 +65,23 @@ def rel(a, b):
     d = np.linalg.norm((a - b).ravel())
     s = np.linalg.norm(b.ravel())
     return d / s if s > 0 else d
+
+
+def block_rel(a, b):
+    """Relative error of every block: ||a_k - b_k||_F / ||b_k||_F over the leading axis (a block
+    of b with zero norm gives its absolute error)."""
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    a = a.reshape(len(b), -1); b = b.reshape(len(b), -1)
+    dn = np.linalg.norm(a - b, axis=1)
+    bn = np.linalg.norm(b, axis=1)
+    return np.where(bn > 0, dn / np.where(bn > 0, bn, 1.0), dn)
+
+
+def assert_same_bits(a, b, what=""):
+    """Bit-for-bit equality (signed zeros compare equal), with the size of any difference."""
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    if not np.array_equal(a, b):
+        bad = a != b
+        raise AssertionError(f"{what}: {int(bad.sum())} of {a.size} values differ; relative error {rel(a, b):.3e}, "
+                             f"largest absolute difference {np.abs(a - b)[bad].max():.3e}")

@@ -15,7 +15,8 @@ import pytest
 
 import oracle
 from paper_1912_00539_amd import workloads as W
-from tests.dense_ref import rel
+from tests.dense_ref import assert_same_bits, rel
+from tests.f32_bars import FactorBars, VectorBars, report
 
 pytestmark = pytest.mark.gpu
 
@@ -148,15 +149,19 @@ def test_chunk_schedule_replaced_and_modes_need_it():
 
 
 # ------------------------------------------------------------------ CHUNK_SYNC factor vs the oracle
-def chunk_tolerance(c, nsw, R, prec, X0=None):
-    Xo, Do, _ = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, nsw, R, X0=X0)
+def check_chunked(c, nsw, R, prec, X, D, what=""):
+    """FP64: bit for bit against the chunked oracle (the GPU's block products and inverse evaluate
+    the oracle's operations in its order, and the Gauss-Seidel order within a chunk is the oracle's
+    row-major order). FP32: block by block (tests/f32_bars.py)."""
+    run = lambda A, X0: oracle.factor_chunked(c.n, c.rowptr, c.colidx, A, nsw, R, X0=X0)[:2]
     if prec == "f64":
-        d = np.random.default_rng(17).uniform(-1.0, 1.0, c.vals.shape) * 2.0 ** -53
-        Ap, floor = c.vals * (1.0 + d), 1e-12
-    else:
-        Ap, floor = c.vals.astype(np.float32).astype(np.float64), 1e-5
-    Xr, Dr, _ = oracle.factor_chunked(c.n, c.rowptr, c.colidx, Ap, nsw, R, X0=X0)
-    return Xo, Do, max(floor, 8 * rel(Xr, Xo)), max(floor, 8 * rel(Dr, Do))
+        Xo, Do = run(c.vals, None)
+        assert_same_bits(X, Xo, f"{what} X")
+        assert_same_bits(D, Do, f"{what} Dinv")
+        return None
+    out = FactorBars(run, c.vals).check(X, D, what)
+    report(f"{what} f32 chunked", out)
+    return out
 
 
 @pytest.mark.parametrize("runner", RUNNERS)
@@ -168,8 +173,7 @@ def test_factor_chunk_sync_f64(name, R, nsw, runner):
     s = DS(c, "f64", R=R, runner=runner)
     s.factor(nsw, "chunk_sync")
     X, D = s.factor_host()
-    Xo, Do, tx, td = chunk_tolerance(c, nsw, R, "f64")
-    assert rel(X, Xo) <= tx and rel(D, Do) <= td, (rel(X, Xo), tx, rel(D, Do), td)
+    check_chunked(c, nsw, R, "f64", X, D, name)
     assert s.flags() == 0
 
 
@@ -182,9 +186,7 @@ def test_factor_chunk_sync_f32(name, R, nsw, runner):
     s = DS(c, "f32", R=R, runner=runner)
     s.factor(nsw, "chunk_sync")
     X, D = s.factor_host()
-    Xo, Do, tx, td = chunk_tolerance(c, nsw, R, "f32")
-    print(f"f32 chunked vs f64 oracle: X {rel(X, Xo):.2e} (tol {tx:.1e}), Dinv {rel(D, Do):.2e} (tol {td:.1e})")
-    assert rel(X, Xo) <= tx and rel(D, Do) <= td
+    check_chunked(c, nsw, R, "f32", X, D, name)
 
 
 @pytest.mark.parametrize("runner", RUNNERS)
@@ -198,20 +200,20 @@ def test_factor_chunk_sync_warm_start(name, runner):
             s.factor(first, "chunk_sync")
             s.factor(second, "chunk_sync", init="LU")
             X, D = s.factor_host()
-            Xo, Do, tx, td = chunk_tolerance(c, first + second, 64, prec)
-            assert rel(X, Xo) <= tx and rel(D, Do) <= td, (prec, first, second)
+            check_chunked(c, first + second, 64, prec, X, D, f"{name} {first}+{second}")
 
 
 # ------------------------------------------------------------------ CHUNK_ASYNC factor: unique results
-def seq_tolerance(c, prec):
-    Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+def check_sequential(c, prec, X, D, what=""):
+    """Against the sequential block ILU(0): FP64 bit for bit (every block is then computed from
+    final values by the oracle's operations), FP32 block by block."""
+    run = lambda A, X0: oracle.ilu0_seq(c.n, c.rowptr, c.colidx, A)[:2]
     if prec == "f64":
-        d = np.random.default_rng(19).uniform(-1.0, 1.0, c.vals.shape) * 2.0 ** -53
-        Ap, floor = c.vals * (1.0 + d), 1e-12
+        Xs, Ds = run(c.vals, None)
+        assert_same_bits(X, Xs, f"{what} X")
+        assert_same_bits(D, Ds, f"{what} Dinv")
     else:
-        Ap, floor = c.vals.astype(np.float32).astype(np.float64), 1e-5
-    Xr, Dr, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, Ap)
-    return Xs, Ds, max(floor, 8 * rel(Xr, Xs)), max(floor, 8 * rel(Dr, Ds))
+        report(f"{what} f32 vs sequential ILU(0)", FactorBars(run, c.vals).check(X, D, what))
 
 
 @pytest.mark.parametrize("runner", RUNNERS)
@@ -221,13 +223,12 @@ def test_factor_single_chunk_is_sequential_ilu(name, prec, runner):
     """One chunk over every row: one sweep is the sequential block ILU(0) in both chunked modes,
     and the two modes (the same kernel reading only the chunk's own rows) agree bit for bit."""
     c = get(name)
-    Xs, Ds, tx, td = seq_tolerance(c, prec)
     out = []
     for mode in ("chunk_sync", "chunk_async"):
         s = DS(c, prec, R=4096, runner=runner)
         s.factor(1, mode)
         X, D = s.factor_host()
-        assert rel(X, Xs) <= tx and rel(D, Ds) <= td, (mode, rel(X, Xs), rel(D, Ds))
+        check_sequential(c, prec, X, D, f"{name} {mode}")
         out.append((X, D))
     np.testing.assert_array_equal(out[0][0], out[1][0])
     np.testing.assert_array_equal(out[0][1], out[1][1])
@@ -241,12 +242,11 @@ def test_factor_chunked_exact_after_one_sweep_per_chunk(name, R, runner):
     ran (CHUNK_ASYNC) -- and CHUNK_SYNC likewise."""
     c = get(name)
     nch = (c.n + R - 1) // R
-    Xs, Ds, tx, td = seq_tolerance(c, "f64")
     for mode in ("chunk_async", "chunk_sync"):
         s = DS(c, "f64", R=R, runner=runner)
         s.factor(nch, mode)
         X, D = s.factor_host()
-        assert rel(X, Xs) <= tx and rel(D, Ds) <= td, (mode, rel(X, Xs), rel(D, Ds))
+        check_sequential(c, "f64", X, D, f"{name} {mode}")
         assert s.ilu_residual() <= 1e-12
 
 
@@ -286,7 +286,7 @@ def test_apply_chunk_sync_f64(name, R, nsw, runner):
     zt = torch.zeros_like(rt)
     s.apply(rt, zt, nsw, "chunk_sync")
     ref = oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xo, Do, r, nsw, R)
-    assert rel(zt.cpu().numpy(), ref) <= 1e-12
+    assert_same_bits(zt.cpu().numpy(), ref, "z")
 
 
 @pytest.mark.parametrize("runner", RUNNERS)
@@ -303,8 +303,9 @@ def test_apply_chunk_sync_f32(name, nsw, runner):
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
     s.apply(rt, zt, nsw, "chunk_sync")
-    ref = oracle.apply_chunked(c.n, c.rowptr, c.colidx, X, D, r, nsw, 64)
-    assert rel(zt.cpu().numpy(), ref) <= 1e-5
+    bars = VectorBars(lambda X_, D_, r_: oracle.apply_chunked(c.n, c.rowptr, c.colidx, X_, D_, r_, nsw, 64), X, D, r)
+    e, worst = bars.check(zt.cpu().numpy(), name)
+    print(f"{name} f32 chunked apply {nsw}: rel {e:.2e}, worst cell at {worst:.2f} of its bar")
 
 
 @pytest.mark.parametrize("runner", RUNNERS)
@@ -325,7 +326,7 @@ def test_apply_chunked_exact(name, R, runner):
     for mode in ("chunk_sync", "chunk_async"):
         zt = torch.zeros_like(rt)
         s.apply(rt, zt, nch, mode)
-        assert rel(zt.cpu().numpy(), ref) <= 1e-12, mode
+        assert_same_bits(zt.cpu().numpy(), ref, mode)
 
 
 def test_apply_chunk_async_converges():
@@ -375,10 +376,8 @@ def test_full_size_tri300_chunk_sync(prec):
         s = DS(c, prec, R=64)
         s.factor(nsw, "chunk_sync")
         X, D = s.factor_host()
-        Xo, Do, _ = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, nsw, 64)
-        tol = 1e-12 if prec == "f64" else 1e-5
-        print(f"{prec} nsw {nsw}: X {rel(X, Xo):.2e} Dinv {rel(D, Do):.2e}")
-        assert rel(X, Xo) <= tol and rel(D, Do) <= tol
+        check_chunked(c, nsw, 64, prec, X, D, f"tri300 {nsw}")
+    Xo, Do, _ = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, 2, 64)
     if prec == "f32":   # the oracle factor as FP32 storage holds it
         Xo, Do = Xo.astype(np.float32).astype(np.float64), Do.astype(np.float32).astype(np.float64)
     s.set_factor(Xo, Do)
@@ -386,8 +385,11 @@ def test_full_size_tri300_chunk_sync(prec):
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
     s.apply(rt, zt, 2, "chunk_sync")
-    ref = oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xo, Do, r, 2, 64)
-    assert rel(zt.cpu().numpy(), ref) <= (1e-12 if prec == "f64" else 1e-5)
+    run = lambda X_, D_, r_: oracle.apply_chunked(c.n, c.rowptr, c.colidx, X_, D_, r_, 2, 64)
+    if prec == "f64":
+        assert_same_bits(zt.cpu().numpy(), run(Xo, Do, r), "z")
+    else:
+        VectorBars(run, Xo, Do, r).check(zt.cpu().numpy(), "tri300")
 
 
 def test_full_size_aniso1000_line_chunk_sync():
@@ -398,9 +400,7 @@ def test_full_size_aniso1000_line_chunk_sync():
     s = DS(c, "f64", R=64)
     s.factor(1, "chunk_sync")
     X, D = s.factor_host()
-    Xo, Do, tx, td = chunk_tolerance(c, 1, 64, "f64")
-    print(f"aniso1000 line, 1 chunked sweep: X {rel(X, Xo):.2e} (tol {tx:.1e}) Dinv {rel(D, Do):.2e} (tol {td:.1e})")
-    assert rel(X, Xo) <= tx and rel(D, Do) <= td
+    check_chunked(c, 1, 64, "f64", X, D, "aniso1000 line")
     s32 = DS(c, "f32", restart=30, R=64)
     s32.factor(1, "chunk_async")
     st, res = s32.solve(apply_sweeps=3, mode="chunk_async", rtol=1e-2, maxit=300)
@@ -437,8 +437,8 @@ def test_line_ordering_then_chunked_sweeps():
         s = DS(c, "f64", R=16)
         s.factor(1, "chunk_sync")
         X, D = s.factor_host()
-        Xo, Do, tx, td = chunk_tolerance(c, 1, 16, "f64")
-        assert rel(X, Xo) <= tx and rel(D, Do) <= td, name
+        check_chunked(c, 1, 16, "f64", X, D, name)
+        Xo, _, _ = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, 1, 16)
         res[name] = s.ilu_residual()
         assert abs(res[name] - oracle.ilu_residual(c.n, c.rowptr, c.colidx, c.vals, Xo)) <= 1e-10 * res[name]
         s32 = DS(c, "f32", restart=30, R=16)

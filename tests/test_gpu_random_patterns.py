@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_1912_00539_amd import workloads as W
-from tests.dense_ref import rel
+from tests.dense_ref import assert_same_bits, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -75,14 +75,16 @@ def test_random_pattern_parity(n, deg, order, seed):
     s.factor(2, "sync")
     X2, D2 = s.factor_host()
     Xo, Do, fo = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 2)
-    assert rel(X2, Xo) <= 1e-12 and rel(D2, Do) <= 1e-12
+    assert_same_bits(X2, Xo, "X")
+    assert_same_bits(D2, Do, "Dinv")
     assert s.flags() == fo == 0
     # exactness at the depth, synchronous and asynchronous
     D, _ = oracle.depth(c.n, c.rowptr, c.colidx)
     Xs, Ds, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
     s.factor(D, "sync")
     Xg, Dg = s.factor_host()
-    assert rel(Xg, Xs) <= 1e-12 and rel(Dg, Ds) <= 1e-12
+    assert_same_bits(Xg, Xs, "X at depth")
+    assert_same_bits(Dg, Ds, "Dinv at depth")
     t = DS(c)
     t.factor(D + 2, "async")
     Xa, Da = t.factor_host()
@@ -94,10 +96,10 @@ def test_random_pattern_parity(n, deg, order, seed):
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
     s.apply(rt, zt, 3, "sync")
-    assert rel(zt.cpu().numpy(), oracle.apply_sync(c.n, c.rowptr, c.colidx, Xo, Do, r, 3)) <= 1e-12
+    assert_same_bits(zt.cpu().numpy(), oracle.apply_sync(c.n, c.rowptr, c.colidx, Xo, Do, r, 3), "z")
     yt = torch.zeros_like(rt)
     s.spmv(rt, yt)
-    assert rel(yt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r)) <= 1e-13
+    assert_same_bits(yt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r), "SpMV")
 
 
 @pytest.mark.parametrize("runner", ["levels", "rows"])
@@ -115,11 +117,12 @@ def test_random_pattern_chunked_parity(n, deg, order, seed, R, runner):
     s.factor(2, "chunk_sync")
     X, D = s.factor_host()
     Xo, Do, fo = oracle.factor_chunked(c.n, c.rowptr, c.colidx, c.vals, 2, R)
-    assert rel(X, Xo) <= 1e-12 and rel(D, Do) <= 1e-12
+    assert_same_bits(X, Xo, "X")
+    assert_same_bits(D, Do, "Dinv")
     assert s.flags() == fo == 0
     s.set_factor(Xo, Do)
     r = np.random.default_rng(seed + 1).uniform(-1, 1, 4 * c.n)
     rt = torch.from_numpy(r).cuda()
     zt = torch.zeros_like(rt)
     s.apply(rt, zt, 2, "chunk_sync")
-    assert rel(zt.cpu().numpy(), oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xo, Do, r, 2, R)) <= 1e-12
+    assert_same_bits(zt.cpu().numpy(), oracle.apply_chunked(c.n, c.rowptr, c.colidx, Xo, Do, r, 2, R), "z")
