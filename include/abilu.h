@@ -107,9 +107,39 @@ abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_rowptr, const 
  * all work that uses it. */
 abilu_status abilu_pattern_destroy(abilu_pattern *p);
 
-/* Sizes of a pattern: block rows N, block nonzeros Z, total length of the update-set lists. */
-abilu_status abilu_pattern_info(const abilu_pattern *p, int32_t *nbrows, int64_t *nnzb,
-                                int64_t *npairs);
+/* Sizes of a pattern: block rows N, block nonzeros Z, total length of the update-set lists, and
+ * the dependency figures of abilu_pattern_depth: the depth D, the number of levels of the strictly
+ * lower and strictly upper triangle (each -1 until abilu_pattern_depth has computed them). Any
+ * output pointer may be NULL. Non-blocking (reads host fields only). */
+abilu_status abilu_pattern_info(const abilu_pattern *p, int32_t *nbrows, int64_t *nnzb, int64_t *npairs,
+                                int32_t *depth_D, int32_t *levels_lower, int32_t *levels_upper);
+
+/*
+ * Dependency analysis of the block ILU fixed-point problem on the device.
+ *  - Depth (Lemma 2 and Theorem 8, Section 4.2): in the Gaussian-elimination ordering of the
+ *    blocks the fixed-point map h is strictly lower triangular; block (i,j) reads X_ik and X_kj for
+ *    k in K(i,j), and X_jj when i > j. depth(i,j) = 1 + the largest depth of what it reads (1 if
+ *    nothing). After p synchronous sweeps every block of depth <= p holds its fixed-point value, so
+ *    the sweeps are exact after D = max depth sweeps.
+ *  - Levels (Theorem 3, Section 4.1): the lower level of row i is 1 + the largest lower level of
+ *    its strictly lower neighbours j < i (1 if none), the upper level likewise over j > i. A
+ *    forward (backward) Jacobi sweep solve is exact after as many sweeps as there are lower (upper)
+ *    levels.
+ * Computed by monotone relaxation passes over all blocks and rows in place (every value starts
+ * below its fixed point and only grows towards it), until a pass changes nothing; the result is
+ * exact whatever order the passes' reads see. The three counts are kept in the pattern (returned by
+ * abilu_pattern_info afterwards).
+ *   d_depth         device int32[Z]: depth of every block in CSR order (may be NULL)
+ *   d_level_lower   device int32[N]: lower level of every row (may be NULL)
+ *   d_level_upper   device int32[N]: upper level of every row (may be NULL)
+ *   depth_D, levels_lower, levels_upper: host outputs (may be NULL); D = 0 and no levels for N = 0
+ * Allocates and frees temporary device memory (a set-up call, like abilu_build_pattern); no work
+ * that uses the pattern may be in flight. Blocks on `stream`. Errors: ABILU_EINVAL, ABILU_ENOMEM,
+ * ABILU_EDEVICE.
+ */
+abilu_status abilu_pattern_depth(abilu_pattern *p, int32_t *d_depth, int32_t *d_level_lower,
+                                 int32_t *d_level_upper, int32_t *depth_D, int32_t *levels_lower,
+                                 int32_t *levels_upper, void *stream);
 
 /* Copy the pattern's analysis to caller device buffers (for verification): d_diag_pos int32[N],
  * d_pair_ptr int32[Z+1], d_pik int32[npairs], d_pkj int32[npairs]. Any pointer may be NULL. */
@@ -319,6 +349,30 @@ abilu_status fgmres_solve(const abilu_pattern *p, const double *d_A, const doubl
  */
 abilu_status abilu_ilu_residual(const abilu_pattern *p, const double *d_A, const void *d_LU,
                                 abilu_prec prec, void *d_work, size_t work_bytes, double *h_rel,
+                                void *stream);
+
+/*
+ * Largest entry-wise difference between a factor and a reference factor, both in the factor
+ * layout: *h_lower = max |X - Y| over the entries of the strictly lower blocks (L), *h_upper over
+ * the diagonal and strictly upper blocks (U). With Y the exact incomplete factors X_ilu, two calls
+ * give the factor errors the paper follows against the sweep count (Section 6.2):
+ * ||vec(L - L_ilu)||_inf / ||vec(L_0 - L_ilu)||_inf and likewise for U (L_0, U_0 the initial guess,
+ * A in the factor layout by abilu_factor_from_csr). A NaN anywhere shows as NaN.
+ *   d_X  prec[Z][4][4] (factor layout); d_Y double[Z][4][4] (factor layout)
+ * Uses the workspace's reduction area (work_bytes >= abilu_workspace_bytes(p, prec, 0)). Blocks.
+ */
+abilu_status abilu_factor_maxdiff(const abilu_pattern *p, abilu_prec prec, const void *d_X, const double *d_Y,
+                                  void *d_work, size_t work_bytes, double *h_lower, double *h_upper, void *stream);
+
+/*
+ * Max-norms of the Jacobi iteration matrices of the two block triangular solves (Section 6.2:
+ * a smaller norm is a more diagonally dominant factor): *h_norm_l = ||L_strict||_inf (L has a unit
+ * diagonal) and *h_norm_u = ||D^{-1} U_strict||_inf with D the block diagonal of U (D^{-1} = Dinv),
+ * each the largest absolute scalar row sum. Block products in the factor precision, sums in double.
+ * A NaN anywhere shows as NaN. d_LU prec (factor layout), d_Dinv prec[N][4][4]. Blocks.
+ */
+abilu_status abilu_jacobi_norms(const abilu_pattern *p, abilu_prec prec, const void *d_LU, const void *d_Dinv,
+                                void *d_work, size_t work_bytes, double *h_norm_l, double *h_norm_u,
                                 void *stream);
 
 /* Read (and if `clear`, reset) the workspace flag word. Blocks on `stream`. */

@@ -63,6 +63,9 @@ def _lib():
         L.oracle_fixed_point_residual.restype = C.c_double
         L.oracle_jacobi_norms.argtypes = [C.c_int, i32p, i32p, f64p, f64p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_jacobi_norms.restype = None
+        L.oracle_factor_error.argtypes = [C.c_int, i32p, i32p, f64p, f64p, f64p, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
+        L.oracle_factor_error.restype = None
         L.oracle_num_threads.argtypes = []; L.oracle_num_threads.restype = C.c_int
         _LIB = L
     return _LIB
@@ -244,3 +247,13 @@ def jacobi_norms(n, rowptr, colidx, X, Dinv):
     _lib().oracle_jacobi_norms(n, rp, ci, _c(X, np.float64).reshape(-1), _c(Dinv, np.float64).reshape(-1),
                                C.byref(a), C.byref(b))
     return a.value, b.value
+
+
+def factor_error(n, rowptr, colidx, X, X0, Xilu):
+    """(L error, U error): ||vec(L - L_ilu)||_inf / ||vec(L0 - L_ilu)||_inf and likewise for U, the
+    factors in CSR block order (Section 6.2)."""
+    rp, ci = _pat(rowptr, colidx)
+    eL, eU = C.c_double(), C.c_double()
+    _lib().oracle_factor_error(int(n), rp, ci, _c(X, np.float64).reshape(-1), _c(X0, np.float64).reshape(-1),
+                               _c(Xilu, np.float64).reshape(-1), C.byref(eL), C.byref(eU))
+    return eL.value, eU.value

@@ -735,6 +735,30 @@ void oracle_jacobi_norms(int n, const int *rowptr, const int *colidx, const doub
     *normU = mU;
 }
 
+/* Factor errors of the ILU-convergence study (Section 6.2): the largest absolute entry of
+ * X - X_ilu over the strictly lower blocks, divided by the largest of X0 - X_ilu over the same
+ * blocks (the L error), and likewise over the diagonal and strictly upper blocks (the U error).
+ * X, X0 and X_ilu are factors in CSR block order. A zero denominator gives the bare numerator. */
+void oracle_factor_error(int n, const int *rowptr, const int *colidx, const double *X,
+                         const double *X0, const double *Xilu, double *errL, double *errU) {
+    double numL = 0.0, denL = 0.0, numU = 0.0, denU = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (long e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            for (int q = 0; q < BB; ++q) {
+                double a = fabs(X[e * BB + q] - Xilu[e * BB + q]);
+                double b = fabs(X0[e * BB + q] - Xilu[e * BB + q]);
+                if (colidx[e] < i) {
+                    if (a > numL) numL = a;
+                    if (b > denL) denL = b;
+                } else {
+                    if (a > numU) numU = a;
+                    if (b > denU) denU = b;
+                }
+            }
+    *errL = denL > 0 ? numL / denL : numL;
+    *errU = denU > 0 ? numU / denU : numU;
+}
+
 /* number of OpenMP threads the parallel loops above use (1 without OpenMP) */
 int oracle_num_threads(void) {
 #ifdef _OPENMP

@@ -111,7 +111,11 @@ def lib():
         sig = {
             "abilu_build_pattern": ([i32, vp, vp, i32, vp, C.POINTER(vp)], st),
             "abilu_pattern_destroy": ([vp], st),
-            "abilu_pattern_info": ([vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)], st),
+            "abilu_pattern_info": ([vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32),
+                                    C.POINTER(i32), C.POINTER(i32)], st),
+            "abilu_pattern_depth": ([vp, vp, vp, vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), vp], st),
+            "abilu_factor_maxdiff": ([vp, st, vp, vp, vp, sz, C.POINTER(C.c_double), C.POINTER(C.c_double), vp], st),
+            "abilu_jacobi_norms": ([vp, st, vp, vp, vp, sz, C.POINTER(C.c_double), C.POINTER(C.c_double), vp], st),
             "abilu_pattern_export": ([vp, vp, vp, vp, vp, vp], st),
             "abilu_pattern_set_chunks": ([vp, i32, i32, vp], st),
             "abilu_pattern_chunk_info": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
@@ -192,9 +196,18 @@ class Pattern:
         self.handle = C.c_void_p(handle)
 
     def info(self):
+        """(N, Z, npairs)."""
         n = C.c_int32(); z = C.c_int64(); npairs = C.c_int64()
-        _check(lib().abilu_pattern_info(self.handle, C.byref(n), C.byref(z), C.byref(npairs)), "abilu_pattern_info")
+        _check(lib().abilu_pattern_info(self.handle, C.byref(n), C.byref(z), C.byref(npairs), None, None, None),
+               "abilu_pattern_info")
         return n.value, z.value, npairs.value
+
+    def dependency_info(self):
+        """(depth D, lower levels, upper levels) as abilu_pattern_info reports them (-1: not computed)."""
+        d = C.c_int32(); ll = C.c_int32(); lu = C.c_int32()
+        _check(lib().abilu_pattern_info(self.handle, None, None, None, C.byref(d), C.byref(ll), C.byref(lu)),
+               "abilu_pattern_info")
+        return d.value, ll.value, lu.value
 
     def destroy(self):
         if self.handle is not None and self.handle.value:
@@ -218,6 +231,15 @@ def abilu_build_pattern(nbrows: int, rowptr, colidx, bs: int = 4, stream=None) -
 def abilu_pattern_export(p: Pattern, diag_pos=None, pair_ptr=None, pik=None, pkj=None, stream=None):
     _check(lib().abilu_pattern_export(p.handle, _ptr(diag_pos), _ptr(pair_ptr), _ptr(pik), _ptr(pkj),
                                       _stream(stream)), "abilu_pattern_export")
+
+
+def abilu_pattern_depth(p: Pattern, depth=None, level_lower=None, level_upper=None, stream=None):
+    """Dependency analysis on the device: (D, lower levels, upper levels); optional int32 device
+    tensors receive the depth of every block (CSR order) and the level of every row."""
+    d = C.c_int32(); ll = C.c_int32(); lu = C.c_int32()
+    _check(lib().abilu_pattern_depth(p.handle, _ptr(depth), _ptr(level_lower), _ptr(level_upper), C.byref(d),
+                                     C.byref(ll), C.byref(lu), _stream(stream)), "abilu_pattern_depth")
+    return d.value, ll.value, lu.value
 
 
 def abilu_pattern_set_chunks(p: Pattern, rows_per_chunk: int, runner: str = "auto", stream=None):
@@ -325,6 +347,25 @@ def abilu_ilu_residual(p: Pattern, A, LU, prec: str, work, stream=None) -> float
                                     work.numel() * work.element_size(), C.byref(out), _stream(stream)),
            "abilu_ilu_residual")
     return out.value
+
+
+def abilu_factor_maxdiff(p: Pattern, prec: str, X, Y, work, stream=None):
+    """(max |X - Y| over the strictly lower blocks, over the diagonal and upper blocks); Y double,
+    both in the factor layout."""
+    lo = C.c_double(); up = C.c_double()
+    _check(lib().abilu_factor_maxdiff(p.handle, PRECS[prec], _ptr(X), _ptr(Y), _ptr(work),
+                                      work.numel() * work.element_size(), C.byref(lo), C.byref(up), _stream(stream)),
+           "abilu_factor_maxdiff")
+    return lo.value, up.value
+
+
+def abilu_jacobi_norms(p: Pattern, prec: str, LU, Dinv, work, stream=None):
+    """(||L_strict||_inf, ||Dinv U_strict||_inf)."""
+    nl = C.c_double(); nu = C.c_double()
+    _check(lib().abilu_jacobi_norms(p.handle, PRECS[prec], _ptr(LU), _ptr(Dinv), _ptr(work),
+                                    work.numel() * work.element_size(), C.byref(nl), C.byref(nu), _stream(stream)),
+           "abilu_jacobi_norms")
+    return nl.value, nu.value
 
 
 def abilu_read_flags(work, clear: bool = False, stream=None) -> int:

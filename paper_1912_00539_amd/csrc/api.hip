@@ -56,6 +56,8 @@ bool hip_ok(hipError_t e, const char *what) {
     return false;
 }
 
+void note_error(const char *what) { snprintf(g_last_error, sizeof g_last_error, "%s", what); }
+
 abilu_status launch_status() { return hip_ok(hipGetLastError(), "kernel launch") ? ABILU_OK : ABILU_EDEVICE; }
 
 // ------------------------------------------------------------------ profiling

@@ -245,11 +245,15 @@ extern "C" abilu_status abilu_pattern_destroy(abilu_pattern *p) {
 }
 
 extern "C" abilu_status abilu_pattern_info(const abilu_pattern *p, int32_t *nbrows, int64_t *nnzb,
-                                           int64_t *npairs) {
+                                           int64_t *npairs, int32_t *depth_D, int32_t *levels_lower,
+                                           int32_t *levels_upper) {
     if (!p) return ABILU_EINVAL;
     if (nbrows) *nbrows = p->n;
     if (nnzb) *nnzb = p->nnzb;
     if (npairs) *npairs = p->npairs;
+    if (depth_D) *depth_D = p->depth_D;
+    if (levels_lower) *levels_lower = p->levels[0];
+    if (levels_upper) *levels_upper = p->levels[1];
     return ABILU_OK;
 }
 

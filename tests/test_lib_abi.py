@@ -61,6 +61,11 @@ def test_argument_checks_without_device():
     assert lib.abilu_pattern_chunk_info(None, None, None, None, None, None, None, None) == L.ABILU_EINVAL
     assert lib.abilu_pattern_chunk_export(None, 0, None, None, None, None) == L.ABILU_EINVAL
     assert lib.abilu_stream_copy(None, None, 7, None) == L.ABILU_EINVAL
+    assert lib.abilu_pattern_info(None, None, None, None, None, None, None) == L.ABILU_EINVAL
+    assert lib.abilu_pattern_depth(None, None, None, None, None, None, None, None) == L.ABILU_EINVAL
+    d = C.c_double()
+    assert lib.abilu_factor_maxdiff(None, L.ABILU_F32, None, None, None, 0, C.byref(d), C.byref(d), None) == L.ABILU_EINVAL
+    assert lib.abilu_jacobi_norms(None, L.ABILU_F32, None, None, None, 0, C.byref(d), C.byref(d), None) == L.ABILU_EINVAL
     assert lib.abilu_profile_enable(1, 0) == L.ABILU_EINVAL
 
 

@@ -455,6 +455,36 @@ def test_diagnostics(name, c):
     assert abs(nU - np.abs(np.linalg.inv(Dm) @ (U - Dm)).sum(axis=1).max()) < 1e-12
 
 
+@pytest.mark.parametrize("name,c", small_cases())
+def test_factor_error(name, c):
+    """The factor errors of the ILU-convergence study (Section 6.2): against the dense factors
+    (the L error is the largest entry of the dense unit-lower L - L_ilu over that of L0 - L_ilu,
+    whose identity diagonals cancel; the U error likewise over the dense U), exactly 1 at the
+    initial guess and 0 at X_ilu, |1 - t| on the segment from X0 to X_ilu, and 0 after the
+    synchronous sweeps reach the depth."""
+    Xs, _, _ = oracle.ilu0_seq(c.n, c.rowptr, c.colidx, c.vals)
+    X0 = c.vals
+    X1, _, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    eL, eU = oracle.factor_error(c.n, c.rowptr, c.colidx, X1, X0, Xs)
+    L1, U1 = factors_dense(c.n, c.rowptr, c.colidx, X1)
+    Ls, Us = factors_dense(c.n, c.rowptr, c.colidx, Xs)
+    L0, U0 = factors_dense(c.n, c.rowptr, c.colidx, X0)
+    dL0 = np.abs(L0 - Ls).max()
+    refL = np.abs(L1 - Ls).max() / dL0 if dL0 > 0 else np.abs(L1 - Ls).max()
+    refU = np.abs(U1 - Us).max() / np.abs(U0 - Us).max()
+    assert eL == refL and eU == refU
+    assert oracle.factor_error(c.n, c.rowptr, c.colidx, Xs, X0, Xs) == (0.0, 0.0)
+    e0 = oracle.factor_error(c.n, c.rowptr, c.colidx, X0, X0, Xs)
+    assert e0[1] == 1.0 and e0[0] == (1.0 if dL0 > 0 else 0.0)
+    for t in (0.25, 0.5, 0.75):
+        Xt = X0 + t * (Xs - X0)
+        et = oracle.factor_error(c.n, c.rowptr, c.colidx, Xt, X0, Xs)
+        assert abs(et[1] - (1 - t)) <= 1e-12 and (dL0 == 0 or abs(et[0] - (1 - t)) <= 1e-12), (t, et)
+    D, _ = oracle.depth(c.n, c.rowptr, c.colidx)
+    XD, _, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, D)
+    assert oracle.factor_error(c.n, c.rowptr, c.colidx, XD, X0, Xs) == (0.0, 0.0)
+
+
 def test_generator_shapes():
     c = W.case("quad32")
     assert (c.n, c.nnzb) == (1024, 4992)
