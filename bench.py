@@ -21,7 +21,8 @@ The "orderings" object measures the step under the orderings of Section 5 (RCM, 
 dissection, lines of anisotropic cells, line and hybrid line-X orderings).
 The "configs" object gives factor and apply bandwidth on the 180,000-triangle and the
 500,000-cell anisotropic workloads (line and RCM order), SYNC/ASYNC, FP32/FP64.
-Prints one JSON line.
+The full result object goes to a detail file (--detail) and to stderr; the last line of stdout is a
+compact headline of a few KB (the figures above and a summary of each sub-benchmark).
 """
 import argparse
 import hashlib
@@ -112,8 +113,25 @@ def oracle_bytes_f64(N, Z, ZL, ZU, P, apply_sweeps):
     return sweep + apply_sweeps * (fwd + bwd) + spmv
 
 
-def cpu_baseline(case, args):
-    """The oracle as it stands, on the host cores, on a bounded sample of the same workload."""
+def gpu_sync_factors(case):
+    """One synchronous factor sweep from A on the GPU in FP64 and FP32, as (X in CSR block order,
+    Dinv) float64 host arrays, for the check against the oracle in cpu_baseline."""
+    import torch
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    out = {}
+    for prec in ("f64", "f32"):
+        s = DeviceSystem(case, prec=prec, restart=1)
+        s.factor(1, "sync")
+        out[prec] = s.factor_host()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(case, args, gpu=None):
+    """The oracle as it stands, on the host cores, on a bounded sample of the same workload. With
+    `gpu` (gpu_sync_factors), the oracle's one-sweep factor of the first sample is also compared
+    with the GPU's: FP64 bit for bit, FP32 as relative errors."""
     import numpy as np
     import oracle
     n, rp, ci, A = case.n, case.rowptr, case.colidx, case.vals
@@ -124,9 +142,14 @@ def cpu_baseline(case, args):
     ZL = int(np.count_nonzero(ci < rows))
     ZU = Z - n - ZL
     reps = 0
+    check = None
     t0 = time.perf_counter()
     while reps < 50 and (reps == 0 or time.perf_counter() - t0 < 10.0):
         X, D, _ = oracle.factor_sync(n, rp, ci, A, 1)
+        if reps == 0 and gpu:
+            tc = time.perf_counter()
+            check = oracle_check(X, D, gpu)
+            t0 += time.perf_counter() - tc   # the comparison is not oracle work
         z = oracle.apply_sync(n, rp, ci, X, D, case.b, args.apply_sweeps)
         oracle.spmv(n, rp, ci, A, z)
         reps += 1
@@ -152,10 +175,33 @@ def cpu_baseline(case, args):
             "sample": f"{reps} x (one synchronous FP64 factor sweep + {args.apply_sweeps} forward/backward sweep pairs "
                       f"+ one SpMV) on the full {n}-cell matrix ({t1 - t0:.1f} s); bytes from the same algorithmic "
                       "model as the GPU kernels, in FP64",
-            "seconds": round(t1 - t0, 2),
+            "seconds": round(t1 - t0, 2), "oracle_check": check,
             "sequential": {"ilu0_ms": round((s1 - s0) * 1e3, 1), "exact_substitution_ms": round((s2 - s1) * 1e3, 1),
                            "threads": 1, "what": "traditional block ILU(0) (row by row) and the exact forward and "
                                                  "backward block substitutions, once each, on the full matrix"}}
+
+
+def oracle_check(X, D, gpu):
+    """GPU one-sweep synchronous factors against the oracle's (X, D): FP64 bitwise equality and the
+    largest relative difference; FP32 relative Frobenius and largest per-block relative errors."""
+    import numpy as np
+
+    def errs(a, ref):
+        d = (a - ref).reshape(len(ref), -1)
+        rn = np.linalg.norm(ref.reshape(len(ref), -1), axis=1)
+        dn = np.linalg.norm(d, axis=1)
+        nz = rn > 0
+        return {"rel": float(f"{np.linalg.norm(d) / np.linalg.norm(ref):.3e}"),
+                "max_block_rel": float(f"{(dn[nz] / rn[nz]).max() if nz.any() else 0.0:.3e}")}
+    out = {"what": "one synchronous factor sweep from A on the full matrix, GPU against the oracle"}
+    if "f64" in gpu:
+        Xg, Dg = gpu["f64"]
+        out["f64_bitwise_equal"] = bool(np.array_equal(Xg, X) and np.array_equal(Dg, D))
+        out["f64"] = {"X": errs(Xg, X), "Dinv": errs(Dg, D)}
+    if "f32" in gpu:
+        Xg, Dg = gpu["f32"]
+        out["f32"] = {"X": errs(Xg, X), "Dinv": errs(Dg, D)}
+    return out
 
 
 def load_traffic(kernel, shash):
@@ -225,6 +271,20 @@ def serving_bench(args):
         return out
 
     sat = {name: run(name, None) for name in forms}
+    kernel_profile = None
+    if "batched_f32" in forms and args.serve_profile:
+        # the same saturation run again with a HIP event pair around every batched launch: each
+        # kernel's bandwidth against the sum of its members' algorithmic bytes
+        srv = L.Server(forms["batched_f32"], pool)
+        L.abilu_profile_enable(True, 400000)
+        srv.run(reqs)
+        rep = L.abilu_profile_report()
+        L.abilu_profile_enable(False)
+        srv.destroy()
+        kernel_profile = {k: {"launches": v[0], "ms": round(v[1], 3), "GB": round(v[2] / 1e9, 2),
+                              "GBps": round(v[2] / (v[1] / 1e3) / 1e9, 1) if v[1] > 0 else None}
+                          for k, v in sorted(rep.items(), key=lambda kv: -kv[1][1]) if not k.startswith("_")}
+        log(f"serving kernel profile (batched_f32): {kernel_profile}")
     poisson, lam = {}, None
     if "one_at_a_time_f64" in sat and not args.serve_saturation_only:
         lam = 0.8 * sat["one_at_a_time_f64"]["solves_per_s"]
@@ -247,6 +307,7 @@ def serving_bench(args):
         "preconditioner": f"ASYNC, {args.build_sweeps} factor sweep(s), {args.apply_sweeps} apply sweep pairs",
         "pool_GiB": args.serve_pool_gib, "slots": args.serve_slots,
         "saturation": sat,
+        "kernel_profile_batched_f32": kernel_profile,
         "poisson": {"rate_per_s": round(lam, 2), **poisson} if lam else None,
         "poisson_high_load": poisson_high,
         "speedup_solves_per_s": (round(sat["batched_f32"]["solves_per_s"] / sat["one_at_a_time_f64"]["solves_per_s"], 3)
@@ -348,9 +409,9 @@ def warm_chunked_line(args):
 
 
 def precision_bench(case, args):
-    """The precision boundary on the headline workload: the same step with the preconditioner in
-    FP64 (factor storage and sweep arithmetic) beside FP32, the Krylov solver being FP64 in both; and
-    the distance between the FP32 and FP64 factors after two synchronous sweeps."""
+    """The precision boundary: the headline step with the preconditioner in FP64 (factor storage and
+    sweep arithmetic) beside FP32, the Krylov solver being FP64 in both; and, per workload, the error
+    of the FP32 factor and application against the FP64 ones (precision_errors)."""
     import torch
     from paper_1912_00539_amd.runtime import DeviceSystem
     steps = {}
@@ -370,27 +431,59 @@ def precision_bench(case, args):
                        "fgmres_iters": [r["iters"] for _, r in res],
                        "max_rel_true_residual": max(r["rel_true_residual"] for _, r in res),
                        "ilu_residual": float(f"{s.ilu_residual():.4e}")}
-        s.factor(2, "sync")
-        torch.cuda.synchronize()
-        steps[prec]["_sys"] = s
         log(f"precision {prec}: {steps[prec]['ms_per_step']} ms/step, iters {steps[prec]['fgmres_iters']}")
-    s32, s64 = steps["f32"].pop("_sys"), steps["f64"].pop("_sys")
-
-    def rel(a32, a64):
-        d = a32.double() - a64
-        return {"frobenius": float(f"{(d.norm() / a64.norm()).item():.3e}"),
-                "max_abs_over_max": float(f"{(d.abs().max() / a64.abs().max()).item():.3e}")}
-    dist = {"LU": rel(s32.LU, s64.LU), "Dinv": rel(s32.Dinv, s64.Dinv),
-            "ilu_residual_f32": float(f"{s32.ilu_residual():.4e}"),
-            "ilu_residual_f64": float(f"{s64.ilu_residual():.4e}")}
-    del s32, s64
-    torch.cuda.empty_cache()
+        del s
+        torch.cuda.empty_cache()
     f32, f64 = steps["f32"], steps["f64"]
     return {"mode": args.mode, "build_sweeps": args.build_sweeps, "apply_sweeps": args.apply_sweeps,
             "steps": steps,
             "f32_speedup_step": round(f64["ms_per_step"] / f32["ms_per_step"], 3),
             "f32_speedup_preconditioner": round(f64["preconditioner_ms_per_step"] / f32["preconditioner_ms_per_step"], 3),
-            "factor_distance_after_2_sync_sweeps": dist}
+            "f32_vs_f64": precision_errors(args)}
+
+
+def _errors(a32, a64, bs):
+    """Relative Frobenius error of a32 against a64, and the largest per-block relative error
+    ||block difference||_F / ||block of a64||_F (blocks of `bs` consecutive values)."""
+    d = a32.double() - a64
+    nb = a64.numel() // bs
+    dn = d[: nb * bs].reshape(nb, bs).norm(dim=1)
+    an = a64[: nb * bs].reshape(nb, bs).norm(dim=1)
+    nz = an > 0
+    blk = (dn[nz] / an[nz]).max().item() if bool(nz.any()) else 0.0
+    return {"rel": float(f"{(d.norm() / a64.norm()).item():.3e}"), "max_block_rel": float(f"{blk:.3e}")}
+
+
+def precision_errors(args):
+    """FP32 against FP64 on each full-size workload: the factor (X and Dinv) after 1 and 2
+    synchronous sweeps, and one synchronous application (apply-sweeps pairs) of the 2-sweep factor
+    to a seeded vector. The FP64 synchronous factor and application equal the FP64 oracle's bit for
+    bit (the parity tests assert it), so these are the errors against the oracle."""
+    import torch
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    out = {}
+    for label, name, kw in (("tri300_cfl100", "tri300", {"cfl": 100.0}), ("aniso1000_line", "aniso1000", {"order": "line"}),
+                            ("aniso1000_rcm", "aniso1000", {"order": "rcm"}), (args.workload, args.workload, {})):
+        c = W.case(name, **kw)
+        s = {p: DeviceSystem(c, prec=p, restart=1) for p in ("f32", "f64")}
+        g = torch.Generator(device="cpu").manual_seed(args.serve_seed)
+        r = (2 * torch.rand(4 * c.n, dtype=torch.float64, generator=g) - 1).cuda()
+        row = {}
+        for nsw in (1, 2):
+            for p in s.values():
+                p.factor(nsw, "sync")
+            row[f"sweeps{nsw}"] = {"X": _errors(s["f32"].LU, s["f64"].LU, 16),
+                                   "Dinv": _errors(s["f32"].Dinv, s["f64"].Dinv, 16)}
+        z = {p: torch.zeros_like(r) for p in s}
+        for p in s:
+            s[p].apply(r, z[p], args.apply_sweeps, "sync")
+        row["apply"] = _errors(z["f32"], z["f64"], 4)
+        out[label] = row
+        log(f"precision errors {label}: {row}")
+        del s, z
+        torch.cuda.empty_cache()
+    return out
 
 
 def configs_bench(args):
@@ -466,6 +559,83 @@ def tri300_sweep_bench():
         out[f"cfl{cfl:g}"] = rows
         del s
         torch.cuda.empty_cache()
+    return out
+
+
+def factor_convergence_bench(args):
+    """The ILU-convergence study of Section 6.2 on the full-size workloads: the factor errors
+    ||vec(L - L_ilu)||_inf / ||vec(L0 - L_ilu)||_inf and likewise for U, and the ILU residual,
+    after 1 to 5 factor sweeps from A, for SYNC, ASYNC and CHUNK_ASYNC in FP64 and FP32; the
+    asynchronous modes run 5 times (mean, min, max), as the paper averages 5 runs; and the Jacobi
+    max-norms of the final factors and of X_ilu. X_ilu is the floating-point fixed point of the FP64
+    synchronous sweeps, reached by sweeping until an iterate repeats bit for bit: the map is
+    triangular in the Gaussian-elimination ordering, so that fixed point is unique and is the
+    sequential block ILU(0) (the GPU tests check this against the oracle)."""
+    import numpy as np
+    import torch
+    from paper_1912_00539_amd import abilu as L
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    out, summary = {}, {}
+    nsws = list(range(1, 6))
+    for label, name, kw, R in (("aniso1000_line", "aniso1000", {"order": "line"}, 16),
+                               (args.workload, args.workload, {}, 64)):
+        c = W.case(name, **kw)
+        ref = DeviceSystem(c, prec="f64", restart=0)
+        ref.factor(1, "sync")
+        prev = ref.LU.clone()
+        fixed = None
+        for q in range(2, args.fixed_point_cap + 1):
+            ref.factor(1, "sync", init="LU")
+            if torch.equal(ref.LU, prev):
+                fixed = q - 1
+                break
+            prev.copy_(ref.LU)
+        del prev
+        Y, DY = ref.LU, ref.Dinv
+        X0 = torch.empty_like(Y)
+        L.abilu_factor_from_csr(ref.pattern, "f64", ref.A, X0)
+        dL, dU = L.abilu_factor_maxdiff(ref.pattern, "f64", X0, Y, ref.work)
+        del X0
+        row = {"n": c.n, "nnzb": c.nnzb, "sweeps_to_fixed_point": fixed,
+               "x_ilu_ilu_residual": float(f"{ref.ilu_residual():.3e}"),
+               "x_ilu_jacobi_norms": [float(f"{v:.4g}") for v in L.abilu_jacobi_norms(ref.pattern, "f64", Y, DY, ref.work)],
+               "initial_maxdiff": [dL, dU], "runs": {}}
+        log(f"factor convergence {label}: X_ilu after {fixed} sweeps")
+        for prec in ("f64", "f32"):
+            for mode, reps in (("sync", 1), ("async", 5), ("chunk_async", 5)):
+                s = DeviceSystem(c, prec=prec, restart=0)
+                if mode == "chunk_async":
+                    s.set_chunks(R)
+                eL = np.zeros((reps, len(nsws)))
+                eU = np.zeros_like(eL)
+                ilu = np.zeros_like(eL)
+                for t in range(reps):
+                    for k, nsw in enumerate(nsws):
+                        s.factor(nsw, mode)
+                        nL, nU = L.abilu_factor_maxdiff(s.pattern, prec, s.LU, Y, s.work)
+                        eL[t, k] = nL / dL if dL > 0 else nL
+                        eU[t, k] = nU / dU if dU > 0 else nU
+                        ilu[t, k] = s.ilu_residual()
+                jn = L.abilu_jacobi_norms(s.pattern, prec, s.LU, s.Dinv, s.work)
+                f = lambda a: [float(f"{v:.3e}") for v in a]
+                r = {"E_L_mean": f(eL.mean(0)), "E_U_mean": f(eU.mean(0)), "ilu_residual_mean": f(ilu.mean(0)),
+                     "jacobi_norms_final": [float(f"{v:.4g}") for v in jn], "runs": reps}
+                if reps > 1:
+                    r.update({"E_L_min": f(eL.min(0)), "E_L_max": f(eL.max(0)), "E_U_min": f(eU.min(0)),
+                              "E_U_max": f(eU.max(0)), "ilu_residual_min": f(ilu.min(0)),
+                              "ilu_residual_max": f(ilu.max(0))})
+                row["runs"][f"{prec}_{mode}"] = r
+                log(f"factor convergence {label} {prec} {mode}: {r}")
+                del s
+                torch.cuda.empty_cache()
+        out[label] = row
+        summary[label] = {k: {"E_L": v["E_L_mean"], "E_U": v["E_U_mean"]} for k, v in row["runs"].items()
+                          if k in ("f64_async", "f32_async")}
+        del ref, Y, DY
+        torch.cuda.empty_cache()
+    out["sweeps"] = nsws
+    out["summary"] = summary
     return out
 
 
@@ -574,7 +744,93 @@ def chunked_bench(args):
     return out
 
 
+# Kernels of the headline step (rocprofv3's demangled names) and the names the library's profiler
+# gives their launches in the asynchronous FP32 step.
+TRAFFIC_KERNELS = {
+    "k_spmv<false>": "spmv", "k_spmv<true>": "spmv_resid",
+    "k_factor_sweep<float, false, true>": "factor_sweep_f32_async_fromA",
+    "k_factor_init<float, double, true, false>": "factor_init_f32",
+    "k_fwd<float, double, false>": "apply_fwd_f32_async", "k_fwd<float, float, true>": "apply_fwd_emitz_f32_async",
+    "k_bwd<float, float, float, true, false>": "apply_bwd_f32_async",
+    "k_bwd<float, float, double, true, false>": "apply_bwd_last_f32_async",
+    "k_update": "fgmres_update", "k_mdot": "fgmres_mdot", "k_stream_copy": "stream_copy",
+}
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    out = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            out += list(csv.DictReader(fh))
+    return out
+
+
+def summarize_stats(d, title, command):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (its *kernel_stats.csv)."""
+    rows = _csv_rows(d, "kernel_stats.csv")
+    if not rows:
+        raise SystemExit(f"no kernel_stats.csv under {d}")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics: {title}", "", "Command (run from the repository root on an MI355X machine):",
+             "", "```", command, "```", "", "| kernel | calls | avg us | min us | max us | total ms | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{100 * float(r['TotalDurationNs']) / tot:.2f} |")
+    lines += ["", f"Total kernel time {tot / 1e6:.3f} ms."]
+    return "\n".join(lines) + "\n"
+
+
+def summarize_traffic(fetch_dir, write_dir, command):
+    """Bytes per launch of the headline step's kernels from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE, KiB per dispatch), each scaled by the ratio of the known bytes of the STREAM
+    copy kernel (its reads, its writes) to what the counter reads for it. Returns (json, markdown)."""
+    import numpy as np
+
+    def per_kernel(d, counter):
+        acc = {}
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].strip()
+            acc.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy_bytes = STREAM_BYTES // 2      # bytes read (and written) by one STREAM copy launch
+    cf = copy_bytes / float(np.median(fetch["k_stream_copy"]))
+    cw = copy_bytes / float(np.median(write["k_stream_copy"]))
+    shash = source_hash()
+    out = {"_source": "rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (separate runs), KiB per dispatch, scaled by "
+                      "the ratio of the known bytes of a 2 GiB STREAM copy to what each counter reads for it",
+           "copy_factor_fetch": cf, "copy_factor_write": cw}
+    md = ["# Measured L2-to-memory traffic per launch: tri2000 (4M cells), async FP32 step", "",
+          "Command (run from the repository root on an MI355X machine):", "", "```", command, "```", "",
+          f"Calibration: the 2 GiB STREAM copy reads {1 / cf:.3f}x its bytes in FETCH_SIZE and {1 / cw:.3f}x in "
+          f"WRITE_SIZE; every figure below is scaled by those factors ({cf:.3f}, {cw:.3f}).", "",
+          "| kernel (library name) | dispatches | fetch MB | write MB | total MB per launch |",
+          "|---|---:|---:|---:|---:|"]
+    for kname, lname in TRAFFIC_KERNELS.items():
+        if kname not in fetch or kname not in write:
+            continue
+        f = float(np.median(fetch[kname])) * cf
+        w = float(np.median(write[kname])) * cw
+        out[lname] = {"dispatches": len(fetch[kname]), "fetch_bytes_per_launch": round(f),
+                      "write_bytes_per_launch": round(w), "bytes_per_launch": round(f + w), "source_hash": shash}
+        md.append(f"| `{lname}` | {len(fetch[kname])} | {f / 1e6:.1f} | {w / 1e6:.1f} | {(f + w) / 1e6:.1f} |")
+    md += ["", f"Kernel source hash when measured: `{shash}` (bench.py reports this traffic only while the hash matches)."]
+    return json.dumps(out, indent=1) + "\n", "\n".join(md) + "\n"
+
+
+STREAM_BYTES = 2 * (2 << 30)   # algorithmic bytes of one stream_reference copy launch (read + write)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-stats", "--summarize-traffic"):
+        return summarize_main(sys.argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -598,6 +854,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-forms", default="batched_f32,one_at_a_time_f64,one_at_a_time_f32")
     ap.add_argument("--serve-saturation-only", action="store_true")
+    ap.add_argument("--serve-profile", action="store_true",
+                    help="add a profiled saturation run of the batched form (per-kernel GB/s)")
     ap.add_argument("--warm-steps", type=int, default=12)
     ap.add_argument("--warm-steps-line", type=int, default=8)
     ap.add_argument("--no-warm-start", action="store_true")
@@ -605,10 +863,17 @@ def main():
     ap.add_argument("--no-chunked", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-orderings", action="store_true")
+    ap.add_argument("--no-factor-convergence", action="store_true")
+    ap.add_argument("--fixed-point-cap", type=int, default=400,
+                    help="most FP64 synchronous sweeps spent looking for the fixed point X_ilu")
+    ap.add_argument("--only-factor-convergence", action="store_true",
+                    help="print the factor_convergence object alone")
     ap.add_argument("--only-orderings", action="store_true", help="print the orderings object alone")
     ap.add_argument("--only-warm", action="store_true", help="print the warm_start object alone")
     ap.add_argument("--only-chunked", action="store_true", help="print the chunked object alone")
     ap.add_argument("--only-serving", action="store_true", help="print the serving object alone (profiling)")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file that receives the full result object (the last stdout line is the compact headline)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -632,6 +897,9 @@ def main():
         return
     if args.only_orderings:
         print(json.dumps({"orderings": orderings_bench(args)}), flush=True)
+        return
+    if args.only_factor_convergence:
+        print(json.dumps({"factor_convergence": factor_convergence_bench(args)}), flush=True)
         return
     if args.only_chunked:
         print(json.dumps({"chunked": chunked_bench(args)}), flush=True)
@@ -745,12 +1013,113 @@ def main():
     out["orderings"] = None if args.no_orderings else orderings_bench(args)
     out["serving"] = None if args.no_serving else serving_bench(args)
     out["warm_start"] = None if args.no_warm_start else warm_start_bench(args)
+    out["factor_convergence"] = None if args.no_factor_convergence else factor_convergence_bench(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(case, args)
+        out["cpu_baseline"] = cpu_baseline(case, args, gpu=gpu_sync_factors(case))
     else:
         out["cpu_baseline"] = None
-    print(json.dumps(out), flush=True)
+    emit(out, args.detail)
+
+
+def emit(out, detail_path):
+    """Write the full result object to `detail_path` (and to stderr), then print the compact
+    headline as the last line of stdout."""
+    text = json.dumps(out)
+    if detail_path:
+        d = os.path.dirname(os.path.abspath(detail_path))
+        os.makedirs(d, exist_ok=True)
+        with open(detail_path, "w") as f:
+            f.write(text + "\n")
+    log("detail:", text)
+    head = headline(out, detail_path)
+    print(json.dumps(head, separators=(",", ":")), flush=True)
+
+
+def _pick(d, *keys):
+    return {k: d.get(k) for k in keys} if d else None
+
+
+def headline(out, detail_path=None):
+    """The compact result line (a few KB): the headline figures of `out` and a summary of every
+    sub-benchmark, the full object being in the detail file."""
+    h = {k: out.get(k) for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                 "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")}
+    h["value_covers"] = ("whole step: factor (init + build sweeps) and FGMRES to rtol with its apply sweeps, SpMVs and "
+                         "Gram-Schmidt; algorithmic bytes of every launch / wall time of the step")
+    rl = out.get("roofline") or {}
+    h["roofline"] = _pick(rl, "bound", "kernel", "achieved", "peak", "unit", "frac", "traffic", "avg_launch_ms",
+                          "algorithmic_bytes_per_launch")
+    for k in ("frac_hbm_peak", "stream_copy_GBps", "frac_stream", "factor_apply_GBps", "factor_sweeps_per_s",
+              "solves_per_s", "converged", "max_rel_true_residual", "ilu_residual", "timing"):
+        h[k] = out.get(k)
+    if out.get("factor_apply_GBps"):
+        h["factor_apply_frac_hbm_peak"] = round(out["factor_apply_GBps"] / HBM_PEAK_GBPS, 4)
+    it = out.get("fgmres_iters") or []
+    h["fgmres_iters"] = [min(it), max(it)] if it else None
+    cpu = out.get("cpu_baseline")
+    if cpu:
+        h["cpu_baseline"] = {**_pick(cpu, "value", "unit", "cores", "kind", "cpu_model", "host_cpus", "seconds"),
+                             "sample": cpu.get("sample"),
+                             "sequential_ms": _pick(cpu.get("sequential") or {}, "ilu0_ms", "exact_substitution_ms"),
+                             "oracle_check": {k: v for k, v in (cpu.get("oracle_check") or {}).items()
+                                              if k != "what"} or None}
+    else:
+        h["cpu_baseline"] = None
+    sv = out.get("serving")
+    if sv:
+        sat = sv.get("saturation") or {}
+        po = sv.get("poisson") or {}
+        form = lambda r, keys: _pick(r, *keys) if r else None
+        h["serving"] = {
+            "requests": (sat.get("batched_f32") or {}).get("converged"),
+            "saturation": {k: form(sat.get(k), ("solves_per_s", "p50_ms", "p99_ms", "solve_path_GBps", "mean_iters",
+                                                "max_rel_true_residual")) for k in sat},
+            "speedup_solves_per_s": sv.get("speedup_solves_per_s"),
+            "poisson_rate_per_s": po.get("rate_per_s"),
+            "poisson": {k: form(po.get(k), ("p50_ms", "p99_ms")) for k in po if k != "rate_per_s"}}
+    else:
+        h["serving"] = None
+    pr = out.get("precision")
+    if pr:
+        pair = lambda e: [e.get("rel"), e.get("max_block_rel")] if e else None
+        h["precision"] = {
+            "f32_speedup_step": pr.get("f32_speedup_step"),
+            "f32_vs_f64_legend": "[relative Frobenius, largest per-block relative] of FP32 against FP64 (= oracle) "
+                                 "after 1 and 2 SYNC sweeps (X, Dinv) and of one SYNC application (z)",
+            "f32_vs_f64": {k: {"X1": pair(v.get("sweeps1", {}).get("X")), "D1": pair(v.get("sweeps1", {}).get("Dinv")),
+                               "X2": pair(v.get("sweeps2", {}).get("X")), "D2": pair(v.get("sweeps2", {}).get("Dinv")),
+                               "z": pair(v.get("apply"))}
+                           for k, v in (pr.get("f32_vs_f64") or {}).items()}}
+    else:
+        h["precision"] = None
+    ch = out.get("chunked")
+    if ch:
+        h["chunked_over_async_step_time"] = {k: v.get("chunk_over_async_step_time") for k, v in ch.items()}
+    ws = out.get("warm_start")
+    if ws:
+        t = ws.get("totals") or {}
+        h["warm_start_iters"] = {k: v.get("iters") for k, v in t.items()}
+    fc = out.get("factor_convergence")
+    if fc:
+        h["factor_convergence"] = fc.get("summary")
+    h["detail_file"] = detail_path
+    h["source_hash"] = out.get("source_hash")
+    return h
+
+
+def summarize_main(argv):
+    """bench.py --summarize-stats DIR TITLE COMMAND OUT.md
+       bench.py --summarize-traffic FETCH_DIR WRITE_DIR COMMAND OUT_BASENAME  (writes .txt and .md)
+    Turn rocprofv3 output into the summaries kept under profiles/."""
+    if argv[0] == "--summarize-stats":
+        d, title, command, out = argv[1:5]
+        open(out, "w").write(summarize_stats(d, title, command))
+    else:
+        fd, wd, command, base = argv[1:5]
+        js, md = summarize_traffic(fd, wd, command)
+        open(base + ".txt", "w").write(js)
+        open(base + ".md", "w").write(md)
 
 
 if __name__ == "__main__":
