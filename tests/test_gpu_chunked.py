@@ -16,7 +16,7 @@ import pytest
 import oracle
 from paper_1912_00539_amd import workloads as W
 from tests.dense_ref import assert_same_bits, rel
-from tests.f32_bars import FactorBars, VectorBars, report
+from tests.f32_bars import FactorBars, VectorBars, perturb, report
 
 pytestmark = pytest.mark.gpu
 
@@ -153,13 +153,22 @@ def check_chunked(c, nsw, R, prec, X, D, what=""):
     """FP64: bit for bit against the chunked oracle (the GPU's block products and inverse evaluate
     the oracle's operations in its order, and the Gauss-Seidel order within a chunk is the oracle's
     row-major order). FP32: block by block (tests/f32_bars.py)."""
-    run = lambda A, X0: oracle.factor_chunked(c.n, c.rowptr, c.colidx, A, nsw, R, X0=X0)[:2]
+    run = lambda A, X0, k=nsw: oracle.factor_chunked(c.n, c.rowptr, c.colidx, A, k, R, X0=X0)[:2]
     if prec == "f64":
         Xo, Do = run(c.vals, None)
         assert_same_bits(X, Xo, f"{what} X")
         assert_same_bits(D, Do, f"{what} Dinv")
         return None
-    out = FactorBars(run, c.vals).check(X, D, what)
+
+    def perturbed(g):
+        # A and every iterate stored between sweeps perturbed by a float ulp
+        Ap = perturb(c.vals, g)
+        Xp = None
+        for _ in range(nsw):
+            Xp, _ = run(Ap, Xp, 1)
+            Xp = perturb(Xp, g)
+        return run(Ap, Xp, 0)
+    out = FactorBars(run, c.vals, perturbed=perturbed).check(X, D, what)
     report(f"{what} f32 chunked", out)
     return out
 

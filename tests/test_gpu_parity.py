@@ -18,7 +18,7 @@ import pytest
 import oracle
 from paper_1912_00539_amd import workloads as W
 from tests.dense_ref import assert_same_bits, rel
-from tests.f32_bars import FactorBars, VectorBars, report
+from tests.f32_bars import FactorBars, VectorBars, perturb, report
 
 pytestmark = pytest.mark.gpu
 
@@ -130,9 +130,19 @@ def test_factor_sync_f64(name, nsw):
 
 
 def F32Bars(c, nsw, X0=None):
-    """Block-by-block single-precision bars for nsw synchronous sweeps (tests/f32_bars.py)."""
-    run = lambda A, X0_: oracle.factor_sync(c.n, c.rowptr, c.colidx, A, nsw, X0=X0_)[:2]
-    return FactorBars(run, c.vals, X0)
+    """Block-by-block single-precision bars for nsw synchronous sweeps (tests/f32_bars.py): the
+    sensitivity run perturbs A and every iterate between sweeps, sweep by sweep, the last one
+    before its diagonal blocks are inverted."""
+    sync = lambda A, X0_, k: oracle.factor_sync(c.n, c.rowptr, c.colidx, A, k, X0=X0_)[:2]
+
+    def perturbed(g):
+        Ap = perturb(c.vals, g)
+        X = Ap if X0 is None else perturb(X0, g)
+        for _ in range(nsw):
+            X, _ = sync(Ap, X, 1)
+            X = perturb(X, g)
+        return sync(Ap, X, 0)
+    return FactorBars(lambda A, X0_: sync(A, X0_, nsw), c.vals, X0, perturbed=perturbed)
 
 
 def apply_bars(c, X, D, r, nsw):
