@@ -294,6 +294,29 @@ abilu_status abilu_apply(const abilu_pattern *p, const void *d_LU, const void *d
                          abilu_prec prec, const double *d_r, double *d_z, int32_t nsweeps,
                          abilu_mode mode, void *d_work, size_t work_bytes, void *stream);
 
+/* Device bytes abilu_apply_noalloc may use on each device (64 MiB). */
+#define ABILU_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * abilu_apply without a workspace argument and without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. Same arguments (less the workspace), modes and results as abilu_apply; it runs the same
+ * kernels, so the deterministic modes give the same bits. Its four intermediate vectors (4N values
+ * of the factor precision each, each rounded up to 256 bytes) live in a library-owned device array
+ * of ABILU_NOALLOC_SCRATCH_BYTES, one per device, whose address is taken once per device on the
+ * first call there and which is held until the process ends. Hence N <= 1,048,576 block rows in
+ * ABILU_F32 and N <= 524,288 in ABILU_F64; a larger pattern gets ABILU_EINVAL before anything is
+ * launched (abilu_last_error says why). The pattern must belong to the current device (else
+ * ABILU_EINVAL). Every call on a device shares that device's array, which keeps the last call's
+ * contents: calls that overlap on one device (several streams or threads) race and must be
+ * serialised by the caller; no call relies on the array's previous contents (the one-worker mode
+ * clears its vectors with a kernel each time). Calls no hipMalloc, hipFree or hipMemset.
+ * Non-blocking. Errors: ABILU_EINVAL, ABILU_EDEVICE.
+ */
+abilu_status abilu_apply_noalloc(const abilu_pattern *p, const void *d_LU, const void *d_Dinv,
+                                 abilu_prec prec, const double *d_r, double *d_z, int32_t nsweeps,
+                                 abilu_mode mode, void *stream);
+
 /* Permute a factor between the factor layout and A's CSR block order (for inspection, warm
  * starts from external factors, and verification). d_LU and d_csr: prec[Z][4][4], distinct
  * buffers. Non-blocking. */

@@ -126,6 +126,7 @@ def lib():
             "abilu_workspace_bytes": ([vp, st, i32], sz),
             "abilu_factor": ([vp, vp, vp, vp, st, i32, st, st, vp, sz, vp], st),
             "abilu_apply": ([vp, vp, vp, st, vp, vp, i32, st, vp, sz, vp], st),
+            "abilu_apply_noalloc": ([vp, vp, vp, st, vp, vp, i32, st, vp], st),
             "abilu_spmv": ([vp, vp, vp, vp, vp], st),
             "abilu_factor_to_csr": ([vp, st, vp, vp, vp], st),
             "abilu_factor_from_csr": ([vp, st, vp, vp, vp], st),
@@ -312,6 +313,14 @@ def abilu_apply(p: Pattern, LU, Dinv, prec: str, r, z, nsweeps: int, mode: str, 
     return _check(lib().abilu_apply(p.handle, _ptr(LU), _ptr(Dinv), PRECS[prec], _ptr(r), _ptr(z), int(nsweeps),
                                     MODES[mode], _ptr(work), work.numel() * work.element_size(), _stream(stream)),
                   "abilu_apply")
+
+
+ABILU_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def abilu_apply_noalloc(p: Pattern, LU, Dinv, prec: str, r, z, nsweeps: int, mode: str, stream=None) -> int:
+    return _check(lib().abilu_apply_noalloc(p.handle, _ptr(LU), _ptr(Dinv), PRECS[prec], _ptr(r), _ptr(z),
+                                            int(nsweeps), MODES[mode], _stream(stream)), "abilu_apply_noalloc")
 
 
 def abilu_factor_to_csr(p: Pattern, prec: str, LU, csr, stream=None) -> int:

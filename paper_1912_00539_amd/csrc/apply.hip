@@ -15,6 +15,7 @@
 // The chunked sweeps (a forward or backward substitution inside each chunk of consecutive rows)
 // run a chunk per workgroup level by level, or a chunk per quad row by row; the single-worker
 // sweeps run all rows in one quad.
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.h"
@@ -454,6 +455,71 @@ extern "C" abilu_status abilu_apply(const abilu_pattern *p, const void *d_LU, co
     if (!d_r || !d_z || d_r == d_z) return ABILU_EINVAL;
     if (nsweeps > 0 && (!d_LU || !d_Dinv)) return ABILU_EINVAL;
     return apply_impl(p, d_LU, d_Dinv, prec, d_r, d_z, nsweeps, mode, (char *)d_work, W, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ allocation-free application
+// abilu_apply_noalloc keeps the four apply vectors in this file-scope device array instead of a
+// caller workspace. In host code `scratch` names a host-side stand-in, not device memory: its device
+// address is obtained once per device with hipGetSymbolAddress (with that device current) and only
+// that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[ABILU_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (set up on the first call per device).
+abilu_status scratch_ptr(int dev, char **out) {
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        note_error("abilu_apply_noalloc: device index beyond the library's table");
+        return ABILU_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (!hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)") || !ptr)
+            return ABILU_EDEVICE;
+        g_scratch[dev] = (char *)ptr;
+    }
+    *out = g_scratch[dev];
+    return ABILU_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+extern "C" abilu_status abilu_apply_noalloc(const abilu_pattern *p, const void *d_LU, const void *d_Dinv,
+                                            abilu_prec prec, const double *d_r, double *d_z, int32_t nsweeps,
+                                            abilu_mode mode, void *stream) {
+    if (!p || nsweeps < 0) return ABILU_EINVAL;
+    if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
+    if (!mode_ok(p, mode)) return ABILU_EINVAL;
+    // the apply vectors ya, yb, za, zb: 4N elements of the factor precision each
+    const size_t v = align256((size_t)4 * (size_t)p->n * (prec == ABILU_F32 ? 4 : 8));
+    Workspace W{};
+    W.ya = 0;
+    W.yb = v;
+    W.za = 2 * v;
+    W.zb = 3 * v;
+    W.total = 4 * v;
+    if (W.total > (size_t)ABILU_NOALLOC_SCRATCH_BYTES) {
+        note_error("abilu_apply_noalloc: the pattern's apply vectors exceed ABILU_NOALLOC_SCRATCH_BYTES");
+        return ABILU_EINVAL;
+    }
+    if (p->n == 0) return ABILU_OK;
+    if (!d_r || !d_z || d_r == d_z) return ABILU_EINVAL;
+    if (nsweeps > 0 && (!d_LU || !d_Dinv)) return ABILU_EINVAL;
+    int dev = -1;
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return ABILU_EDEVICE;
+    if (dev != p->device) {
+        note_error("abilu_apply_noalloc: the pattern belongs to another device");
+        return ABILU_EINVAL;
+    }
+    char *work = nullptr;
+    const abilu_status st = scratch_ptr(dev, &work);
+    if (st != ABILU_OK) return st;
+    return apply_impl(p, d_LU, d_Dinv, prec, d_r, d_z, nsweeps, mode, work, W, (hipStream_t)stream);
 }
 
 extern "C" abilu_status abilu_spmv(const abilu_pattern *p, const double *d_A, const double *d_x, double *d_y,
