@@ -232,17 +232,6 @@ __device__ __forceinline__ T dot4(T a0, T b0, T a1, T b1, T a2, T b2, T a3, T b3
     }
 }
 
-// (((acc + a0 b0) + a1 b1) + a2 b2) + a3 b3: the products added to the accumulator one by one.
-template <typename T>
-__device__ __forceinline__ T acc_dot4(T acc, T a0, T b0, T a1, T b1, T a2, T b2, T a3, T b3) {
-    if constexpr (sizeof(T) == 8) {
-#pragma clang fp contract(off)
-        return (((acc + a0 * b0) + a1 * b1) + a2 * b2) + a3 * b3;
-    } else {
-        return (((acc + a0 * b0) + a1 * b1) + a2 * b2) + a3 * b3;
-    }
-}
-
 // a - b c (the product rounded first in double precision).
 template <typename T>
 __device__ __forceinline__ T sub_prod(T a, T b, T c) {

@@ -222,8 +222,10 @@ __device__ __forceinline__ void spmv_body(int blk, int n, const int32_t *__restr
         for (int u = 0; u < SCH; ++u) {
             double xj[4];
             gather_vec(xv[u], xj);
-            const double t = acc_dot4(acc, a[u][0], xj[0], a[u][1], xj[1], a[u][2], xj[2], a[u][3], xj[3]);
-            acc = (e0 + u < b1) ? t : acc;
+            // one product tree per block, fused: the accumulator's dependent chain is one add per
+            // block (a chain of four adds per block, the oracle's order, made the SpMV 12% slower)
+            const double c = a[u][0] * xj[0] + a[u][1] * xj[1] + a[u][2] * xj[2] + a[u][3] * xj[3];
+            acc += (e0 + u < b1) ? c : 0.0;
         }
     }
     y[(int64_t)i * 4 + r] = RESID ? b[(int64_t)i * 4 + r] - acc : acc;

@@ -2,10 +2,12 @@
 
 Bars:
   * pattern analysis (integers): bit-exact;
-  * double-precision synchronous factor sweeps, synchronous apply sweeps and SpMV: bit-exact. The
+  * double-precision synchronous factor sweeps and synchronous apply sweeps: bit-exact. The
     stated bar is 1e-12 relative; the GPU's double-precision block products evaluate every
     product and sum in the oracle's order without fused multiply-add, and its 4x4 inverse follows
     the oracle's elimination operation for operation, so the results are identical;
+  * SpMV: 1e-13 (rounding order only: each block's four products are summed as one fused tree
+    before the accumulator, which keeps the accumulator's dependent chain short);
   * single precision against the double oracle, block by block (tests/f32_bars.py): every block
     of X and Dinv (every cell of z) within max(1e-5, 32 s_b), s_b being that block's relative change
     in the oracle's result under a one-float-ulp perturbation of the inputs; checked against the
@@ -339,7 +341,7 @@ def test_spmv(name):
     yt = torch.zeros_like(xt)
     s.spmv(xt, yt)
     ref = oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)
-    assert_same_bits(yt.cpu().numpy(), ref, "y")
+    assert rel(yt.cpu().numpy(), ref) <= 1e-13
 
 
 # ------------------------------------------------------------------ FGMRES (a8, a9)
@@ -546,7 +548,7 @@ def test_full_size_tri2000_f32():
     del Xo, Do
     print(f"tri2000 f32 apply 3: rel {e:.2e}, worst cell at {worst:.2f} of its bar")
     s.spmv(rt, zt)
-    assert_same_bits(zt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r), "SpMV")
+    assert rel(zt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r)) <= 1e-13
     for mode, nsw in (("async", 1), ("sync", 2)):
         s.factor(nsw, mode)
         st, res = s.solve(apply_sweeps=3, mode=mode, rtol=1e-2, maxit=500, restart=50)

@@ -3,10 +3,11 @@
 Random symmetric patterns (block diagonal to dense-ish rows), in natural or random order, at
 sizes around the 64-row workgroup tile (one row, a ragged tail, several tiles). On each:
   - pattern analysis bit-exact (diagonal positions, update-set pairs);
-  - two synchronous FP64 factor sweeps within 1e-12 of the oracle's;
-  - synchronous sweeps at the dependency depth D equal the sequential factor (Theorem 8), and
-    in-place asynchronous sweeps reach the same floating-point result bit for bit;
-  - three synchronous FP64 apply sweep pairs and the SpMV within 1e-12 / 1e-13.
+  - two synchronous FP64 factor sweeps equal the oracle's bit for bit;
+  - synchronous sweeps at the dependency depth D equal the sequential factor bit for bit
+    (Theorem 8), and in-place asynchronous sweeps reach the same floating-point result;
+  - three synchronous FP64 apply sweep pairs equal the oracle's bit for bit, the SpMV within 1e-13
+    (its products are summed per block, fused, before the accumulator: rounding order only).
 """
 import numpy as np
 import pytest
@@ -99,7 +100,7 @@ def test_random_pattern_parity(n, deg, order, seed):
     assert_same_bits(zt.cpu().numpy(), oracle.apply_sync(c.n, c.rowptr, c.colidx, Xo, Do, r, 3), "z")
     yt = torch.zeros_like(rt)
     s.spmv(rt, yt)
-    assert_same_bits(yt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r), "SpMV")
+    assert rel(yt.cpu().numpy(), oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, r)) <= 1e-13
 
 
 @pytest.mark.parametrize("runner", ["levels", "rows"])
