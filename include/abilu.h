@@ -382,7 +382,8 @@ abilu_status abilu_ilu_residual(const abilu_pattern *p, const double *d_A, const
  * ||vec(L - L_ilu)||_inf / ||vec(L_0 - L_ilu)||_inf and likewise for U (L_0, U_0 the initial guess,
  * A in the factor layout by abilu_factor_from_csr). A NaN anywhere shows as NaN.
  *   d_X  prec[Z][4][4] (factor layout); d_Y double[Z][4][4] (factor layout)
- * Uses the workspace's reduction area (work_bytes >= abilu_workspace_bytes(p, prec, 0)). Blocks.
+ * Uses scratch in the workspace (a workspace of either precision: work_bytes >=
+ * abilu_workspace_bytes(p, ABILU_F32, 0)); d_X and d_Y must not lie in it. Blocks.
  */
 abilu_status abilu_factor_maxdiff(const abilu_pattern *p, abilu_prec prec, const void *d_X, const double *d_Y,
                                   void *d_work, size_t work_bytes, double *h_lower, double *h_upper, void *stream);
@@ -392,7 +393,8 @@ abilu_status abilu_factor_maxdiff(const abilu_pattern *p, abilu_prec prec, const
  * a smaller norm is a more diagonally dominant factor): *h_norm_l = ||L_strict||_inf (L has a unit
  * diagonal) and *h_norm_u = ||D^{-1} U_strict||_inf with D the block diagonal of U (D^{-1} = Dinv),
  * each the largest absolute scalar row sum. Block products in the factor precision, sums in double.
- * A NaN anywhere shows as NaN. d_LU prec (factor layout), d_Dinv prec[N][4][4]. Blocks.
+ * A NaN anywhere shows as NaN. d_LU prec (factor layout), d_Dinv prec[N][4][4]. Workspace as for
+ * abilu_factor_maxdiff. Blocks.
  */
 abilu_status abilu_jacobi_norms(const abilu_pattern *p, abilu_prec prec, const void *d_LU, const void *d_Dinv,
                                 void *d_work, size_t work_bytes, double *h_norm_l, double *h_norm_u,

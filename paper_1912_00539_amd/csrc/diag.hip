@@ -112,31 +112,45 @@ abilu_status finish_max2(const abilu_pattern *p, double *partial, int nb, double
     return ABILU_OK;
 }
 
-template <typename T>
-abilu_status maxdiff_t(const abilu_pattern *p, const T *X, const double *Y, char *work, const Workspace &W,
-                       double *h_lower, double *h_upper, hipStream_t s) {
-    const int nb = W.nb_vec;
-    double *partial = (double *)(work + W.partials);
-    {
-        ProfScope ps("factor_maxdiff", s, (sizeof(T) + 8.0) * 16.0 * (double)p->nnzb);
-        k_factor_maxdiff<T><<<nb, WG, 0, s>>>(16 * p->nnzb, 16 * p->nnzb_lower, X, Y, partial, nb);
-    }
-    if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
-    return finish_max2(p, partial, nb, (double *)(work + W.red), h_lower, h_upper, s);
+// The diagnostics' scratch: 2 nb partial maxima, then 2 results, from byte 256 of the workspace
+// (the region after the header, which every workspace of either precision has room for: it holds
+// at least the factor ping-pong buffers and the reduction areas). Returns false when too small.
+struct DiagScratch {
+    double *partial, *red;
+    int nb;
+};
+bool diag_scratch(const abilu_pattern *p, void *work, size_t work_bytes, DiagScratch *out) {
+    const Workspace W = layout(p, ABILU_F32, 0);    // the smaller of the two precisions' layouts
+    if (work_bytes < W.total) return false;
+    const size_t part = ((size_t)16 * W.nb_vec + 255) & ~(size_t)255;
+    if (256 + part + 256 > W.total) return false;
+    out->nb = W.nb_vec;
+    out->partial = (double *)((char *)work + 256);
+    out->red = (double *)((char *)work + 256 + part);
+    return true;
 }
 
 template <typename T>
-abilu_status jacobi_t(const abilu_pattern *p, const T *LU, const T *Dinv, char *work, const Workspace &W,
-                      double *h_l, double *h_u, hipStream_t s) {
-    const int nb = W.nb_vec;
-    double *partial = (double *)(work + W.partials);
+abilu_status maxdiff_t(const abilu_pattern *p, const T *X, const double *Y, const DiagScratch &D, double *h_lower,
+                       double *h_upper, hipStream_t s) {
+    {
+        ProfScope ps("factor_maxdiff", s, (sizeof(T) + 8.0) * 16.0 * (double)p->nnzb);
+        k_factor_maxdiff<T><<<D.nb, WG, 0, s>>>(16 * p->nnzb, 16 * p->nnzb_lower, X, Y, D.partial, D.nb);
+    }
+    if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
+    return finish_max2(p, D.partial, D.nb, D.red, h_lower, h_upper, s);
+}
+
+template <typename T>
+abilu_status jacobi_t(const abilu_pattern *p, const T *LU, const T *Dinv, const DiagScratch &D, double *h_l,
+                      double *h_u, hipStream_t s) {
     const T *Ub = LU + ((int64_t)p->nnzb_lower + p->n) * BB;
     {
         ProfScope ps("jacobi_norms", s);
-        k_jacobi_norms<T><<<nb, WG, 0, s>>>(p->n, p->lrow, p->urow, LU, Ub, Dinv, partial, nb);
+        k_jacobi_norms<T><<<D.nb, WG, 0, s>>>(p->n, p->lrow, p->urow, LU, Ub, Dinv, D.partial, D.nb);
     }
     if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
-    return finish_max2(p, partial, nb, (double *)(work + W.red), h_l, h_u, s);
+    return finish_max2(p, D.partial, D.nb, D.red, h_l, h_u, s);
 }
 
 }  // namespace
@@ -146,17 +160,16 @@ extern "C" abilu_status abilu_factor_maxdiff(const abilu_pattern *p, abilu_prec 
                                              double *h_upper, void *stream) {
     if (!p || !d_work || !h_lower || !h_upper) return ABILU_EINVAL;
     if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
-    const Workspace W = layout(p, prec, 0);
-    if (work_bytes < W.total) return ABILU_EINVAL;
+    DiagScratch D;
+    if (!diag_scratch(p, d_work, work_bytes, &D)) return ABILU_EINVAL;
     if (p->n == 0) {
         *h_lower = *h_upper = 0.0;
         return ABILU_OK;
     }
     if (!d_X || !d_Y) return ABILU_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (prec == ABILU_F32)
-        return maxdiff_t<float>(p, (const float *)d_X, d_Y, (char *)d_work, W, h_lower, h_upper, s);
-    return maxdiff_t<double>(p, (const double *)d_X, d_Y, (char *)d_work, W, h_lower, h_upper, s);
+    if (prec == ABILU_F32) return maxdiff_t<float>(p, (const float *)d_X, d_Y, D, h_lower, h_upper, s);
+    return maxdiff_t<double>(p, (const double *)d_X, d_Y, D, h_lower, h_upper, s);
 }
 
 extern "C" abilu_status abilu_jacobi_norms(const abilu_pattern *p, abilu_prec prec, const void *d_LU,
@@ -164,15 +177,14 @@ extern "C" abilu_status abilu_jacobi_norms(const abilu_pattern *p, abilu_prec pr
                                            double *h_norm_u, void *stream) {
     if (!p || !d_work || !h_norm_l || !h_norm_u) return ABILU_EINVAL;
     if (prec != ABILU_F32 && prec != ABILU_F64) return ABILU_EINVAL;
-    const Workspace W = layout(p, prec, 0);
-    if (work_bytes < W.total) return ABILU_EINVAL;
+    DiagScratch D;
+    if (!diag_scratch(p, d_work, work_bytes, &D)) return ABILU_EINVAL;
     if (p->n == 0) {
         *h_norm_l = *h_norm_u = 0.0;
         return ABILU_OK;
     }
     if (!d_LU || !d_Dinv) return ABILU_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (prec == ABILU_F32)
-        return jacobi_t<float>(p, (const float *)d_LU, (const float *)d_Dinv, (char *)d_work, W, h_norm_l, h_norm_u, s);
-    return jacobi_t<double>(p, (const double *)d_LU, (const double *)d_Dinv, (char *)d_work, W, h_norm_l, h_norm_u, s);
+    if (prec == ABILU_F32) return jacobi_t<float>(p, (const float *)d_LU, (const float *)d_Dinv, D, h_norm_l, h_norm_u, s);
+    return jacobi_t<double>(p, (const double *)d_LU, (const double *)d_Dinv, D, h_norm_l, h_norm_u, s);
 }

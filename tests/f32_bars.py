@@ -3,8 +3,9 @@
 A single-precision factor (or vector) is judged block by block (cell by cell): block b passes when
 its relative error is within max(1e-5, C s_b), where s_b is the relative change of the oracle's
 block b when its inputs, and every iterate the single-precision path stores between sweeps, are
-perturbed by one float unit in the last place (relative perturbation 2^-24 with random signs): the
-block's sensitivity to float-sized errors. Well-conditioned blocks get the stated 1e-5; blocks that
+perturbed by one float unit in the last place, normwise per block (each value moved by up to 2^-24
+times the largest magnitude in its block, random signs): the block's sensitivity to float-sized
+errors. Well-conditioned blocks get the stated 1e-5; blocks that
 depend on an ill-conditioned diagonal block get its conditioning. Under the initial guess L = A the
 first sweep forms U_ii = A_ii - sum A_ik A_ki, whose condition number reaches 8e6 on the
 aspect-ratio-1000 layers; storing that U_ii in float moves its inverse by up to cond x 2^-24 even
@@ -27,8 +28,17 @@ def f32(a):
 
 
 def _perturb(a, g):
+    """Normwise float-sized perturbation of every block (an [n,4,4] array) or every cell's 4-vector
+    (a vector of 4n values): each value moved by up to 2^-24 times the largest magnitude in its
+    block, with random signs. Float block arithmetic errs normwise (Gaussian elimination with
+    partial pivoting is normwise backward stable; a rounded product of blocks errs by a float ulp
+    of the sums of products), so a componentwise perturbation would miss blocks whose entries
+    differ greatly in size."""
     a = np.asarray(a, np.float64)
-    return a * (1.0 + g.uniform(-1.0, 1.0, a.shape) * 2.0 ** -24)
+    bs = 16 if a.ndim == 3 else (4 if a.ndim == 1 and a.size % 4 == 0 else 1)
+    blocks = a.reshape(-1, bs)
+    scale = np.abs(blocks).max(axis=1, keepdims=True)
+    return (blocks + g.uniform(-1.0, 1.0, blocks.shape) * 2.0 ** -24 * scale).reshape(a.shape)
 
 
 def _judge(name, got, ref, ref32, sens, what, shape=None):
@@ -44,7 +54,7 @@ def _judge(name, got, ref, ref32, sens, what, shape=None):
 
 
 def perturb(a, g):
-    """a with every value perturbed by one float unit in the last place (relative 2^-24, random sign)."""
+    """a perturbed by one float unit in the last place, normwise per block (see _perturb)."""
     return _perturb(a, g)
 
 
