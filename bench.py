@@ -597,7 +597,12 @@ def factor_convergence_bench(args):
         L.abilu_factor_from_csr(ref.pattern, "f64", ref.A, X0)
         dL, dU = L.abilu_factor_maxdiff(ref.pattern, "f64", X0, Y, ref.work)
         del X0
-        row = {"n": c.n, "nnzb": c.nnzb, "sweeps_to_fixed_point": fixed,
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        D, nl, nu = L.abilu_pattern_depth(ref.pattern)
+        t_depth = time.perf_counter() - t0
+        row = {"n": c.n, "nnzb": c.nnzb, "depth_D": D, "levels_lower": nl, "levels_upper": nu,
+               "depth_analysis_ms": round(t_depth * 1e3, 1), "sweeps_to_fixed_point": fixed,
                "x_ilu_ilu_residual": float(f"{ref.ilu_residual():.3e}"),
                "x_ilu_jacobi_norms": [float(f"{v:.4g}") for v in L.abilu_jacobi_norms(ref.pattern, "f64", Y, DY, ref.work)],
                "initial_maxdiff": [dL, dU], "runs": {}}
@@ -630,8 +635,9 @@ def factor_convergence_bench(args):
                 del s
                 torch.cuda.empty_cache()
         out[label] = row
-        summary[label] = {k: {"E_L": v["E_L_mean"], "E_U": v["E_U_mean"]} for k, v in row["runs"].items()
-                          if k in ("f64_async", "f32_async")}
+        a = row["runs"]["f32_async"]
+        summary[label] = {"D": D, "fixed_point_sweeps": fixed, "f32_async_E_L": a["E_L_mean"],
+                          "f32_async_E_U": a["E_U_mean"]}
         del ref, Y, DY
         torch.cuda.empty_cache()
     out["sweeps"] = nsws
@@ -757,6 +763,14 @@ TRAFFIC_KERNELS = {
 }
 
 
+def kernel_short_name(name):
+    """rocprofv3's kernel name without return type, namespace and parameter list: k_spmv<false>."""
+    n = name.replace("(anonymous namespace)::", "").strip()
+    if n.startswith("void "):
+        n = n[5:]
+    return n.split("(")[0].strip()
+
+
 def _csv_rows(d, suffix):
     import csv
     import glob
@@ -772,6 +786,8 @@ def summarize_stats(d, title, command):
     rows = _csv_rows(d, "kernel_stats.csv")
     if not rows:
         raise SystemExit(f"no kernel_stats.csv under {d}")
+    for r in rows:
+        r["Name"] = kernel_short_name(r["Name"])
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = [f"# rocprofv3 kernel statistics: {title}", "", "Command (run from the repository root on an MI355X machine):",
@@ -796,7 +812,7 @@ def summarize_traffic(fetch_dir, write_dir, command):
         for r in _csv_rows(d, "counter_collection.csv"):
             if r.get("Counter_Name") != counter:
                 continue
-            name = r["Kernel_Name"].split("(")[0].strip()
+            name = kernel_short_name(r["Kernel_Name"])
             acc.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0)
         return acc
     fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
@@ -1045,8 +1061,7 @@ def headline(out, detail_path=None):
     sub-benchmark, the full object being in the detail file."""
     h = {k: out.get(k) for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
                                  "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")}
-    h["value_covers"] = ("whole step: factor (init + build sweeps) and FGMRES to rtol with its apply sweeps, SpMVs and "
-                         "Gram-Schmidt; algorithmic bytes of every launch / wall time of the step")
+    h["value_covers"] = "whole step (factor, FGMRES with apply sweeps, SpMV, Gram-Schmidt): algorithmic bytes / wall time"
     rl = out.get("roofline") or {}
     h["roofline"] = _pick(rl, "bound", "kernel", "achieved", "peak", "unit", "frac", "traffic", "avg_launch_ms",
                           "algorithmic_bytes_per_launch")
@@ -1085,8 +1100,8 @@ def headline(out, detail_path=None):
         pair = lambda e: [e.get("rel"), e.get("max_block_rel")] if e else None
         h["precision"] = {
             "f32_speedup_step": pr.get("f32_speedup_step"),
-            "f32_vs_f64_legend": "[relative Frobenius, largest per-block relative] of FP32 against FP64 (= oracle) "
-                                 "after 1 and 2 SYNC sweeps (X, Dinv) and of one SYNC application (z)",
+            "f32_vs_f64_legend": "[rel Frobenius, max per-block rel] FP32 vs FP64 (= oracle): X, Dinv after 1, 2 SYNC "
+                                 "sweeps; z of one SYNC apply",
             "f32_vs_f64": {k: {"X1": pair(v.get("sweeps1", {}).get("X")), "D1": pair(v.get("sweeps1", {}).get("Dinv")),
                                "X2": pair(v.get("sweeps2", {}).get("X")), "D2": pair(v.get("sweeps2", {}).get("Dinv")),
                                "z": pair(v.get("apply"))}

@@ -5,7 +5,8 @@ its relative error is within max(1e-5, C s_b), where s_b is the relative change 
 block b when its inputs, and every iterate the single-precision path stores between sweeps, are
 perturbed by one float unit in the last place, normwise per block (each value moved by up to 2^-24
 times the largest magnitude in its block, random signs): the block's sensitivity to float-sized
-errors. Well-conditioned blocks get the stated 1e-5; blocks that
+errors, the largest response over 4 independent perturbations (one random direction can miss a
+block's ill-conditioned direction: the ratio of two random responses is heavy-tailed). Well-conditioned blocks get the stated 1e-5; blocks that
 depend on an ill-conditioned diagonal block get its conditioning. Under the initial guess L = A the
 first sweep forms U_ii = A_ii - sum A_ik A_ki, whose condition number reaches 8e6 on the
 aspect-ratio-1000 layers; storing that U_ii in float moves its inverse by up to cond x 2^-24 even
@@ -19,6 +20,7 @@ import numpy as np
 from tests.dense_ref import block_rel, rel
 
 C = 32.0      # float error allowed per block, in units of the block's float sensitivity
+SAMPLES = 4   # independent perturbations; a block's sensitivity is the largest response among them
 FLOOR = 1e-5  # the stated single-precision bar
 CAP = 0.5     # no block may be off by more than half its size, however ill-conditioned
 
@@ -66,12 +68,17 @@ class FactorBars:
     def __init__(self, run, A, X0=None, seed=23, perturbed=None):
         self.Xo, self.Do = run(A, X0)
         self.X32, self.D32 = run(f32(A), f32(X0))
-        g = np.random.default_rng(seed)
-        if perturbed is not None:
-            Xp, Dp = perturbed(g)
-        else:
-            Xp, Dp = run(_perturb(A, g), None if X0 is None else _perturb(X0, g))
-        self.sX, self.sD = block_rel(Xp, self.Xo), block_rel(Dp, self.Do)
+        self.sX = self.sD = None
+        for q in range(SAMPLES):
+            g = np.random.default_rng(seed + 1000 * q)
+            if perturbed is not None:
+                Xp, Dp = perturbed(g)
+            else:
+                Xp, Dp = run(_perturb(A, g), None if X0 is None else _perturb(X0, g))
+            sX, sD = block_rel(Xp, self.Xo), block_rel(Dp, self.Do)
+            del Xp, Dp
+            self.sX = sX if self.sX is None else np.maximum(self.sX, sX)
+            self.sD = sD if self.sD is None else np.maximum(self.sD, sD)
 
     def check(self, X, D, what=""):
         return {"X": _judge("X", X, self.Xo, self.X32, self.sX, what),
@@ -84,9 +91,12 @@ class VectorBars:
 
     def __init__(self, run, X, D, r, seed=29):
         self.ref = run(X, D, f32(r))
-        g = np.random.default_rng(seed)
-        refp = run(_perturb(X, g), _perturb(D, g), _perturb(f32(r), g))
-        self.sens = block_rel(refp.reshape(-1, 4), self.ref.reshape(-1, 4))
+        self.sens = None
+        for q in range(SAMPLES):
+            g = np.random.default_rng(seed + 1000 * q)
+            refp = run(_perturb(X, g), _perturb(D, g), _perturb(f32(r), g))
+            s = block_rel(refp.reshape(-1, 4), self.ref.reshape(-1, 4))
+            self.sens = s if self.sens is None else np.maximum(self.sens, s)
 
     def check(self, z, what=""):
         """Every cell within its bar and the whole vector within 1e-5."""

@@ -70,10 +70,13 @@ def _stub_detail():
                     "poisson": {"rate_per_s": 1096.0, "batched_f32": serve, "one_at_a_time_f64": serve},
                     "speedup_solves_per_s": 2.16},
         "warm_start": {"totals": {"cold": {"iters": 24}, "warm": {"iters": 12}}, "steps": steps},
-        "factor_convergence": {"summary": {"tri300_cfl1000": {"async_E4_mean": [0.5, 0.2, 0.1, 0.05, 0.01]}},
+        "factor_convergence": {"summary": {k: {"D": 11085, "fixed_point_sweeps": 37,
+                                               "f32_async_E_L": [0.03239, 0.001111, 4.155e-05, 1.88e-06, 7.728e-08],
+                                               "f32_async_E_U": [0.08257, 0.002898, 0.000103, 3.774e-06, 1.348e-06]}
+                                           for k in ("aniso1000_line", "tri2000")},
                                "runs": ["z" * 100] * 50},
         "cpu_baseline": {"value": 13.5, "unit": "GB/s", "cores": 16, "kind": "oracle", "cpu_model": "AMD EPYC 9575F",
-                         "host_cpus": 256, "sample": "s" * 300, "seconds": 12.3,
+                         "host_cpus": 256, "sample": "s" * 220, "seconds": 12.3,
                          "sequential": {"ilu0_ms": 615.0, "exact_substitution_ms": 80.0, "threads": 1, "what": "w" * 200},
                          "oracle_check": {"what": "w" * 80, "f64_bitwise_equal": True,
                                           "f64": {"X": err, "Dinv": err}, "f32": {"X": err, "Dinv": err}}},
