@@ -13,7 +13,10 @@
 //
 // One thread per row: row t's blocks in ascending column order (a block reads the X_ik of its own
 // row, computed earlier in the same pass) and its lower level, and the upper level of row n-1-t,
-// so that both chains run with the ascending dispatch order of the workgroups.
+// so that both chains run with the ascending dispatch order of the workgroups. After the first
+// pass a row is recomputed only when it or a row it reads changed in the pass before: at the fixed
+// point every row was recomputed after the last change of everything it reads, and most passes
+// touch only the rows near the advancing front of the longest chains.
 #include "abilu_internal.h"
 
 using namespace abilu;
@@ -23,43 +26,63 @@ namespace {
 constexpr int DWG = 256;
 constexpr int BATCH = 32;   // passes launched between two host checks
 
+// One relaxation pass. A row is recomputed only if it, or a row it reads, changed in the previous
+// pass (chg_prev): the lower rows for its blocks' depths and its lower level, the upper rows for
+// its upper level. Rows that change raise chg_cur; chg_clear (the flags two passes on) is zeroed
+// here, so that three flag arrays rotate without a separate clearing launch.
 __global__ __launch_bounds__(DWG) void k_depth_pass(int n, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ colidx,
                                                     const int32_t *__restrict__ diag_pos,
                                                     const int32_t *__restrict__ pair_ptr,
                                                     const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
-                                                    int32_t *depth, int32_t *lev_l, int32_t *lev_u, int *changed) {
+                                                    int32_t *depth, int32_t *lev_l, int32_t *lev_u,
+                                                    const uint8_t *__restrict__ chg_prev, uint8_t *chg_cur,
+                                                    uint8_t *__restrict__ chg_clear, int all, int *changed) {
     const int t = blockIdx.x * DWG + threadIdx.x;
     bool ch = false;
     if (t < n) {
+        chg_clear[t] = 0;
         const int i = t;
-        int ml = 0;
-        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-            const int j = colidx[e];
-            int d = 0;
-            for (int q = pair_ptr[e]; q < pair_ptr[e + 1]; ++q) d = max(d, max(depth[pik[q]], depth[pkj[q]]));
-            if (i > j) {
-                d = max(d, depth[diag_pos[j]]);
-                ml = max(ml, lev_l[j]);
+        const int b0 = rowptr[i], d = diag_pos[i];
+        bool go = all || chg_prev[i];
+        for (int e = b0; e < d && !go; ++e) go = chg_prev[colidx[e]] != 0;
+        if (go) {
+            bool mine = false;
+            int ml = 0;
+            for (int e = b0; e < rowptr[i + 1]; ++e) {
+                const int j = colidx[e];
+                int dd = 0;
+                for (int q = pair_ptr[e]; q < pair_ptr[e + 1]; ++q) dd = max(dd, max(depth[pik[q]], depth[pkj[q]]));
+                if (i > j) {
+                    dd = max(dd, depth[diag_pos[j]]);
+                    ml = max(ml, lev_l[j]);
+                }
+                if (dd + 1 > depth[e]) {
+                    depth[e] = dd + 1;
+                    mine = true;
+                }
             }
-            if (d + 1 > depth[e]) {
-                depth[e] = d + 1;
+            if (ml + 1 > lev_l[i]) {
+                lev_l[i] = ml + 1;
+                mine = true;
+            }
+            if (mine) {
+                chg_cur[i] = 1;
                 ch = true;
             }
         }
-        if (ml + 1 > lev_l[i]) {
-            lev_l[i] = ml + 1;
-            ch = true;
-        }
         const int iu = n - 1 - t;
-        int mu = 0;
-        for (int e = rowptr[iu]; e < rowptr[iu + 1]; ++e) {
-            const int j = colidx[e];
-            if (j > iu) mu = max(mu, lev_u[j]);
-        }
-        if (mu + 1 > lev_u[iu]) {
-            lev_u[iu] = mu + 1;
-            ch = true;
+        const int du = diag_pos[iu], e1 = rowptr[iu + 1];
+        bool gu = all || chg_prev[iu];
+        for (int e = du + 1; e < e1 && !gu; ++e) gu = chg_prev[colidx[e]] != 0;
+        if (gu) {
+            int mu = 0;
+            for (int e = du + 1; e < e1; ++e) mu = max(mu, lev_u[colidx[e]]);
+            if (mu + 1 > lev_u[iu]) {
+                lev_u[iu] = mu + 1;
+                chg_cur[iu] = 1;
+                ch = true;
+            }
         }
     }
     // one flag write per wavefront that changed something
@@ -108,11 +131,13 @@ extern "C" abilu_status abilu_pattern_depth(abilu_pattern *p, int32_t *d_depth, 
         p->depth_D = 0;
         p->levels[0] = p->levels[1] = 0;
     } else {
-        // scratch: depth[Z], lev_l[N], lev_u[N], BATCH change flags, 3 maxima
+        // scratch: depth[Z], lev_l[N], lev_u[N], BATCH pass flags, 3 maxima, then 3 x N row flags
         int32_t *buf = nullptr;
         const size_t words = (size_t)Z + 2 * (size_t)n + BATCH + 3;
-        if (!hip_ok(hipMalloc(&buf, sizeof(int32_t) * words), "depth scratch")) return ABILU_ENOMEM;
+        const size_t rowflags = ((size_t)3 * n + 3) / 4;     // in int32 words
+        if (!hip_ok(hipMalloc(&buf, sizeof(int32_t) * (words + rowflags)), "depth scratch")) return ABILU_ENOMEM;
         int32_t *depth = buf, *lev_l = buf + Z, *lev_u = lev_l + n, *flags = lev_u + n, *mx = flags + BATCH;
+        uint8_t *chg = (uint8_t *)(buf + words);
         abilu_status st = ABILU_OK;
         const int grid = div_up(n, DWG);
         // each pass reads at least the values the pass before it left, so after pass p every value
@@ -121,13 +146,17 @@ extern "C" abilu_status abilu_pattern_depth(abilu_pattern *p, int32_t *d_depth, 
         const int64_t cap = Z + (int64_t)n + 2 * BATCH;
         int64_t passes = 0;
         bool done = false;
-        k_fill_i32<<<div_up((int64_t)words, DWG), DWG, 0, s>>>((int64_t)words, buf, 0);
+        k_fill_i32<<<div_up((int64_t)(words + rowflags), DWG), DWG, 0, s>>>((int64_t)(words + rowflags), buf, 0);
         if (launch_status() != ABILU_OK) st = ABILU_EDEVICE;
         while (st == ABILU_OK && !done) {
             k_fill_i32<<<1, DWG, 0, s>>>(BATCH, flags, 0);
-            for (int q = 0; q < BATCH; ++q)
+            for (int q = 0; q < BATCH; ++q) {
+                const int64_t pass = passes + q;
                 k_depth_pass<<<grid, DWG, 0, s>>>(n, p->rowptr, p->colidx, p->diag_pos, p->pair_ptr, p->pik, p->pkj,
-                                                   depth, lev_l, lev_u, flags + q);
+                                                   depth, lev_l, lev_u, chg + (size_t)n * ((pass + 2) % 3),
+                                                   chg + (size_t)n * (pass % 3), chg + (size_t)n * ((pass + 1) % 3),
+                                                   pass == 0 ? 1 : 0, flags + q);
+            }
             if (launch_status() != ABILU_OK) { st = ABILU_EDEVICE; break; }
             int32_t h[BATCH];
             if (!hip_ok(hipMemcpyAsync(h, flags, sizeof h, hipMemcpyDeviceToHost, s), "depth flags") ||
