@@ -841,11 +841,51 @@ def summarize_traffic(fetch_dir, write_dir, command):
     return json.dumps(out, indent=1) + "\n", "\n".join(md) + "\n"
 
 
+def summarize_serving_traffic(fetch_dir, write_dir, cf, cw, command):
+    """Measured bytes of the serving run per kernel, summed over its dispatches, from two
+    rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), scaled by the STREAM-copy calibration
+    factors cf, cw of the headline traffic measurement. Solve kernels (kb_*) and admission kernels
+    (kbs_*) are totalled separately. Returns markdown."""
+    def per_kernel(d, counter, f):
+        acc = {}
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = kernel_short_name(r["Kernel_Name"])
+            n, b = acc.get(name, (0, 0.0))
+            acc[name] = (n + 1, b + float(r["Counter_Value"]) * 1024.0 * f)
+        return acc
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE", cf), per_kernel(write_dir, "WRITE_SIZE", cw)
+    names = sorted(set(fetch) | set(write), key=lambda k: -(fetch.get(k, (0, 0))[1] + write.get(k, (0, 0))[1]))
+    md = ["# Measured HBM traffic of the serving run: 2000 requests released at t = 0, batched FP32 preconditioner",
+          "", "Command (run from the repository root on an MI355X machine):", "", "```", command, "```", "",
+          f"FETCH_SIZE and WRITE_SIZE (KiB per dispatch) summed over each kernel's dispatches and scaled by the "
+          f"STREAM-copy calibration of the headline traffic measurement ({cf:.3f}, {cw:.3f}). `kb_*` are the "
+          "batched solve kernels, `kbs_*` the admission kernels (matrix generation and pattern analysis of "
+          "arriving requests), which run concurrently on a second stream.", "",
+          "| kernel | dispatches | fetch GB | write GB | total GB |", "|---|---:|---:|---:|---:|"]
+    groups = {"solve (kb_*)": 0.0, "admission (kbs_*)": 0.0, "other": 0.0}
+    for k in names:
+        n = max(fetch.get(k, (0, 0))[0], write.get(k, (0, 0))[0])
+        f, w = fetch.get(k, (0, 0.0))[1], write.get(k, (0, 0.0))[1]
+        g = "admission (kbs_*)" if k.startswith("kbs_") else ("solve (kb_*)" if k.startswith("kb_") else "other")
+        groups[g] += f + w
+        if f + w >= 1e9:
+            md.append(f"| `{k}` | {n} | {f / 1e9:.2f} | {w / 1e9:.2f} | {(f + w) / 1e9:.2f} |")
+    md += ["", "Kernels under 1 GB are left out of the table and counted in the totals.", "",
+           "| group | total GB |", "|---|---:|"]
+    for g, b in groups.items():
+        md.append(f"| {g} | {b / 1e9:.1f} |")
+    md.append(f"| all | {sum(groups.values()) / 1e9:.1f} |")
+    return "\n".join(md) + "\n"
+
+
 STREAM_BYTES = 2 * (2 << 30)   # algorithmic bytes of one stream_reference copy launch (read + write)
 
 
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-stats", "--summarize-traffic"):
+    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-stats", "--summarize-traffic",
+                                             "--summarize-serving-traffic"):
         return summarize_main(sys.argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1126,10 +1166,14 @@ def headline(out, detail_path=None):
 def summarize_main(argv):
     """bench.py --summarize-stats DIR TITLE COMMAND OUT.md
        bench.py --summarize-traffic FETCH_DIR WRITE_DIR COMMAND OUT_BASENAME  (writes .txt and .md)
+       bench.py --summarize-serving-traffic FETCH_DIR WRITE_DIR FETCH_FACTOR WRITE_FACTOR COMMAND OUT.md
     Turn rocprofv3 output into the summaries kept under profiles/."""
     if argv[0] == "--summarize-stats":
         d, title, command, out = argv[1:5]
         open(out, "w").write(summarize_stats(d, title, command))
+    elif argv[0] == "--summarize-serving-traffic":
+        fd, wd, cf, cw, command, out = argv[1:7]
+        open(out, "w").write(summarize_serving_traffic(fd, wd, float(cf), float(cw), command))
     else:
         fd, wd, command, base = argv[1:5]
         js, md = summarize_traffic(fd, wd, command)
