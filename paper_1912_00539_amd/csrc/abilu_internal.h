@@ -43,6 +43,10 @@ struct abilu_pattern {
     int32_t *order[2] = {nullptr, nullptr};
     int32_t *lvptr[2] = {nullptr, nullptr};
     int32_t *lvstart[2] = {nullptr, nullptr};
+    // per-row records of the quad-per-chunk runner (ABILU_CHUNK_BY_ROWS only): REC_INTS int32 per
+    // row, stored step-major (record of row c * chunk_rows + t at index t * nchunks + c)
+    int32_t *rec = nullptr;
+    int32_t rec_max[3] = {0, 0, 0};   // largest strictly lower / strictly upper / pair count of a row
     // dependency analysis (abilu_pattern_depth): depth D and the lower/upper level counts, -1 until
     // computed
     int32_t depth_D = -1;
@@ -181,6 +185,26 @@ inline bool mode_ok(const abilu_pattern *p, abilu_mode m) {
 void free_chunks(abilu_pattern *p);
 int32_t chunk_runner_auto(int n, int nch, const int64_t *total_levels);
 constexpr int MAX_CHUNK_ROWS = 4096;
+
+// Per-row record of the quad-per-chunk runner: everything a row's chunked sweep needs to find its
+// operands, in one 96-byte read, classified by where each operand comes from.
+//   [0] rowptr[i]  [1] lrow[i]  [2] urow[i]
+//   [3] meta: bits 0-3 min(nl, 15), 4-7 min(nu, 15), 8-11 min(np, 15) (strictly lower blocks,
+//       strictly upper blocks, update pairs of the row); bits 12 + 2u: source of the lower
+//       neighbour u (u < 4); bits 20 + 2w: source of the upper neighbour w (w < 4)
+//   [4..7] columns of the first four strictly lower blocks
+//   [8..11] update pair p (p < 4, in pair-list order): bits 0-3 target block (0-3 lower block u,
+//       4 diagonal, 5-8 upper block w), 4-5 ordinal of L_ik among the row's lower blocks,
+//       6-7 source of U_kj, 8-9 ordinal of U_kj among row i-1's upper blocks (source REC_PREV;
+//       meaningful when row i-1 has at most REC_CAP of them)
+//   [12..15] factor-layout position of U_kj  [16..19] CSR position of (k, j)
+//   [20..23] columns of the first four strictly upper blocks
+// A row with more than REC_CAP lower or upper blocks or update pairs takes the general code.
+constexpr int REC_INTS = 24;
+constexpr int REC_CAP = 4;
+// Sources: the neighbouring row of the chunk computed just before (row i - 1 forward, i + 1
+// backward), another row of the chunk, a row outside the chunk.
+enum : int { REC_PREV = 0, REC_CHUNK = 1, REC_OUT = 2 };
 
 // ------------------------------------------------------------------ entry points used across files
 abilu_status apply_impl(const abilu_pattern *p, const void *LU, const void *Dinv, abilu_prec prec,

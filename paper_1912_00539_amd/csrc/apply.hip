@@ -193,26 +193,133 @@ __global__ __launch_bounds__(WG) void k_bwd_chunk(int n, int R, const int32_t *_
 }
 
 // The same sweeps with one quad per chunk running its rows in order (forward ascending, backward
-// descending); a lane only reads chunk values it stored itself.
+// descending); a lane only reads chunk values it stored itself, and takes the element of the row
+// computed just before from a register. Each row's operands are located by its record (read one
+// row ahead) and fetched together; rows with more than REC_CAP blocks in the part take the general
+// row code. The arithmetic and its order are those of fwd_chunk_row / bwd_chunk_row.
+__device__ __forceinline__ int4 rec_quad(const int32_t *__restrict__ rec, int c, int nch, int t, int k) {
+    return reinterpret_cast<const int4 *>(rec + ((int64_t)t * nch + c) * REC_INTS)[k];
+}
+
 template <typename T, bool ZERO_OUT>
-__global__ __launch_bounds__(WG) void k_fwd_chunk_rows(int n, int R, int nch, const int32_t *__restrict__ lrow,
+__global__ __launch_bounds__(WG) void k_fwd_chunk_rows(int n, int R, int nch, const int32_t *__restrict__ rec,
+                                                       const int32_t *__restrict__ lrow,
                                                        const int32_t *__restrict__ lcol, const T *__restrict__ Lb,
                                                        const double *__restrict__ rhs, const T *yo, T *yn) {
     const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
     if (c >= nch) return;
-    const int c0 = c * R, c1 = min(n, c0 + R);
-    for (int i = c0; i < c1; ++i) fwd_chunk_row<T, ZERO_OUT>(i, c0, lrow, lcol, Lb, rhs, yo, yn);
+    const int r = threadIdx.x & 3;
+    const int c0 = c * R, m = min(n, c0 + R) - c0;
+    T py = T(0);               // y of row i - 1 (this lane's element)
+    bool have_prev = false;
+    int4 h = rec_quad(rec, c, nch, 0, 0), cols = rec_quad(rec, c, nch, 0, 1);
+    for (int t = 0; t < m; ++t) {
+        const int i = c0 + t;
+        const int lb = h.y, meta = h.w, nl = meta & 15;
+        const int jl[REC_CAP] = {cols.x, cols.y, cols.z, cols.w};
+        if (nl > REC_CAP) {
+            if (t + 1 < m) {
+                h = rec_quad(rec, c, nch, t + 1, 0);
+                cols = rec_quad(rec, c, nch, t + 1, 1);
+            }
+            fwd_chunk_row<T, ZERO_OUT>(i, c0, lrow, lcol, Lb, rhs, yo, yn);
+            have_prev = false;
+            continue;
+        }
+        T acc = (T)rhs[(int64_t)i * 4 + r];
+        T l[REC_CAP][4], yv[REC_CAP];
+#pragma unroll
+        for (int u = 0; u < REC_CAP; ++u)
+            if (u < nl) load_row(Lb + (int64_t)(lb + u) * BB, r, l[u]);
+#pragma unroll
+        for (int u = 0; u < REC_CAP; ++u) {
+            if (u < nl) {
+                const int src = (meta >> (12 + 2 * u)) & 3;
+                if (src == REC_PREV && have_prev) yv[u] = py;
+                else if (src != REC_OUT) yv[u] = yn[(int64_t)jl[u] * 4 + r];
+                else if constexpr (ZERO_OUT) yv[u] = T(0);
+                else yv[u] = yo[(int64_t)jl[u] * 4 + r];
+            }
+        }
+        if (t + 1 < m) {
+            h = rec_quad(rec, c, nch, t + 1, 0);
+            cols = rec_quad(rec, c, nch, t + 1, 1);
+        }
+#pragma unroll
+        for (int u = 0; u < REC_CAP; ++u) {
+            if (u < nl) {
+                T yj[4];
+                gather_vec(yv[u], yj);
+                acc -= dot4(l[u][0], yj[0], l[u][1], yj[1], l[u][2], yj[2], l[u][3], yj[3]);
+            }
+        }
+        yn[(int64_t)i * 4 + r] = acc;
+        py = acc;
+        have_prev = true;
+    }
 }
 
 template <typename T, typename ZN, bool ZERO_OUT>
-__global__ __launch_bounds__(WG) void k_bwd_chunk_rows(int n, int R, int nch, const int32_t *__restrict__ urow,
+__global__ __launch_bounds__(WG) void k_bwd_chunk_rows(int n, int R, int nch, const int32_t *__restrict__ rec,
+                                                       const int32_t *__restrict__ urow,
                                                        const int32_t *__restrict__ ucol, const T *__restrict__ Ub,
                                                        const T *__restrict__ Dinv, const T *__restrict__ y,
                                                        const T *zo, ZN *zn) {
     const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
     if (c >= nch) return;
-    const int c0 = c * R, c1 = min(n, c0 + R);
-    for (int i = c1 - 1; i >= c0; --i) bwd_chunk_row<T, ZN, ZERO_OUT>(i, c1, urow, ucol, Ub, Dinv, y, zo, zn);
+    const int r = threadIdx.x & 3;
+    const int c0 = c * R, c1 = min(n, c0 + R), m = c1 - c0;
+    T pz = T(0);               // z of row i + 1 (this lane's element)
+    bool have_prev = false;
+    int4 h = rec_quad(rec, c, nch, m - 1, 0), cols = rec_quad(rec, c, nch, m - 1, 5);
+    for (int t = m - 1; t >= 0; --t) {
+        const int i = c0 + t;
+        const int ub = h.z, meta = h.w, nu = (meta >> 4) & 15;
+        const int ju[REC_CAP] = {cols.x, cols.y, cols.z, cols.w};
+        if (nu > REC_CAP) {
+            if (t > 0) {
+                h = rec_quad(rec, c, nch, t - 1, 0);
+                cols = rec_quad(rec, c, nch, t - 1, 5);
+            }
+            bwd_chunk_row<T, ZN, ZERO_OUT>(i, c1, urow, ucol, Ub, Dinv, y, zo, zn);
+            have_prev = false;
+            continue;
+        }
+        T acc = y[(int64_t)i * 4 + r];
+        T u4[REC_CAP][4], zv[REC_CAP], dr[4];
+#pragma unroll
+        for (int w = 0; w < REC_CAP; ++w)
+            if (w < nu) load_row(Ub + (int64_t)(ub + w) * BB, r, u4[w]);
+#pragma unroll
+        for (int w = 0; w < REC_CAP; ++w) {
+            if (w < nu) {
+                const int src = (meta >> (20 + 2 * w)) & 3;
+                if (src == REC_PREV && have_prev) zv[w] = pz;
+                else if (src != REC_OUT) zv[w] = (T)zn[(int64_t)ju[w] * 4 + r];
+                else if constexpr (ZERO_OUT) zv[w] = T(0);
+                else zv[w] = zo[(int64_t)ju[w] * 4 + r];
+            }
+        }
+        load_row(Dinv + (int64_t)i * BB, r, dr);
+        if (t > 0) {
+            h = rec_quad(rec, c, nch, t - 1, 0);
+            cols = rec_quad(rec, c, nch, t - 1, 5);
+        }
+#pragma unroll
+        for (int w = 0; w < REC_CAP; ++w) {
+            if (w < nu) {
+                T zj[4];
+                gather_vec(zv[w], zj);
+                acc -= dot4(u4[w][0], zj[0], u4[w][1], zj[1], u4[w][2], zj[2], u4[w][3], zj[3]);
+            }
+        }
+        T a[4];
+        gather_vec(acc, a);
+        const T z = dot4(dr[0], a[0], dr[1], a[1], dr[2], a[2], dr[3], a[3]);
+        zn[(int64_t)i * 4 + r] = (ZN)z;
+        pz = z;
+        have_prev = true;
+    }
 }
 
 // y = A x  (RESID: y = b - A x), double precision, CSR; one quad per block row, four blocks
@@ -298,8 +405,8 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
         // yo == nullptr: first sweep (earlier rows contribute their initial value 0)
         auto fwd = [&](const T *yo, T *yn) {
             if (by_rows) {
-                if (!yo) k_fwd_chunk_rows<T, true><<<g, WG, 0, s>>>(n, R, nch, lrow, lcol, Lb, r, yo, yn);
-                else k_fwd_chunk_rows<T, false><<<g, WG, 0, s>>>(n, R, nch, lrow, lcol, Lb, r, yo, yn);
+                if (!yo) k_fwd_chunk_rows<T, true><<<g, WG, 0, s>>>(n, R, nch, p->rec, lrow, lcol, Lb, r, yo, yn);
+                else k_fwd_chunk_rows<T, false><<<g, WG, 0, s>>>(n, R, nch, p->rec, lrow, lcol, Lb, r, yo, yn);
             } else {
                 if (!yo) k_fwd_chunk<T, true><<<g, WG, 0, s>>>(n, R, O[0], LP[0], LS[0], lrow, lcol, Lb, r, yo, yn);
                 else k_fwd_chunk<T, false><<<g, WG, 0, s>>>(n, R, O[0], LP[0], LS[0], lrow, lcol, Lb, r, yo, yn);
@@ -308,8 +415,8 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
         auto bwd = [&](const T *y, const T *zo, auto *zn) {
             using ZN = std::remove_pointer_t<decltype(zn)>;
             if (by_rows) {
-                if (!zo) k_bwd_chunk_rows<T, ZN, true><<<g, WG, 0, s>>>(n, R, nch, urow, ucol, Ub, Dinv, y, zo, zn);
-                else k_bwd_chunk_rows<T, ZN, false><<<g, WG, 0, s>>>(n, R, nch, urow, ucol, Ub, Dinv, y, zo, zn);
+                if (!zo) k_bwd_chunk_rows<T, ZN, true><<<g, WG, 0, s>>>(n, R, nch, p->rec, urow, ucol, Ub, Dinv, y, zo, zn);
+                else k_bwd_chunk_rows<T, ZN, false><<<g, WG, 0, s>>>(n, R, nch, p->rec, urow, ucol, Ub, Dinv, y, zo, zn);
             } else {
                 if (!zo)
                     k_bwd_chunk<T, ZN, true><<<g, WG, 0, s>>>(n, R, O[1], LP[1], LS[1], urow, ucol, Ub, Dinv, y, zo, zn);

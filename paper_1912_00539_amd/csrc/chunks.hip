@@ -75,6 +75,70 @@ __global__ __launch_bounds__(256) void k_chunk_order(int n, int R, const int32_t
     if (threadIdx.x == 0) lvstart[b + nl] = c1;
 }
 
+// One thread per row: the row's record for the quad-per-chunk runner (layout beside REC_INTS).
+__global__ void k_chunk_records(int n, int R, int nch, int ZL, const int32_t *__restrict__ rowptr,
+                                const int32_t *__restrict__ colidx, const int32_t *__restrict__ diag_pos,
+                                const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+                                const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ sik,
+                                const int32_t *__restrict__ skj, const int32_t *__restrict__ pkj,
+                                int32_t *__restrict__ rec, int *__restrict__ maxima) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = i / R, t = i - c * R, c0 = c * R, c1 = min(n, c0 + R);
+    const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
+    const int nl = d - b0, nu = b1 - d - 1;
+    const int p0 = pair_ptr[b0], np = pair_ptr[b1] - p0;
+    int v[REC_INTS];
+    for (int k = 0; k < REC_INTS; ++k) v[k] = 0;
+    v[0] = b0;
+    v[1] = lrow[i];
+    v[2] = urow[i];
+    int meta = min(nl, 15) | (min(nu, 15) << 4) | (min(np, 15) << 8);
+    for (int u = 0; u < min(nl, REC_CAP); ++u) {
+        const int j = colidx[b0 + u];
+        const int src = j < c0 ? REC_OUT : (j == i - 1 ? REC_PREV : REC_CHUNK);
+        meta |= src << (12 + 2 * u);
+        v[4 + u] = j;
+    }
+    for (int w = 0; w < min(nu, REC_CAP); ++w) {
+        const int j = colidx[d + 1 + w];
+        const int src = j >= c1 ? REC_OUT : (j == i + 1 ? REC_PREV : REC_CHUNK);
+        meta |= src << (20 + 2 * w);
+        v[20 + w] = j;
+    }
+    v[3] = meta;
+    // U_kj at factor-layout position s belongs to a row of the chunk when s >= ubound, to row i - 1
+    // when s lies in that row's upper part
+    const int ubase = ZL + n;
+    const int ubound = ubase + urow[c0];
+    const int prev0 = i > c0 ? ubase + urow[i - 1] : -1, prev1 = ubase + urow[i];
+    int e = b0;
+    for (int q = 0; q < min(np, REC_CAP); ++q) {
+        const int pq = p0 + q;
+        while (pair_ptr[e + 1] <= pq) ++e;   // the block the pair updates
+        const int tgt = e < d ? e - b0 : (e == d ? 4 : 5 + (e - d - 1));
+        const int lord = sik[pq] - lrow[i];
+        const int sp = skj[pq];
+        int src = REC_OUT, o = 0;
+        if (sp >= ubound) {
+            src = REC_CHUNK;
+            if (prev0 >= 0 && sp >= prev0 && sp < prev1) {
+                // row i - 1: its blocks are in registers when it had at most REC_CAP upper blocks
+                src = REC_PREV;
+                o = (sp - prev0) & 3;
+            }
+        }
+        v[8 + q] = (tgt & 15) | ((lord & 3) << 4) | (src << 6) | (o << 8);
+        v[12 + q] = sp;
+        v[16 + q] = pkj[pq];
+    }
+    int32_t *out = rec + ((int64_t)t * nch + c) * REC_INTS;
+    for (int k = 0; k < REC_INTS; ++k) out[k] = v[k];
+    atomicMax(&maxima[0], nl);
+    atomicMax(&maxima[1], nu);
+    atomicMax(&maxima[2], np);
+}
+
 }  // namespace
 
 namespace abilu {
@@ -96,6 +160,9 @@ void free_chunks(abilu_pattern *p) {
         p->max_levels[s] = 0;
         p->total_levels[s] = 0;
     }
+    (void)hipFree(p->rec);
+    p->rec = nullptr;
+    p->rec_max[0] = p->rec_max[1] = p->rec_max[2] = 0;
     p->chunk_rows = 0;
     p->nchunks = 0;
     p->chunk_runner = 0;
@@ -176,9 +243,24 @@ extern "C" abilu_status abilu_pattern_set_chunks(abilu_pattern *p, int32_t rows_
     }
     CK(hipStreamSynchronize(s));
     (void)hipFree(scratch);
+    scratch = nullptr;
+    p->chunk_runner = runner != ABILU_CHUNK_AUTO ? runner : chunk_runner_auto(n, nch, p->total_levels);
+    if (p->chunk_runner == ABILU_CHUNK_BY_ROWS) {
+        // the records, then the largest lower, upper and pair counts of a row
+        const size_t rbytes = sizeof(int32_t) * REC_INTS * (size_t)nch * (size_t)R;
+        CKA(hipMalloc(&p->rec, rbytes + 4 * sizeof(int)));
+        int *maxima = (int *)((char *)p->rec + rbytes);
+        CK(hipMemsetAsync(maxima, 0, 4 * sizeof(int), s));
+        k_chunk_records<<<div_up(n, 256), 256, 0, s>>>(n, R, nch, (int)p->nnzb_lower, p->rowptr, p->colidx,
+                                                       p->diag_pos, p->lrow, p->urow, p->pair_ptr, p->sik, p->skj,
+                                                       p->pkj, p->rec, maxima);
+        CK(hipGetLastError());
+        CK(hipMemcpyAsync(h, maxima, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        for (int q = 0; q < 3; ++q) p->rec_max[q] = h[q];
+    }
     p->chunk_rows = R;
     p->nchunks = nch;
-    p->chunk_runner = runner != ABILU_CHUNK_AUTO ? runner : chunk_runner_auto(n, nch, p->total_levels);
     return ABILU_OK;
 fail:
     (void)hipStreamSynchronize(s);

@@ -102,21 +102,332 @@ __global__ __launch_bounds__(WG) void k_factor_sweep_chunk(
 
 // One chunked sweep with one quad per chunk running the chunk's rows in ascending order (the
 // worker-per-chunk form of the same sweep). Every value of the chunk that a lane reads was stored
-// by that same lane (lane r owns row r of every block), so program order makes it visible.
+// by that same lane (lane r owns row r of every block), so program order makes it visible; the
+// values of the row computed just before are taken from registers instead. Each row's operands
+// are located by its record (read one row ahead) and fetched together, so a row costs one memory
+// round trip. The arithmetic, and its order, is that of factor_chunk_row, which takes the rows a
+// record cannot describe.
 template <typename T, bool OUT_FROM_A>
 __global__ __launch_bounds__(WG) void k_factor_sweep_chunk_rows(
-    int n, int ZL, int R, int nch, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-    const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
-    const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pkj, const int32_t *__restrict__ sik,
-    const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XO, const T *DO, T *Xn, T *Dn,
-    unsigned *flags) {
+    int n, int ZL, int R, int nch, const int32_t *__restrict__ rec, const int32_t *__restrict__ rowptr,
+    const int32_t *__restrict__ colidx, const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow,
+    const int32_t *__restrict__ urow, const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pkj,
+    const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XO,
+    const T *DO, T *Xn, T *Dn, unsigned *flags) {
     const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
     if (c >= nch) return;
-    const int c0 = c * R, c1 = min(n, c0 + R);
-    const int ubound = ZL + n + urow[c0];
-    for (int i = c0; i < c1; ++i)
-        factor_chunk_row<T, OUT_FROM_A, true>(i, c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr,
-                                              pkj, sik, skj, A, XO, DO, Xn, Dn, flags);
+    const int r = threadIdx.x & 3;
+    const int c0 = c * R, m = min(n, c0 + R) - c0;
+    const int ubase = ZL + n;
+    const int ubound = ubase + urow[c0];
+    T pD[4] = {}, pU[REC_CAP][4] = {};   // row i - 1: this lane's rows of Dinv and the upper blocks
+    bool have_prev = false;
+    unsigned fl = 0;
+    int4 rc[6];
+    load_rec(rec, c, nch, 0, rc);
+    for (int t = 0; t < m; ++t) {
+        const int i = c0 + t;
+        const int b0 = rec_field<0>(rc), lb = rec_field<1>(rc), ub = rec_field<2>(rc), meta = rec_field<3>(rc);
+        const int nl = meta & 15, nu = (meta >> 4) & 15, np = (meta >> 8) & 15;
+        const int jl[REC_CAP] = {rec_field<4>(rc), rec_field<5>(rc), rec_field<6>(rc), rec_field<7>(rc)};
+        const int pc[REC_CAP] = {rec_field<8>(rc), rec_field<9>(rc), rec_field<10>(rc), rec_field<11>(rc)};
+        const int sp[REC_CAP] = {rec_field<12>(rc), rec_field<13>(rc), rec_field<14>(rc), rec_field<15>(rc)};
+        const int pk[REC_CAP] = {rec_field<16>(rc), rec_field<17>(rc), rec_field<18>(rc), rec_field<19>(rc)};
+        if (nl > REC_CAP || nu > REC_CAP || np > REC_CAP) {
+            if (t + 1 < m) load_rec(rec, c, nch, t + 1, rc);
+            factor_chunk_row<T, OUT_FROM_A, true>(i, c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow,
+                                                  pair_ptr, pkj, sik, skj, A, XO, DO, Xn, Dn, flags);
+            have_prev = false;
+            continue;
+        }
+        // every operand of the row: A's blocks, the inverses of the lower neighbours, the U_kj
+        T aL[REC_CAP][4], aD[4], aU[REC_CAP][4], dj[REC_CAP][4], uv[REC_CAP][4];
+#pragma unroll
+        for (int u = 0; u < REC_CAP; ++u)
+            if (u < nl) load_row(A + (int64_t)(b0 + u) * BB, r, aL[u]);
+        load_row(A + (int64_t)(b0 + nl) * BB, r, aD);
+#pragma unroll
+        for (int w = 0; w < REC_CAP; ++w)
+            if (w < nu) load_row(A + (int64_t)(b0 + nl + 1 + w) * BB, r, aU[w]);
+#pragma unroll
+        for (int u = 0; u < REC_CAP; ++u) {
+            if (u < nl) {
+                const int src = (meta >> (12 + 2 * u)) & 3;
+                if (src == REC_PREV && have_prev) copy_row(pD, dj[u]);
+                else load_row((src == REC_OUT ? DO : (const T *)Dn) + (int64_t)jl[u] * BB, r, dj[u]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < REC_CAP; ++q) {
+            if (q < np) {
+                const int src = (pc[q] >> 6) & 3;
+                if (src == REC_PREV && have_prev) pick_row(pU, (pc[q] >> 8) & 3, uv[q]);
+                else if (src != REC_OUT) load_row((const T *)Xn + (int64_t)sp[q] * BB, r, uv[q]);
+                else if constexpr (OUT_FROM_A) load_row(A + (int64_t)pk[q] * BB, r, uv[q]);
+                else load_row(XO + (int64_t)sp[q] * BB, r, uv[q]);
+            }
+        }
+        if (t + 1 < m) load_rec(rec, c, nch, t + 1, rc);   // the next row's record, behind this row's loads
+        // strictly lower blocks in ascending column order, each seeing the ones before it
+        T Lx[REC_CAP][4] = {};
+#pragma unroll
+        for (int u = 0; u < REC_CAP; ++u) {
+            if (u < nl) {
+                T tt[4];
+                copy_row(aL[u], tt);
+#pragma unroll
+                for (int q = 0; q < REC_CAP; ++q) {
+                    if (q < np && (pc[q] & 15) == u) {
+                        T l[4];
+                        pick_row(Lx, (pc[q] >> 4) & 3, l);
+                        row_times_block_sub(l, uv[q], tt);
+                    }
+                }
+                row_times_block(tt, dj[u], Lx[u]);
+                fl |= nonfinite4(Lx[u]);
+                store_row(Xn + ((int64_t)lb + u) * BB, r, Lx[u]);
+            }
+        }
+        // diagonal block and its inverse
+        {
+#pragma unroll
+            for (int q = 0; q < REC_CAP; ++q) {
+                if (q < np && (pc[q] & 15) == 4) {
+                    T l[4];
+                    pick_row(Lx, (pc[q] >> 4) & 3, l);
+                    row_times_block_sub(l, uv[q], aD);
+                }
+            }
+            fl |= nonfinite4(aD);
+            store_row(Xn + ((int64_t)ZL + i) * BB, r, aD);
+            T M[16];
+            gather_block(aD, M);
+            if (!inv4_row(M, r, pD)) fl |= ABILU_FLAG_MODIFIED;
+            store_row(Dn + (int64_t)i * BB, r, pD);
+        }
+        // strictly upper blocks
+#pragma unroll
+        for (int w = 0; w < REC_CAP; ++w) {
+            if (w < nu) {
+#pragma unroll
+                for (int q = 0; q < REC_CAP; ++q) {
+                    if (q < np && (pc[q] & 15) == 5 + w) {
+                        T l[4];
+                        pick_row(Lx, (pc[q] >> 4) & 3, l);
+                        row_times_block_sub(l, uv[q], aU[w]);
+                    }
+                }
+                fl |= nonfinite4(aU[w]);
+                store_row(Xn + ((int64_t)ubase + ub + w) * BB, r, aU[w]);
+                copy_row(aU[w], pU[w]);
+            }
+        }
+        have_prev = true;
+    }
+    if (fl) atomicOr(flags, fl);
+}
+
+// Pipelined form of the record runner, for patterns whose every row holds at most CL strictly lower
+// and CU strictly upper blocks and CP update pairs: row i + 1's operands are fetched while row i is
+// computed, so the chunk's chain of rows overlaps each row's memory round trip with the previous
+// row's arithmetic. The fetched operands are held as loaded (A's blocks in FP64, converted when
+// used) so that no instruction waits for them before the row that uses them. The row computed
+// just before supplies its values from registers. The arithmetic and its order are those of
+// factor_chunk_row.
+template <int CL, int CP>
+struct RecRow {
+    int b0, lb, ub, meta, nl, nu, np;
+    int jl[CL], pc[CP], sp[CP], pk[CP];
+};
+
+template <int CL, int CP>
+__device__ __forceinline__ RecRow<CL, CP> decode_rec(const int4 (&rc)[6]) {
+    const int v[20] = {rec_field<0>(rc),  rec_field<1>(rc),  rec_field<2>(rc),  rec_field<3>(rc),  rec_field<4>(rc),
+                       rec_field<5>(rc),  rec_field<6>(rc),  rec_field<7>(rc),  rec_field<8>(rc),  rec_field<9>(rc),
+                       rec_field<10>(rc), rec_field<11>(rc), rec_field<12>(rc), rec_field<13>(rc), rec_field<14>(rc),
+                       rec_field<15>(rc), rec_field<16>(rc), rec_field<17>(rc), rec_field<18>(rc), rec_field<19>(rc)};
+    RecRow<CL, CP> f;
+    f.b0 = v[0];
+    f.lb = v[1];
+    f.ub = v[2];
+    f.meta = v[3];
+    f.nl = f.meta & 15;
+    f.nu = (f.meta >> 4) & 15;
+    f.np = (f.meta >> 8) & 15;
+#pragma unroll
+    for (int u = 0; u < CL; ++u) f.jl[u] = v[4 + u];
+#pragma unroll
+    for (int q = 0; q < CP; ++q) {
+        f.pc[q] = v[8 + q];
+        f.sp[q] = v[12 + q];
+        f.pk[q] = v[16 + q];
+    }
+    return f;
+}
+
+template <typename T, bool OUT_FROM_A, int CL, int CU, int CP>
+struct RowOps {
+    double aL[CL][4], aD[4], aU[CU][4];           // A's blocks as stored
+    T dj[CL][4];                                  // inverses of the lower neighbours
+    T uv[CP][4];                                  // U_kj from the factor
+    double ua[OUT_FROM_A ? CP : 1][4];            // U_kj from A (first sweep, rows outside the chunk)
+};
+
+template <typename T, bool OUT_FROM_A, int CL, int CU, int CP>
+__device__ __forceinline__ void issue_row(const RecRow<CL, CP> &f, int r, const double *__restrict__ A, const T *XO,
+                                          const T *DO, const T *Xn, const T *Dn,
+                                          RowOps<T, OUT_FROM_A, CL, CU, CP> &o) {
+    // A's blocks, clamped to the row (an unused slot re-reads the diagonal block)
+#pragma unroll
+    for (int u = 0; u < CL; ++u) load_row(A + (int64_t)(f.b0 + min(u, f.nl)) * BB, r, o.aL[u]);
+    load_row(A + (int64_t)(f.b0 + f.nl) * BB, r, o.aD);
+#pragma unroll
+    for (int w = 0; w < CU; ++w) load_row(A + (int64_t)(f.b0 + f.nl + min(w + 1, f.nu)) * BB, r, o.aU[w]);
+#pragma unroll
+    for (int u = 0; u < CL; ++u) {
+        const int src = (f.meta >> (12 + 2 * u)) & 3;
+        if (u < f.nl && src != REC_PREV) load_row((src == REC_OUT ? DO : Dn) + (int64_t)f.jl[u] * BB, r, o.dj[u]);
+    }
+#pragma unroll
+    for (int q = 0; q < CP; ++q) {
+        const int src = (f.pc[q] >> 6) & 3;
+        if (q < f.np && src != REC_PREV) {
+            if constexpr (OUT_FROM_A) {
+                if (src == REC_CHUNK) load_row(Xn + (int64_t)f.sp[q] * BB, r, o.uv[q]);
+                else load_row(A + (int64_t)f.pk[q] * BB, r, o.ua[q]);
+            } else {
+                load_row((src == REC_OUT ? XO : Xn) + (int64_t)f.sp[q] * BB, r, o.uv[q]);
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void to_t(const double (&a)[4], T (&v)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = (T)a[c];
+}
+
+template <typename T, bool OUT_FROM_A, int CL, int CU, int CP>
+__device__ __forceinline__ unsigned compute_row(const RecRow<CL, CP> &f, int i, int r, int ZL, int ubase,
+                                                const RowOps<T, OUT_FROM_A, CL, CU, CP> &o, T (&pD)[4],
+                                                T (&pU)[CU][4], T *Xn, T *Dn) {
+    unsigned fl = 0;
+    T dj[CL][4], uq[CP][4];
+#pragma unroll
+    for (int u = 0; u < CL; ++u) {
+        if (u < f.nl) {
+            if (((f.meta >> (12 + 2 * u)) & 3) != REC_PREV) copy_row(o.dj[u], dj[u]);
+            else copy_row(pD, dj[u]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CP; ++q) {
+        if (q < f.np) {
+            const int src = (f.pc[q] >> 6) & 3;
+            if (src == REC_PREV) pick_row(pU, (f.pc[q] >> 8) & 3, uq[q]);
+            else if constexpr (OUT_FROM_A) {
+                if (src == REC_OUT) to_t(o.ua[q], uq[q]);
+                else copy_row(o.uv[q], uq[q]);
+            } else {
+                copy_row(o.uv[q], uq[q]);
+            }
+        }
+    }
+    // strictly lower blocks in ascending column order, each seeing the ones before it
+    T Lx[CL][4] = {};
+#pragma unroll
+    for (int u = 0; u < CL; ++u) {
+        if (u < f.nl) {
+            T tt[4];
+            to_t(o.aL[u], tt);
+#pragma unroll
+            for (int q = 0; q < CP; ++q) {
+                if (q < f.np && (f.pc[q] & 15) == u) {
+                    T l[4];
+                    pick_row(Lx, (f.pc[q] >> 4) & 3, l);
+                    row_times_block_sub(l, uq[q], tt);
+                }
+            }
+            row_times_block(tt, dj[u], Lx[u]);
+            fl |= nonfinite4(Lx[u]);
+            store_row(Xn + ((int64_t)f.lb + u) * BB, r, Lx[u]);
+        }
+    }
+    // diagonal block and its inverse
+    {
+        T td[4];
+        to_t(o.aD, td);
+#pragma unroll
+        for (int q = 0; q < CP; ++q) {
+            if (q < f.np && (f.pc[q] & 15) == 4) {
+                T l[4];
+                pick_row(Lx, (f.pc[q] >> 4) & 3, l);
+                row_times_block_sub(l, uq[q], td);
+            }
+        }
+        fl |= nonfinite4(td);
+        store_row(Xn + ((int64_t)ZL + i) * BB, r, td);
+        T M[16];
+        gather_block(td, M);
+        if (!inv4_row(M, r, pD)) fl |= ABILU_FLAG_MODIFIED;
+        store_row(Dn + (int64_t)i * BB, r, pD);
+    }
+    // strictly upper blocks
+#pragma unroll
+    for (int w = 0; w < CU; ++w) {
+        if (w < f.nu) {
+            T tt[4];
+            to_t(o.aU[w], tt);
+#pragma unroll
+            for (int q = 0; q < CP; ++q) {
+                if (q < f.np && (f.pc[q] & 15) == 5 + w) {
+                    T l[4];
+                    pick_row(Lx, (f.pc[q] >> 4) & 3, l);
+                    row_times_block_sub(l, uq[q], tt);
+                }
+            }
+            fl |= nonfinite4(tt);
+            store_row(Xn + ((int64_t)ubase + f.ub + w) * BB, r, tt);
+            copy_row(tt, pU[w]);
+        }
+    }
+    return fl;
+}
+
+template <typename T, bool OUT_FROM_A, int CL, int CU, int CP>
+__global__ __launch_bounds__(WG) void k_factor_sweep_chunk_rows_pipe(int n, int ZL, int R, int nch,
+                                                                     const int32_t *__restrict__ rec,
+                                                                     const double *__restrict__ A, const T *XO,
+                                                                     const T *DO, T *Xn, T *Dn, unsigned *flags) {
+    const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
+    if (c >= nch) return;
+    const int r = threadIdx.x & 3;
+    const int c0 = c * R, m = min(n, c0 + R) - c0;
+    const int ubase = ZL + n;
+    T pD[4] = {}, pU[CU][4] = {};   // row i - 1: this lane's rows of Dinv and the upper blocks
+    unsigned fl = 0;
+    int4 rc[6];
+    load_rec(rec, c, nch, 0, rc);
+    RecRow<CL, CP> f0 = decode_rec<CL, CP>(rc), f1 = f0;
+    RowOps<T, OUT_FROM_A, CL, CU, CP> o0, o1;
+    issue_row<T, OUT_FROM_A>(f0, r, A, XO, DO, Xn, Dn, o0);
+    if (m > 1) load_rec(rec, c, nch, 1, rc);
+    // row t from (fc, oc); row t + 1 fetched into (fn, on) first
+    auto step = [&](int t, const RecRow<CL, CP> &fc, const RowOps<T, OUT_FROM_A, CL, CU, CP> &oc,
+                    RecRow<CL, CP> &fn, RowOps<T, OUT_FROM_A, CL, CU, CP> &on) {
+        if (t + 1 < m) {
+            fn = decode_rec<CL, CP>(rc);
+            issue_row<T, OUT_FROM_A>(fn, r, A, XO, DO, Xn, Dn, on);
+            if (t + 2 < m) load_rec(rec, c, nch, t + 2, rc);
+        }
+        fl |= compute_row<T, OUT_FROM_A>(fc, c0 + t, r, ZL, ubase, oc, pD, pU, Xn, Dn);
+    };
+    for (int t = 0; t < m; t += 2) {
+        step(t, f0, o0, f1, o1);
+        if (t + 1 < m) step(t + 1, f1, o1, f0, o0);
+    }
+    if (fl) atomicOr(flags, fl);
 }
 
 // Conversions between the factor layout and CSR order (one quad per block row).
@@ -228,14 +539,29 @@ abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, i
             ProfScope ps(NAME("factor_sweep", nm), s, bytes_sweep(z, sF, false, fromA) + sched);
             if (p->chunk_runner == ABILU_CHUNK_BY_ROWS) {
                 const int g = div_up(p->nchunks, ROWS_PER_WG);
-                if (fromA)
-                    k_factor_sweep_chunk_rows<T, true><<<g, WG, 0, s>>>(
-                        n, ZL, p->chunk_rows, p->nchunks, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow,
-                        p->pair_ptr, p->pkj, p->sik, p->skj, A, XO, DO, Xn, Dn, flags);
-                else
-                    k_factor_sweep_chunk_rows<T, false><<<g, WG, 0, s>>>(
-                        n, ZL, p->chunk_rows, p->nchunks, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow,
-                        p->pair_ptr, p->pkj, p->sik, p->skj, A, XO, DO, Xn, Dn, flags);
+                // the pipelined form in FP32 when every row of the pattern fits its capacities (2 lower
+                // and 2 upper blocks, 2 update pairs; in FP64 two rows' operands exceed the register
+                // file), otherwise the general record runner
+                bool pipelined = false;
+                if constexpr (sizeof(T) == 4) {
+                    if (p->rec_max[0] <= 2 && p->rec_max[1] <= 2 && p->rec_max[2] <= 2) {
+                        if (fromA)
+                            k_factor_sweep_chunk_rows_pipe<T, true, 2, 2, 2><<<g, WG, 0, s>>>(
+                                n, ZL, p->chunk_rows, p->nchunks, p->rec, A, XO, DO, Xn, Dn, flags);
+                        else
+                            k_factor_sweep_chunk_rows_pipe<T, false, 2, 2, 2><<<g, WG, 0, s>>>(
+                                n, ZL, p->chunk_rows, p->nchunks, p->rec, A, XO, DO, Xn, Dn, flags);
+                        pipelined = true;
+                    }
+                }
+#define ABILU_CHUNK_ROWS_ARGS                                                                                \
+    n, ZL, p->chunk_rows, p->nchunks, p->rec, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow, p->pair_ptr, \
+        p->pkj, p->sik, p->skj, A, XO, DO, Xn, Dn, flags
+                if (!pipelined && fromA)
+                    k_factor_sweep_chunk_rows<T, true><<<g, WG, 0, s>>>(ABILU_CHUNK_ROWS_ARGS);
+                else if (!pipelined)
+                    k_factor_sweep_chunk_rows<T, false><<<g, WG, 0, s>>>(ABILU_CHUNK_ROWS_ARGS);
+#undef ABILU_CHUNK_ROWS_ARGS
             } else if (fromA)
                 k_factor_sweep_chunk<T, true><<<p->nchunks, WG, 0, s>>>(
                     n, ZL, p->chunk_rows, p->order[0], p->lvptr[0], p->lvstart[0], p->rowptr, p->colidx, p->diag_pos,

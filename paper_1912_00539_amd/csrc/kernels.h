@@ -3,6 +3,8 @@
 // takes its tile index `blk` explicitly; the arithmetic lives only here.
 #pragma once
 
+#include <type_traits>
+
 #include "abilu_internal.h"
 
 namespace abilu_k {
@@ -662,6 +664,46 @@ __device__ __forceinline__ void factor_sweep_body(int blk,
     const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
     factor_sweep_row<T, L_FROM_A, U_FROM_A>(blk * ROWS_PER_WG + (threadIdx.x >> 2), n, ZL, rowptr, colidx, diag_pos,
                                             lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags);
+}
+
+// ------------------------------------------------------------------ per-row records of the
+// quad-per-chunk runner (layout beside REC_INTS)
+
+// Record of row c * R + t (step-major: the quads of a wavefront, chunks c, c + 1, ..., read
+// adjacent records at every step).
+__device__ __forceinline__ void load_rec(const int32_t *__restrict__ rec, int c, int nch, int t, int4 (&rc)[6]) {
+    const int4 *q = reinterpret_cast<const int4 *>(rec + ((int64_t)t * nch + c) * REC_INTS);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rc[k] = q[k];
+}
+
+template <int K>
+__device__ __forceinline__ int rec_field(const int4 (&rc)[6]) {
+    if constexpr ((K & 3) == 0) return rc[K >> 2].x;
+    else if constexpr ((K & 3) == 1) return rc[K >> 2].y;
+    else if constexpr ((K & 3) == 2) return rc[K >> 2].z;
+    else return rc[K >> 2].w;
+}
+
+// v = rows[k] for a runtime k < N, as a masked blend of the bit patterns: the rows stay in
+// registers (a chain of selects between the rows would be folded into a load at a computed offset,
+// which forces the rows into scratch memory)
+template <typename T, int N>
+__device__ __forceinline__ void pick_row(const T (&rows)[N][4], int k, T (&v)[4]) {
+    using U = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        U x = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) x |= ((U)0 - (U)(k == q)) & __builtin_bit_cast(U, rows[q][c]);
+        v[c] = __builtin_bit_cast(T, x);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void copy_row(const T (&a)[4], T (&b)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = a[c];
 }
 
 }  // namespace abilu_k

@@ -416,6 +416,28 @@ def test_full_size_aniso1000_line_chunk_sync():
     assert st == 0 and res["converged"]
 
 
+def test_full_size_aniso1000_line_runners_agree_f32():
+    """The bench's chunked case (500,000 quads in line order, 16-row chunks, FP32): the quad-per-chunk
+    runner (its pipelined form: every row has at most two lower and two upper blocks and two
+    update pairs) gives the bits of the workgroup-per-chunk runner for three CHUNK_SYNC factor
+    sweeps (the first from A) and for three apply sweep pairs."""
+    c = W.case("aniso1000", order="line")
+    r = np.random.default_rng(9).uniform(-1, 1, 4 * c.n)
+    out = {}
+    for runner in RUNNERS:
+        s = DS(c, "f32", R=16, runner=runner)
+        assert s.set_chunks(16, runner)["runner"] == runner
+        s.factor(3, "chunk_sync")
+        X, D = s.factor_host()
+        rt = torch.from_numpy(r).cuda()
+        zt = torch.zeros_like(rt)
+        s.apply(rt, zt, 3, "chunk_sync")
+        out[runner] = (X, D, zt.cpu().numpy())
+        del s
+    for a, b, what in zip(out["levels"], out["rows"], ("X", "Dinv", "z")):
+        np.testing.assert_array_equal(a, b, err_msg=what)
+
+
 # ------------------------------------------------------------------ orderings + chunked sweeps, end to end
 def test_line_ordering_then_chunked_sweeps():
     """Section 5 with the chunk schedule of Section 3.3: the library finds lines on a boundary-layer
