@@ -322,7 +322,7 @@ __global__ __launch_bounds__(WG) void k_bwd_chunk_rows(int n, int R, int nch, co
     }
 }
 
-// y = A x  (RESID: y = b - A x), double precision, CSR; one quad per block row, four blocks
+// y = A x  (RESID: y = b - A x), double precision, CSR; eight lanes per block row, four blocks
 // loaded per step (clamped: rows always hold at least their diagonal block); desc: workgroups
 // take the rows in descending order
 template <bool RESID>
@@ -535,7 +535,7 @@ bool apply_ends_descending(int nsweeps, abilu_mode mode) {
 abilu_status spmv_impl(const abilu_pattern *p, const double *A, const double *x, double *y, const double *b,
                        bool desc, hipStream_t s) {
     if (p->n == 0) return ABILU_OK;
-    const int grid = div_up(p->n, ROWS_PER_WG);
+    const int grid = div_up(p->n, SPMV_ROWS);
     const Sizes z = sizes(p);
     if (b) {
         ProfScope ps("spmv_resid", s, bytes_spmv(z, true));

@@ -20,6 +20,7 @@ constexpr int rpq() { return sizeof(T) == 8 ? 1 : 2; }
 template <typename T>
 constexpr int rows_per_wg2() { return rpq<T>() * ROWS_PER_WG; }
 constexpr int MAX_RESTART = 256;
+constexpr int SPMV_ROWS = WG / 8;            // SpMV: eight lanes per block row
 
 // status slots (double[8] in the workspace header, copied to the host)
 enum { ST_EST = 0, ST_HN = 1, ST_BETA = 2, ST_NUM = 3, ST_GUARD = 4 };
@@ -203,34 +204,36 @@ __device__ __forceinline__ void spmv_body(int blk, int n, const int32_t *__restr
                                              const int32_t *__restrict__ colidx, const double *__restrict__ A,
                                              const double *__restrict__ x, double *__restrict__ y,
                                              const double *__restrict__ b) {
+    // eight lanes per block row (SPMV_ROWS rows per workgroup): lane l takes row l / 2, columns
+    // 2 (l % 2) and 2 (l % 2) + 1 of every block, so each load instruction covers whole 128-byte
+    // FP64 blocks (a quad per row covers half of each block per instruction and reads each line
+    // in two passes: 4-5% slower on the 4M-cell matrix)
     constexpr int SCH = 4;
-    const int i = blk * ROWS_PER_WG + (threadIdx.x >> 2);
-    const int r = threadIdx.x & 3;
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const int i = blk * SPMV_ROWS + (threadIdx.x >> 3);
+    const int rr = (threadIdx.x >> 1) & 3, h = threadIdx.x & 1;
     if (i >= n) return;
     const int b0 = rowptr[i], b1 = rowptr[i + 1];
     double acc = 0.0;
     for (int e0 = b0; e0 < b1; e0 += SCH) {
         int j[SCH];
-        double a[SCH][4], xv[SCH];
+        d2 a[SCH], xv[SCH];
 #pragma unroll
         for (int u = 0; u < SCH; ++u) {
             const int e = min(e0 + u, b1 - 1);
             j[u] = colidx[e];
-            load_row(A + (int64_t)e * BB, r, a[u]);
+            a[u] = *reinterpret_cast<const d2 *>(A + (int64_t)e * BB + rr * 4 + 2 * h);
         }
 #pragma unroll
-        for (int u = 0; u < SCH; ++u) xv[u] = x[(int64_t)j[u] * 4 + r];
+        for (int u = 0; u < SCH; ++u) xv[u] = *reinterpret_cast<const d2 *>(x + (int64_t)j[u] * 4 + 2 * h);
 #pragma unroll
         for (int u = 0; u < SCH; ++u) {
-            double xj[4];
-            gather_vec(xv[u], xj);
-            // one product tree per block, fused: the accumulator's dependent chain is one add per
-            // block (a chain of four adds per block, the oracle's order, made the SpMV 12% slower)
-            const double c = a[u][0] * xj[0] + a[u][1] * xj[1] + a[u][2] * xj[2] + a[u][3] * xj[3];
+            const double c = a[u].x * xv[u].x + a[u].y * xv[u].y;
             acc += (e0 + u < b1) ? c : 0.0;
         }
     }
-    y[(int64_t)i * 4 + r] = RESID ? b[(int64_t)i * 4 + r] - acc : acc;
+    acc += __shfl_xor(acc, 1, 64);   // the row's other two columns, from the neighbouring lane
+    if (h == 0) y[(int64_t)i * 4 + rr] = RESID ? b[(int64_t)i * 4 + rr] - acc : acc;
 }
 
 __device__ __forceinline__ void mdot_body(int blk, int64_t len, const double *__restrict__ V, int64_t ldv, int q,

@@ -774,7 +774,8 @@ abilu_status admit_queued(abilu_server *s, int64_t cell_budget) {
 }
 
 // ---- per-tick member tables
-enum Shape { SH_ROW64 = 0, SH_APPLY, SH_VEC, SH_COLSQ, SH_ONE, SH_COUNT };   // SH_APPLY: rows_per_wg2<T>() rows
+// SH_APPLY: rows_per_wg2<T>() rows per tile; SH_SPMV: SPMV_ROWS rows per tile
+enum Shape { SH_ROW64 = 0, SH_APPLY, SH_VEC, SH_COLSQ, SH_ONE, SH_SPMV, SH_COUNT };
 
 struct Table {
     const Member *d = nullptr;
@@ -786,6 +787,7 @@ int tiles_of(const Req &r, int shape, State g, abilu_prec prec) {
         case SH_ROW64: return div_up(r.n, ROWS_PER_WG);
         case SH_APPLY: return div_up(r.n, prec == ABILU_F32 ? rows_per_wg2<float>() : rows_per_wg2<double>());
         case SH_VEC: return r.L.nb_vec;
+        case SH_SPMV: return div_up(r.n, SPMV_ROWS);
         case SH_COLSQ: return g == Q_ITER ? r.k + 2 : 1;
         default: return 1;
     }
@@ -901,9 +903,9 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
         ProfScope ps(resid ? "serve_spmv_resid" : "serve_spmv", st,
                      B([&](const Sizes &z, const Req &) { return bytes_spmv(z, resid); }));
         if (resid)
-            kb_spmv<true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), xin, yout, 1);
+            kb_spmv<true><<<L_(SH_SPMV)>>>(A_(SH_SPMV), xin, yout, 1);
         else
-            kb_spmv<false><<<L_(SH_ROW64)>>>(A_(SH_ROW64), xin, yout, spmv_desc ? 1 : 0);
+            kb_spmv<false><<<L_(SH_SPMV)>>>(A_(SH_SPMV), xin, yout, spmv_desc ? 1 : 0);
         CKL();
         return ABILU_OK;
     };
