@@ -801,6 +801,36 @@ def summarize_stats(d, title, command):
     return "\n".join(lines) + "\n"
 
 
+def summarize_trace_segments(d, marker, title, command, seg_titles):
+    """Markdown tables of a rocprofv3 --kernel-trace run (its *kernel_trace.csv) split into segments,
+    each starting at a dispatch of the kernel `marker` (e.g. each workload's pattern build)."""
+    rows = _csv_rows(d, "kernel_trace.csv")
+    if not rows:
+        raise SystemExit(f"no kernel_trace.csv under {d}")
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    starts = [q for q, r in enumerate(rows) if kernel_short_name(r["Kernel_Name"]) == marker]
+    if len(starts) != len(seg_titles):
+        raise SystemExit(f"{len(starts)} segments start with {marker}, {len(seg_titles)} titles given")
+    lines = [f"# rocprofv3 kernel statistics: {title}", "", "Command (run from the repository root on an MI355X machine):",
+             "", "```", command, "```"]
+    for q, st in enumerate(starts):
+        seg = rows[st:starts[q + 1] if q + 1 < len(starts) else len(rows)]
+        acc = {}
+        for r in seg:
+            name = kernel_short_name(r["Kernel_Name"])
+            acc.setdefault(name, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        tot = sum(sum(v) for v in acc.values())
+        lines += ["", f"## {seg_titles[q]}", "", "| kernel | calls | avg us | min us | max us | total ms | % |",
+                  "|---|---:|---:|---:|---:|---:|---:|"]
+        for name, v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+            if sum(v) < 0.001 * tot:
+                continue
+            lines.append(f"| `{name}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
+                         f"{sum(v) / 1e3:.3f} | {100 * sum(v) / tot:.2f} |")
+        lines += ["", f"Segment kernel time {tot / 1e3:.3f} ms (kernels under 0.1% of it left out)."]
+    return "\n".join(lines) + "\n"
+
+
 def summarize_traffic(fetch_dir, write_dir, command):
     """Bytes per launch of the headline step's kernels from two rocprofv3 --pmc runs (FETCH_SIZE,
     then WRITE_SIZE, KiB per dispatch), each scaled by the ratio of the known bytes of the STREAM
@@ -880,12 +910,43 @@ def summarize_serving_traffic(fetch_dir, write_dir, cf, cw, command):
     return "\n".join(md) + "\n"
 
 
+def summarize_launch_traffic(fetch_dir, write_dir, cf, cw, title, command):
+    """Measured bytes per launch (medians over dispatches) of every kernel of a run, split by grid
+    size (one run may cover several workloads), from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE), scaled by the STREAM-copy calibration factors cf, cw. Returns markdown."""
+    import numpy as np
+
+    def per_kernel(d, counter, f):
+        acc = {}
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = (kernel_short_name(r["Kernel_Name"]), int(r.get("Grid_Size", 0) or 0))
+            acc.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0 * f)
+        return acc
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE", cf), per_kernel(write_dir, "WRITE_SIZE", cw)
+    keys = sorted(set(fetch) & set(write), key=lambda k: (k[0], -k[1]))
+    md = [f"# Measured L2-to-memory traffic per launch: {title}", "", "Command (run from the repository root on an MI355X "
+          "machine):", "", "```", command, "```", "",
+          f"Medians over each kernel's dispatches, split by grid size (threads), scaled by the STREAM-copy "
+          f"calibration of the headline traffic measurement ({cf:.3f}, {cw:.3f}).", "",
+          "| kernel | grid | dispatches | fetch MB | write MB | total MB per launch |", "|---|---:|---:|---:|---:|---:|"]
+    for k in keys:
+        f, w = float(np.median(fetch[k])), float(np.median(write[k]))
+        if f + w < 1e6 or not k[0].startswith("k"):
+            continue
+        md.append(f"| `{k[0]}` | {k[1]} | {len(fetch[k])} | {f / 1e6:.1f} | {w / 1e6:.1f} | {(f + w) / 1e6:.1f} |")
+    md += ["", "Library kernels only; launches under 1 MB are left out."]
+    return "\n".join(md) + "\n"
+
+
 STREAM_BYTES = 2 * (2 << 30)   # algorithmic bytes of one stream_reference copy launch (read + write)
 
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-stats", "--summarize-traffic",
-                                             "--summarize-serving-traffic"):
+                                             "--summarize-serving-traffic", "--summarize-launch-traffic",
+                                             "--summarize-trace-segments"):
         return summarize_main(sys.argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1167,10 +1228,18 @@ def summarize_main(argv):
     """bench.py --summarize-stats DIR TITLE COMMAND OUT.md
        bench.py --summarize-traffic FETCH_DIR WRITE_DIR COMMAND OUT_BASENAME  (writes .txt and .md)
        bench.py --summarize-serving-traffic FETCH_DIR WRITE_DIR FETCH_FACTOR WRITE_FACTOR COMMAND OUT.md
+       bench.py --summarize-launch-traffic FETCH_DIR WRITE_DIR FETCH_FACTOR WRITE_FACTOR TITLE COMMAND OUT.md
+       bench.py --summarize-trace-segments DIR MARKER_KERNEL TITLE COMMAND OUT.md SEGMENT_TITLE...
     Turn rocprofv3 output into the summaries kept under profiles/."""
     if argv[0] == "--summarize-stats":
         d, title, command, out = argv[1:5]
         open(out, "w").write(summarize_stats(d, title, command))
+    elif argv[0] == "--summarize-trace-segments":
+        d, marker, title, command, out = argv[1:6]
+        open(out, "w").write(summarize_trace_segments(d, marker, title, command, argv[6:]))
+    elif argv[0] == "--summarize-launch-traffic":
+        fd, wd, cf, cw, title, command, out = argv[1:8]
+        open(out, "w").write(summarize_launch_traffic(fd, wd, float(cf), float(cw), title, command))
     elif argv[0] == "--summarize-serving-traffic":
         fd, wd, cf, cw, command, out = argv[1:7]
         open(out, "w").write(summarize_serving_traffic(fd, wd, float(cf), float(cw), command))
