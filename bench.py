@@ -172,9 +172,8 @@ def cpu_baseline(case, args, gpu=None):
         pass
     return {"value": round(by / (t1 - t0) / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
             "cpu_model": cpu_model, "host_cpus": os.cpu_count(),
-            "sample": f"{reps} x (one synchronous FP64 factor sweep + {args.apply_sweeps} forward/backward sweep pairs "
-                      f"+ one SpMV) on the full {n}-cell matrix ({t1 - t0:.1f} s); bytes from the same algorithmic "
-                      "model as the GPU kernels, in FP64",
+            "sample": f"{reps} x (1 SYNC FP64 factor sweep + {args.apply_sweeps} apply sweep pairs + 1 SpMV) on the "
+                      f"full {n}-cell matrix ({t1 - t0:.1f} s); bytes by the GPU kernels' model, in FP64",
             "seconds": round(t1 - t0, 2), "oracle_check": check,
             "sequential": {"ilu0_ms": round((s1 - s0) * 1e3, 1), "exact_substitution_ms": round((s2 - s1) * 1e3, 1),
                            "threads": 1, "what": "traditional block ILU(0) (row by row) and the exact forward and "
@@ -297,6 +296,31 @@ def serving_bench(args):
         lam_hi = 0.8 * sat["batched_f32"]["solves_per_s"]
         u = W.uniform01(args.serve_seed, 15, np.arange(len(reqs), dtype=np.int64))
         poisson_high = {"rate_per_s": round(lam_hi, 2), "batched_f32": run("batched_f32", np.cumsum(-np.log1p(-u) / lam_hi))}
+    tight = None
+    if args.serve_tight_rtol > 0 and not args.serve_saturation_only and {"batched_f32", "one_at_a_time_f64"} <= set(forms):
+        # the same two forms on the first requests of the stream solved to a tight tolerance, so that
+        # FGMRES(30) runs deep Arnoldi cycles (and restarts) and the FP32 preconditioner is compared
+        # with the FP64 one at an equal final residual on harder solves
+        sub = reqs[:args.serve_tight_requests]
+        tcommon = dict(common, rtol=args.serve_tight_rtol, maxit=3000)
+        tforms = {"batched_f32": L.serve_config(prec="f32", max_active=args.serve_slots, **tcommon),
+                  "one_at_a_time_f64": L.serve_config(prec="f64", max_active=1, **tcommon)}
+        tight = {"rtol": args.serve_tight_rtol, "requests": len(sub)}
+        for name, cfg in tforms.items():
+            srv = L.Server(cfg, pool)
+            res, el = srv.run(sub)
+            stats = srv.stats()
+            srv.destroy()
+            lat = [r["t_done"] - r["t_arrival"] for r in res]
+            tight[name] = {"solves_per_s": round(len(sub) / el, 2), "elapsed_s": round(el, 3), **percentiles(lat),
+                           "converged": sum(1 for r in res if r["converged"] and r["rel_true_residual"] <= args.serve_tight_rtol),
+                           "max_rel_true_residual": max(r["rel_true_residual"] for r in res),
+                           "mean_iters": round(float(np.mean([r["iters"] for r in res])), 2),
+                           "max_iters": int(max(r["iters"] for r in res)),
+                           "solve_path_GBps": round(stats["bytes"] / el / 1e9, 1)}
+            log(f"serving tight {name}: {tight[name]}")
+        tight["speedup_solves_per_s"] = round(tight["batched_f32"]["solves_per_s"] /
+                                              tight["one_at_a_time_f64"]["solves_per_s"], 3)
     cells = [L.abilu_gen_sizes(r)[0] for r in reqs]
     del pool
     torch.cuda.empty_cache()
@@ -314,6 +338,7 @@ def serving_bench(args):
                                  if "batched_f32" in sat and "one_at_a_time_f64" in sat else None),
         "speedup_from_batching_f32": (round(sat["batched_f32"]["solves_per_s"] / sat["one_at_a_time_f32"]["solves_per_s"], 3)
                                       if "batched_f32" in sat and "one_at_a_time_f32" in sat else None),
+        "tight_tolerance": tight,
     }
 
 
@@ -971,6 +996,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-forms", default="batched_f32,one_at_a_time_f64,one_at_a_time_f32")
     ap.add_argument("--serve-saturation-only", action="store_true")
+    ap.add_argument("--serve-tight-rtol", type=float, default=1e-8,
+                    help="also solve the first --serve-tight-requests requests to this tolerance (0: skip)")
+    ap.add_argument("--serve-tight-requests", type=int, default=400)
     ap.add_argument("--serve-profile", action="store_true",
                     help="add a profiled saturation run of the batched form (per-kernel GB/s)")
     ap.add_argument("--warm-steps", type=int, default=12)
@@ -1194,15 +1222,22 @@ def headline(out, detail_path=None):
             "speedup_solves_per_s": sv.get("speedup_solves_per_s"),
             "poisson_rate_per_s": po.get("rate_per_s"),
             "poisson": {k: form(po.get(k), ("p50_ms", "p99_ms")) for k in po if k != "rate_per_s"}}
+        ti = sv.get("tight_tolerance")
+        if ti:
+            h["serving"]["tight"] = {"rtol": ti["rtol"], "requests": ti["requests"],
+                                     "speedup": ti.get("speedup_solves_per_s"),
+                                     **{k: form(ti.get(k), ("solves_per_s", "mean_iters"))
+                                        for k in ("batched_f32", "one_at_a_time_f64")}}
     else:
         h["serving"] = None
     pr = out.get("precision")
     if pr:
-        pair = lambda e: [e.get("rel"), e.get("max_block_rel")] if e else None
+        sig3 = lambda x: float(f"{x:.2e}") if isinstance(x, float) else x
+        pair = lambda e: [sig3(e.get("rel")), sig3(e.get("max_block_rel"))] if e else None
         h["precision"] = {
             "f32_speedup_step": pr.get("f32_speedup_step"),
-            "f32_vs_f64_legend": "[rel Frobenius, max per-block rel] FP32 vs FP64 (= oracle): X, Dinv after 1, 2 SYNC "
-                                 "sweeps; z of one SYNC apply",
+            "f32_vs_f64_legend": "[rel Frobenius, max block rel] FP32 vs FP64 (= oracle): X, Dinv after 1, 2 SYNC "
+                                 "sweeps; z of a SYNC apply",
             "f32_vs_f64": {k: {"X1": pair(v.get("sweeps1", {}).get("X")), "D1": pair(v.get("sweeps1", {}).get("Dinv")),
                                "X2": pair(v.get("sweeps2", {}).get("X")), "D2": pair(v.get("sweeps2", {}).get("Dinv")),
                                "z": pair(v.get("apply"))}

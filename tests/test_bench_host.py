@@ -68,7 +68,10 @@ def _stub_detail():
         "orderings": {"x": ["y" * 100] * 50},
         "serving": {"saturation": {"batched_f32": serve, "one_at_a_time_f64": serve, "one_at_a_time_f32": serve},
                     "poisson": {"rate_per_s": 1096.0, "batched_f32": serve, "one_at_a_time_f64": serve},
-                    "speedup_solves_per_s": 2.16},
+                    "speedup_solves_per_s": 2.16,
+                    "tight_tolerance": {"rtol": 1e-8, "requests": 400, "speedup_solves_per_s": 1.934,
+                                        "batched_f32": dict(serve, max_iters=31),
+                                        "one_at_a_time_f64": dict(serve, max_iters=30)}},
         "warm_start": {"totals": {"cold": {"iters": 24}, "warm": {"iters": 12}}, "steps": steps},
         "factor_convergence": {"summary": {k: {"D": 11085, "fixed_point_sweeps": 37,
                                                "f32_async_E_L": [0.03239, 0.001111, 4.155e-05, 1.88e-06, 7.728e-08],
@@ -105,5 +108,6 @@ def test_headline_line_is_compact_and_parseable(tmp_path, capsys):
     for k in ("value", "unit", "cores", "kind", "sample"):
         assert k in h["cpu_baseline"], k
     assert h["serving"]["saturation"]["batched_f32"]["p99_ms"] == 8.88
+    assert h["serving"]["tight"]["rtol"] == 1e-8 and h["serving"]["tight"]["speedup"] == 1.934
     assert h["precision"]["f32_vs_f64"]["tri2000"]["z"][1] > 0
     assert json.load(open(path)) == out
