@@ -167,7 +167,10 @@ abilu_status abilu_pattern_set_chunks(abilu_pattern *p, int32_t rows_per_chunk, 
  *   ABILU_CHUNK_BY_LEVELS: one workgroup per chunk, the rows of each dependence level in
  *                          parallel (one quad per row), a workgroup barrier between levels;
  *   ABILU_CHUNK_BY_ROWS  : one quad per chunk, the chunk's rows in order, no barrier (the
- *                          worker-per-chunk form; fits chunks whose rows form chains);
+ *                          worker-per-chunk form; fits chunks whose rows form chains). The
+ *                          schedule then also holds a 96-byte record per row (its offsets,
+ *                          columns, update pairs and where each operand comes from), read one
+ *                          row ahead by the sweeps;
  *   ABILU_CHUNK_AUTO     : BY_ROWS when the chunks average fewer than 4 rows per level, else
  *                          BY_LEVELS. */
 typedef enum { ABILU_CHUNK_AUTO = 0, ABILU_CHUNK_BY_LEVELS = 1, ABILU_CHUNK_BY_ROWS = 2 } abilu_chunk_runner;

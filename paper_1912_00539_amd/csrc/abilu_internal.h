@@ -44,7 +44,8 @@ struct abilu_pattern {
     int32_t *lvptr[2] = {nullptr, nullptr};
     int32_t *lvstart[2] = {nullptr, nullptr};
     // per-row records of the quad-per-chunk runner (ABILU_CHUNK_BY_ROWS only): REC_INTS int32 per
-    // row, stored step-major (record of row c * chunk_rows + t at index t * nchunks + c)
+    // row in REC_INTS / 4 planes of int4, each step-major (row c * chunk_rows + t at index
+    // t * nchunks + c); then 4 ints of per-pattern maxima
     int32_t *rec = nullptr;
     int32_t rec_max[3] = {0, 0, 0};   // largest strictly lower / strictly upper / pair count of a row
     // dependency analysis (abilu_pattern_depth): depth D and the lower/upper level counts, -1 until

@@ -197,10 +197,6 @@ __global__ __launch_bounds__(WG) void k_bwd_chunk(int n, int R, const int32_t *_
 // computed just before from a register. Each row's operands are located by its record (read one
 // row ahead) and fetched together; rows with more than REC_CAP blocks in the part take the general
 // row code. The arithmetic and its order are those of fwd_chunk_row / bwd_chunk_row.
-__device__ __forceinline__ int4 rec_quad(const int32_t *__restrict__ rec, int c, int nch, int t, int k) {
-    return reinterpret_cast<const int4 *>(rec + ((int64_t)t * nch + c) * REC_INTS)[k];
-}
-
 template <typename T, bool ZERO_OUT>
 __global__ __launch_bounds__(WG) void k_fwd_chunk_rows(int n, int R, int nch, const int32_t *__restrict__ rec,
                                                        const int32_t *__restrict__ lrow,
@@ -212,15 +208,15 @@ __global__ __launch_bounds__(WG) void k_fwd_chunk_rows(int n, int R, int nch, co
     const int c0 = c * R, m = min(n, c0 + R) - c0;
     T py = T(0);               // y of row i - 1 (this lane's element)
     bool have_prev = false;
-    int4 h = rec_quad(rec, c, nch, 0, 0), cols = rec_quad(rec, c, nch, 0, 1);
+    int4 h = rec_quad(rec, R, c, nch, 0, 0), cols = rec_quad(rec, R, c, nch, 0, 1);
     for (int t = 0; t < m; ++t) {
         const int i = c0 + t;
         const int lb = h.y, meta = h.w, nl = meta & 15;
         const int jl[REC_CAP] = {cols.x, cols.y, cols.z, cols.w};
         if (nl > REC_CAP) {
             if (t + 1 < m) {
-                h = rec_quad(rec, c, nch, t + 1, 0);
-                cols = rec_quad(rec, c, nch, t + 1, 1);
+                h = rec_quad(rec, R, c, nch, t + 1, 0);
+                cols = rec_quad(rec, R, c, nch, t + 1, 1);
             }
             fwd_chunk_row<T, ZERO_OUT>(i, c0, lrow, lcol, Lb, rhs, yo, yn);
             have_prev = false;
@@ -242,8 +238,8 @@ __global__ __launch_bounds__(WG) void k_fwd_chunk_rows(int n, int R, int nch, co
             }
         }
         if (t + 1 < m) {
-            h = rec_quad(rec, c, nch, t + 1, 0);
-            cols = rec_quad(rec, c, nch, t + 1, 1);
+            h = rec_quad(rec, R, c, nch, t + 1, 0);
+            cols = rec_quad(rec, R, c, nch, t + 1, 1);
         }
 #pragma unroll
         for (int u = 0; u < REC_CAP; ++u) {
@@ -271,15 +267,15 @@ __global__ __launch_bounds__(WG) void k_bwd_chunk_rows(int n, int R, int nch, co
     const int c0 = c * R, c1 = min(n, c0 + R), m = c1 - c0;
     T pz = T(0);               // z of row i + 1 (this lane's element)
     bool have_prev = false;
-    int4 h = rec_quad(rec, c, nch, m - 1, 0), cols = rec_quad(rec, c, nch, m - 1, 5);
+    int4 h = rec_quad(rec, R, c, nch, m - 1, 0), cols = rec_quad(rec, R, c, nch, m - 1, 5);
     for (int t = m - 1; t >= 0; --t) {
         const int i = c0 + t;
         const int ub = h.z, meta = h.w, nu = (meta >> 4) & 15;
         const int ju[REC_CAP] = {cols.x, cols.y, cols.z, cols.w};
         if (nu > REC_CAP) {
             if (t > 0) {
-                h = rec_quad(rec, c, nch, t - 1, 0);
-                cols = rec_quad(rec, c, nch, t - 1, 5);
+                h = rec_quad(rec, R, c, nch, t - 1, 0);
+                cols = rec_quad(rec, R, c, nch, t - 1, 5);
             }
             bwd_chunk_row<T, ZN, ZERO_OUT>(i, c1, urow, ucol, Ub, Dinv, y, zo, zn);
             have_prev = false;
@@ -302,8 +298,8 @@ __global__ __launch_bounds__(WG) void k_bwd_chunk_rows(int n, int R, int nch, co
         }
         load_row(Dinv + (int64_t)i * BB, r, dr);
         if (t > 0) {
-            h = rec_quad(rec, c, nch, t - 1, 0);
-            cols = rec_quad(rec, c, nch, t - 1, 5);
+            h = rec_quad(rec, R, c, nch, t - 1, 0);
+            cols = rec_quad(rec, R, c, nch, t - 1, 5);
         }
 #pragma unroll
         for (int w = 0; w < REC_CAP; ++w) {
@@ -320,6 +316,173 @@ __global__ __launch_bounds__(WG) void k_bwd_chunk_rows(int n, int R, int nch, co
         pz = z;
         have_prev = true;
     }
+}
+
+// Chunks of at most SHORT_CHUNK rows whose rows hold at most REC_CAP blocks in the part swept:
+// the quad reads all of its chunk's records at once (lane r those of steps r, r + 4, r + 8,
+// r + 12, broadcast by DPP when their step comes), fully unrolls the chunk and fetches the
+// operands of step s + LA while it computes step s, so LA memory round trips overlap. Operands
+// from other rows of the chunk (not the one computed just before) are read when the step is
+// computed, after their stores. Same arithmetic, in the same order, as fwd_chunk_row /
+// bwd_chunk_row.
+constexpr int SHORT_CHUNK = 16;
+constexpr int LOOKAHEAD = 2;
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <int L>
+__device__ __forceinline__ int qbi(int v) { return __builtin_amdgcn_update_dpp(0, v, L * 0x55, 0xF, 0xF, false); }
+
+template <int L>
+__device__ __forceinline__ int4 qbi4(int4 v) { return make_int4(qbi<L>(v.x), qbi<L>(v.y), qbi<L>(v.z), qbi<L>(v.w)); }
+
+// records k = 0 (fields 0-3) and k = K1 of the chunk's steps r, r + 4, r + 8, r + 12 (row of step s:
+// c0 + s forward, c0 + m - 1 - s backward; steps past the chunk's rows read its last step's record)
+template <bool DESC, int K1>
+__device__ __forceinline__ void load_chunk_records(const int32_t *__restrict__ rec, int R, int c, int nch, int m, int r,
+                                                   int4 (&h)[4], int4 (&x)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int s = min(r + 4 * k, m - 1);
+        const int t = DESC ? m - 1 - s : s;
+        h[k] = rec_quad(rec, R, c, nch, t, 0);
+        x[k] = rec_quad(rec, R, c, nch, t, K1);
+    }
+}
+
+template <typename T, bool ZERO_OUT>
+__global__ __launch_bounds__(WG) void k_fwd_chunk_short(int n, int R, int nch, const int32_t *__restrict__ rec,
+                                                        const T *__restrict__ Lb, const double *__restrict__ rhs,
+                                                        const T *yo, T *yn) {
+    const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
+    if (c >= nch) return;
+    const int r = threadIdx.x & 3;
+    const int c0 = c * R, m = min(n, c0 + R) - c0;
+    int4 hr[4], cr[4];
+    load_chunk_records<false, 1>(rec, R, c, nch, m, r, hr, cr);
+    struct Ops {
+        int meta, jl[REC_CAP];
+        double b;
+        T l[REC_CAP][4];
+        T yv[REC_CAP];
+    } ring[LOOKAHEAD + 1];
+    T py = T(0);   // y of the row computed just before (this lane's element)
+    auto issue = [&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+        Ops &o = ring[S % (LOOKAHEAD + 1)];
+        const int4 h = qbi4<S % 4>(hr[S / 4]), x = qbi4<S % 4>(cr[S / 4]);
+        o.meta = h.w;
+        o.jl[0] = x.x; o.jl[1] = x.y; o.jl[2] = x.z; o.jl[3] = x.w;
+        if (S >= m) return;
+        const int i = c0 + S, nl = o.meta & 15;
+        o.b = rhs[(int64_t)i * 4 + r];
+#pragma unroll
+        for (int u = 0; u < REC_CAP; ++u)
+            if (u < nl) load_row(Lb + (int64_t)(h.y + u) * BB, r, o.l[u]);
+#pragma unroll
+        for (int u = 0; u < REC_CAP; ++u) {
+            T v = T(0);
+            if (u < nl && ((o.meta >> (12 + 2 * u)) & 3) == REC_OUT && !ZERO_OUT) v = yo[(int64_t)o.jl[u] * 4 + r];
+            o.yv[u] = v;
+        }
+    };
+    static_for<0, LOOKAHEAD>(issue);
+    static_for<0, SHORT_CHUNK>([&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+        if constexpr (S + LOOKAHEAD < SHORT_CHUNK) issue(std::integral_constant<int, S + LOOKAHEAD>{});
+        if (S < m) {
+            const Ops &o = ring[S % (LOOKAHEAD + 1)];
+            const int nl = o.meta & 15;
+            T acc = (T)o.b;
+#pragma unroll
+            for (int u = 0; u < REC_CAP; ++u) {
+                if (u < nl) {
+                    const int src = (o.meta >> (12 + 2 * u)) & 3;
+                    T yv = o.yv[u];
+                    if (src == REC_PREV) yv = py;
+                    else if (src == REC_CHUNK) yv = yn[(int64_t)o.jl[u] * 4 + r];
+                    T yj[4];
+                    gather_vec(yv, yj);
+                    acc -= dot4(o.l[u][0], yj[0], o.l[u][1], yj[1], o.l[u][2], yj[2], o.l[u][3], yj[3]);
+                }
+            }
+            yn[(int64_t)(c0 + S) * 4 + r] = acc;
+            py = acc;
+        }
+    });
+}
+
+template <typename T, typename ZN, bool ZERO_OUT>
+__global__ __launch_bounds__(WG) void k_bwd_chunk_short(int n, int R, int nch, const int32_t *__restrict__ rec,
+                                                        const T *__restrict__ Ub, const T *__restrict__ Dinv,
+                                                        const T *__restrict__ y, const T *zo, ZN *zn) {
+    const int c = blockIdx.x * ROWS_PER_WG + (threadIdx.x >> 2);
+    if (c >= nch) return;
+    const int r = threadIdx.x & 3;
+    const int c0 = c * R, m = min(n, c0 + R) - c0;
+    int4 hr[4], cr[4];
+    load_chunk_records<true, 5>(rec, R, c, nch, m, r, hr, cr);
+    struct Ops {
+        int meta, ju[REC_CAP];
+        T yi;
+        T u[REC_CAP][4];
+        T dr[4];
+        T zv[REC_CAP];
+    } ring[LOOKAHEAD + 1];
+    T pz = T(0);   // z of the row computed just before (this lane's element)
+    auto issue = [&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+        Ops &o = ring[S % (LOOKAHEAD + 1)];
+        const int4 h = qbi4<S % 4>(hr[S / 4]), x = qbi4<S % 4>(cr[S / 4]);
+        o.meta = h.w;
+        o.ju[0] = x.x; o.ju[1] = x.y; o.ju[2] = x.z; o.ju[3] = x.w;
+        if (S >= m) return;
+        const int i = c0 + m - 1 - S, nu = (o.meta >> 4) & 15;
+        o.yi = y[(int64_t)i * 4 + r];
+#pragma unroll
+        for (int w = 0; w < REC_CAP; ++w)
+            if (w < nu) load_row(Ub + (int64_t)(h.z + w) * BB, r, o.u[w]);
+        load_row(Dinv + (int64_t)i * BB, r, o.dr);
+#pragma unroll
+        for (int w = 0; w < REC_CAP; ++w) {
+            T v = T(0);
+            if (w < nu && ((o.meta >> (20 + 2 * w)) & 3) == REC_OUT && !ZERO_OUT) v = zo[(int64_t)o.ju[w] * 4 + r];
+            o.zv[w] = v;
+        }
+    };
+    static_for<0, LOOKAHEAD>(issue);
+    static_for<0, SHORT_CHUNK>([&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+        if constexpr (S + LOOKAHEAD < SHORT_CHUNK) issue(std::integral_constant<int, S + LOOKAHEAD>{});
+        if (S < m) {
+            const Ops &o = ring[S % (LOOKAHEAD + 1)];
+            const int i = c0 + m - 1 - S, nu = (o.meta >> 4) & 15;
+            T acc = o.yi;
+#pragma unroll
+            for (int w = 0; w < REC_CAP; ++w) {
+                if (w < nu) {
+                    const int src = (o.meta >> (20 + 2 * w)) & 3;
+                    T zv = o.zv[w];
+                    if (src == REC_PREV) zv = pz;
+                    else if (src == REC_CHUNK) zv = (T)zn[(int64_t)o.ju[w] * 4 + r];
+                    T zj[4];
+                    gather_vec(zv, zj);
+                    acc -= dot4(o.u[w][0], zj[0], o.u[w][1], zj[1], o.u[w][2], zj[2], o.u[w][3], zj[3]);
+                }
+            }
+            T a[4];
+            gather_vec(acc, a);
+            const T z = dot4(o.dr[0], a[0], o.dr[1], a[1], o.dr[2], a[2], o.dr[3], a[3]);
+            zn[(int64_t)i * 4 + r] = (ZN)z;
+            pz = z;
+        }
+    });
 }
 
 // y = A x  (RESID: y = b - A x), double precision, CSR; eight lanes per block row, four blocks
@@ -403,8 +566,14 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
         const bool by_rows = p->chunk_runner == ABILU_CHUNK_BY_ROWS;
         const int g = by_rows ? div_up(nch, ROWS_PER_WG) : nch;
         // yo == nullptr: first sweep (earlier rows contribute their initial value 0)
+        // chunks of at most SHORT_CHUNK rows whose rows all fit a record: the unrolled runner
+        const bool short_fwd = by_rows && R <= SHORT_CHUNK && p->rec_max[0] <= REC_CAP;
+        const bool short_bwd = by_rows && R <= SHORT_CHUNK && p->rec_max[1] <= REC_CAP;
         auto fwd = [&](const T *yo, T *yn) {
-            if (by_rows) {
+            if (short_fwd) {
+                if (!yo) k_fwd_chunk_short<T, true><<<g, WG, 0, s>>>(n, R, nch, p->rec, Lb, r, yo, yn);
+                else k_fwd_chunk_short<T, false><<<g, WG, 0, s>>>(n, R, nch, p->rec, Lb, r, yo, yn);
+            } else if (by_rows) {
                 if (!yo) k_fwd_chunk_rows<T, true><<<g, WG, 0, s>>>(n, R, nch, p->rec, lrow, lcol, Lb, r, yo, yn);
                 else k_fwd_chunk_rows<T, false><<<g, WG, 0, s>>>(n, R, nch, p->rec, lrow, lcol, Lb, r, yo, yn);
             } else {
@@ -414,7 +583,10 @@ abilu_status apply_t(const abilu_pattern *p, const T *LU, const T *Dinv, const d
         };
         auto bwd = [&](const T *y, const T *zo, auto *zn) {
             using ZN = std::remove_pointer_t<decltype(zn)>;
-            if (by_rows) {
+            if (short_bwd) {
+                if (!zo) k_bwd_chunk_short<T, ZN, true><<<g, WG, 0, s>>>(n, R, nch, p->rec, Ub, Dinv, y, zo, zn);
+                else k_bwd_chunk_short<T, ZN, false><<<g, WG, 0, s>>>(n, R, nch, p->rec, Ub, Dinv, y, zo, zn);
+            } else if (by_rows) {
                 if (!zo) k_bwd_chunk_rows<T, ZN, true><<<g, WG, 0, s>>>(n, R, nch, p->rec, urow, ucol, Ub, Dinv, y, zo, zn);
                 else k_bwd_chunk_rows<T, ZN, false><<<g, WG, 0, s>>>(n, R, nch, p->rec, urow, ucol, Ub, Dinv, y, zo, zn);
             } else {

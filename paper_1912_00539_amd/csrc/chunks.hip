@@ -75,38 +75,38 @@ __global__ __launch_bounds__(256) void k_chunk_order(int n, int R, const int32_t
     if (threadIdx.x == 0) lvstart[b + nl] = c1;
 }
 
-// One thread per row: the row's record for the quad-per-chunk runner (layout beside REC_INTS).
-__global__ void k_chunk_records(int n, int R, int nch, int ZL, const int32_t *__restrict__ rowptr,
-                                const int32_t *__restrict__ colidx, const int32_t *__restrict__ diag_pos,
-                                const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
-                                const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ sik,
-                                const int32_t *__restrict__ skj, const int32_t *__restrict__ pkj,
-                                int32_t *__restrict__ rec, int *__restrict__ maxima) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = i / R, t = i - c * R, c0 = c * R, c1 = min(n, c0 + R);
+// The record of row i (layout beside REC_INTS), written to `out`; returns the row's counts of
+// strictly lower and upper blocks and update pairs.
+__device__ void chunk_record(int i, int n, int R, int ZL, const int32_t *__restrict__ rowptr,
+                             const int32_t *__restrict__ colidx, const int32_t *__restrict__ diag_pos,
+                             const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+                             const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ sik,
+                             const int32_t *__restrict__ skj, const int32_t *__restrict__ pkj,
+                             int32_t *__restrict__ rec, int64_t idx, int64_t nr, int (&counts)[3]) {
+    // field k of this record: component k % 4 of entry idx of plane k / 4
+    auto put = [&](int k, int v) { rec[((int64_t)(k >> 2) * nr + idx) * 4 + (k & 3)] = v; };
+    const int c0 = (i / R) * R, c1 = min(n, c0 + R);
     const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
     const int nl = d - b0, nu = b1 - d - 1;
     const int p0 = pair_ptr[b0], np = pair_ptr[b1] - p0;
-    int v[REC_INTS];
-    for (int k = 0; k < REC_INTS; ++k) v[k] = 0;
-    v[0] = b0;
-    v[1] = lrow[i];
-    v[2] = urow[i];
+    for (int k = 0; k < REC_INTS; ++k) put(k, 0);
+    put(0, b0);
+    put(1, lrow[i]);
+    put(2, urow[i]);
     int meta = min(nl, 15) | (min(nu, 15) << 4) | (min(np, 15) << 8);
     for (int u = 0; u < min(nl, REC_CAP); ++u) {
         const int j = colidx[b0 + u];
         const int src = j < c0 ? REC_OUT : (j == i - 1 ? REC_PREV : REC_CHUNK);
         meta |= src << (12 + 2 * u);
-        v[4 + u] = j;
+        put(4 + u, j);
     }
     for (int w = 0; w < min(nu, REC_CAP); ++w) {
         const int j = colidx[d + 1 + w];
         const int src = j >= c1 ? REC_OUT : (j == i + 1 ? REC_PREV : REC_CHUNK);
         meta |= src << (20 + 2 * w);
-        v[20 + w] = j;
+        put(20 + w, j);
     }
-    v[3] = meta;
+    put(3, meta);
     // U_kj at factor-layout position s belongs to a row of the chunk when s >= ubound, to row i - 1
     // when s lies in that row's upper part
     const int ubase = ZL + n;
@@ -128,15 +128,36 @@ __global__ void k_chunk_records(int n, int R, int nch, int ZL, const int32_t *__
                 o = (sp - prev0) & 3;
             }
         }
-        v[8 + q] = (tgt & 15) | ((lord & 3) << 4) | (src << 6) | (o << 8);
-        v[12 + q] = sp;
-        v[16 + q] = pkj[pq];
+        put(8 + q, (tgt & 15) | ((lord & 3) << 4) | (src << 6) | (o << 8));
+        put(12 + q, sp);
+        put(16 + q, pkj[pq]);
     }
-    int32_t *out = rec + ((int64_t)t * nch + c) * REC_INTS;
-    for (int k = 0; k < REC_INTS; ++k) out[k] = v[k];
-    atomicMax(&maxima[0], nl);
-    atomicMax(&maxima[1], nu);
-    atomicMax(&maxima[2], np);
+    counts[0] = nl;
+    counts[1] = nu;
+    counts[2] = np;
+}
+
+// One thread per row: the records (planes of int4, each step-major: row c * R + t at index
+// t * nch + c), and the largest counts of a row (one atomic per wavefront).
+__global__ void k_chunk_records(int n, int R, int nch, int ZL, const int32_t *__restrict__ rowptr,
+                                const int32_t *__restrict__ colidx, const int32_t *__restrict__ diag_pos,
+                                const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
+                                const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ sik,
+                                const int32_t *__restrict__ skj, const int32_t *__restrict__ pkj,
+                                int32_t *__restrict__ rec, int *__restrict__ maxima) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int mx[3] = {0, 0, 0};
+    if (i < n) {
+        const int c = i / R, t = i - c * R;
+        chunk_record(i, n, R, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, sik, skj, pkj, rec,
+                     (int64_t)t * nch + c, (int64_t)R * nch, mx);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx[q] = max(mx[q], __shfl_xor(mx[q], o, 64));
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 3; ++q) atomicMax(&maxima[q], mx[q]);
 }
 
 }  // namespace

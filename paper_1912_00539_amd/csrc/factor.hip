@@ -124,7 +124,7 @@ __global__ __launch_bounds__(WG) void k_factor_sweep_chunk_rows(
     bool have_prev = false;
     unsigned fl = 0;
     int4 rc[6];
-    load_rec(rec, c, nch, 0, rc);
+    load_rec(rec, R, c, nch, 0, rc);
     for (int t = 0; t < m; ++t) {
         const int i = c0 + t;
         const int b0 = rec_field<0>(rc), lb = rec_field<1>(rc), ub = rec_field<2>(rc), meta = rec_field<3>(rc);
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(WG) void k_factor_sweep_chunk_rows(
         const int sp[REC_CAP] = {rec_field<12>(rc), rec_field<13>(rc), rec_field<14>(rc), rec_field<15>(rc)};
         const int pk[REC_CAP] = {rec_field<16>(rc), rec_field<17>(rc), rec_field<18>(rc), rec_field<19>(rc)};
         if (nl > REC_CAP || nu > REC_CAP || np > REC_CAP) {
-            if (t + 1 < m) load_rec(rec, c, nch, t + 1, rc);
+            if (t + 1 < m) load_rec(rec, R, c, nch, t + 1, rc);
             factor_chunk_row<T, OUT_FROM_A, true>(i, c0, ubound, n, ZL, rowptr, colidx, diag_pos, lrow, urow,
                                                   pair_ptr, pkj, sik, skj, A, XO, DO, Xn, Dn, flags);
             have_prev = false;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(WG) void k_factor_sweep_chunk_rows(
                 else load_row(XO + (int64_t)sp[q] * BB, r, uv[q]);
             }
         }
-        if (t + 1 < m) load_rec(rec, c, nch, t + 1, rc);   // the next row's record, behind this row's loads
+        if (t + 1 < m) load_rec(rec, R, c, nch, t + 1, rc);   // the next row's record, behind this row's loads
         // strictly lower blocks in ascending column order, each seeing the ones before it
         T Lx[REC_CAP][4] = {};
 #pragma unroll
@@ -408,18 +408,18 @@ __global__ __launch_bounds__(WG) void k_factor_sweep_chunk_rows_pipe(int n, int 
     T pD[4] = {}, pU[CU][4] = {};   // row i - 1: this lane's rows of Dinv and the upper blocks
     unsigned fl = 0;
     int4 rc[6];
-    load_rec(rec, c, nch, 0, rc);
+    load_rec(rec, R, c, nch, 0, rc);
     RecRow<CL, CP> f0 = decode_rec<CL, CP>(rc), f1 = f0;
     RowOps<T, OUT_FROM_A, CL, CU, CP> o0, o1;
     issue_row<T, OUT_FROM_A>(f0, r, A, XO, DO, Xn, Dn, o0);
-    if (m > 1) load_rec(rec, c, nch, 1, rc);
+    if (m > 1) load_rec(rec, R, c, nch, 1, rc);
     // row t from (fc, oc); row t + 1 fetched into (fn, on) first
     auto step = [&](int t, const RecRow<CL, CP> &fc, const RowOps<T, OUT_FROM_A, CL, CU, CP> &oc,
                     RecRow<CL, CP> &fn, RowOps<T, OUT_FROM_A, CL, CU, CP> &on) {
         if (t + 1 < m) {
             fn = decode_rec<CL, CP>(rc);
             issue_row<T, OUT_FROM_A>(fn, r, A, XO, DO, Xn, Dn, on);
-            if (t + 2 < m) load_rec(rec, c, nch, t + 2, rc);
+            if (t + 2 < m) load_rec(rec, R, c, nch, t + 2, rc);
         }
         fl |= compute_row<T, OUT_FROM_A>(fc, c0 + t, r, ZL, ubase, oc, pD, pU, Xn, Dn);
     };

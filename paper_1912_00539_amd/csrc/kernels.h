@@ -672,12 +672,17 @@ __device__ __forceinline__ void factor_sweep_body(int blk,
 // ------------------------------------------------------------------ per-row records of the
 // quad-per-chunk runner (layout beside REC_INTS)
 
-// Record of row c * R + t (step-major: the quads of a wavefront, chunks c, c + 1, ..., read
-// adjacent records at every step).
-__device__ __forceinline__ void load_rec(const int32_t *__restrict__ rec, int c, int nch, int t, int4 (&rc)[6]) {
-    const int4 *q = reinterpret_cast<const int4 *>(rec + ((int64_t)t * nch + c) * REC_INTS);
+// Records are stored as REC_INTS / 4 planes of int4 (plane k holds fields 4k .. 4k + 3 of every
+// record), each plane step-major: the record of row c * R + t at index t * nch + c. The quads of a
+// wavefront run chunks c, c + 1, ... in lock step, so a load of one plane reads adjacent 16-byte
+// pieces, and a sweep that needs only some fields reads only their planes.
+__device__ __forceinline__ int4 rec_quad(const int32_t *__restrict__ rec, int R, int c, int nch, int t, int k) {
+    return reinterpret_cast<const int4 *>(rec)[(int64_t)k * R * nch + (int64_t)t * nch + c];
+}
+
+__device__ __forceinline__ void load_rec(const int32_t *__restrict__ rec, int R, int c, int nch, int t, int4 (&rc)[6]) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) rc[k] = q[k];
+    for (int k = 0; k < 6; ++k) rc[k] = rec_quad(rec, R, c, nch, t, k);
 }
 
 template <int K>
