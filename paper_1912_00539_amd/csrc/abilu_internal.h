@@ -29,6 +29,7 @@ struct abilu_pattern {
     int32_t *lcol = nullptr;      // device [ZL+1] columns of the lower part (one padding entry)
     int32_t *ucol = nullptr;      // device [ZU+1] columns of the upper part
     double *pinned = nullptr;     // host pinned, 64 doubles, for blocking scalar reads
+    bool symmetric = false;       // (i,j) in S_B implies (j,i) in S_B
     int device = 0;
     // chunk schedule (abilu_pattern_set_chunks): chunks of chunk_rows consecutive rows; per chunk,
     // the rows grouped by level in the chunk's lower (forward, factor) and upper (backward)
@@ -143,6 +144,12 @@ inline double bytes_sweep(const Sizes &z, double sF, bool l_from_a, bool u_from_
     const double xr = (l_from_a ? 0.0 : 16 * sF * m) + (u_from_a ? 0.0 : 16 * sF * m);
     return 4 * (z.N + 1) + 12 * z.N + 4 * z.ZL + 16 * z.N + 8 * z.P + 128 * z.Z + xr + 16 * sF * z.N +
            16 * sF * z.Z + 16 * sF * z.N;
+}
+
+// first sweep from A forming the initial inverses itself: as a sweep with U (and, in SYNC, L)
+// from A, without the Dinv read (the diagonal blocks it inverts are elements of A, counted once)
+inline double bytes_sweep_from_a(const Sizes &z, double sF, bool l_from_a) {
+    return bytes_sweep(z, sF, l_from_a, true) - 16 * sF * z.N;
 }
 
 // SpMV: rowptr, colidx, A (f64), x gathered once, y written (+ b read when RESID)

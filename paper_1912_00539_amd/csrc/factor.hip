@@ -49,15 +49,16 @@ __global__ __launch_bounds__(WG) void k_factor_init(int n, int ZL, const int32_t
                                           D0, flags);
 }
 
-// One sweep.
-template <typename T, bool L_FROM_A, bool U_FROM_A>
+// One sweep (D_FROM_A: the first sweep from A, forming the initial inverses itself; sym: the
+// pattern is structurally symmetric).
+template <typename T, bool L_FROM_A, bool U_FROM_A, bool D_FROM_A = false>
 __global__ __launch_bounds__(WG) void k_factor_sweep(
     int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
     const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
     const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
-    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
-    factor_sweep_body<T, L_FROM_A, U_FROM_A>(blockIdx.x, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags);
+    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags, int sym) {
+    factor_sweep_body<T, L_FROM_A, U_FROM_A, D_FROM_A>(blockIdx.x, n, ZL, rowptr, colidx, diag_pos, lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags, sym != 0);
 }
 
 // The asynchronous sweep with a single worker: one quad over the rows in ascending order, in
@@ -456,12 +457,12 @@ const char *tname<float>() { return "f32"; }
 template <>
 const char *tname<double>() { return "f64"; }
 
-template <typename T, bool LA, bool UA>
+template <typename T, bool LA, bool UA, bool DA = false>
 void launch_sweep(const abilu_pattern *p, int grid, hipStream_t s, const double *A, const T *XL, const T *XU,
                   const T *Dp, T *Xn, T *Dn, unsigned *flags) {
-    k_factor_sweep<T, LA, UA><<<grid, WG, 0, s>>>(p->n, (int)p->nnzb_lower, p->rowptr, p->colidx, p->diag_pos,
-                                                   p->lrow, p->urow, p->pair_ptr, p->pik, p->pkj, p->sik, p->skj, A,
-                                                   XL, XU, Dp, Xn, Dn, flags);
+    k_factor_sweep<T, LA, UA, DA><<<grid, WG, 0, s>>>(p->n, (int)p->nnzb_lower, p->rowptr, p->colidx, p->diag_pos,
+                                                       p->lrow, p->urow, p->pair_ptr, p->pik, p->pkj, p->sik, p->skj,
+                                                       A, XL, XU, Dp, Xn, Dn, flags, p->symmetric ? 1 : 0);
 }
 
 template <typename T>
@@ -612,9 +613,9 @@ abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, i
     if (mode == ABILU_ASYNC) {
         int q0 = 0;
         if (init == ABILU_INIT_FROM_A) {
-            if ((st = init_dinv_A(Dinv)) != ABILU_OK) return st;
-            ProfScope ps(NAME("factor_sweep", "_async_fromA"), s, bytes_sweep(z, sF, false, true));
-            launch_sweep<T, false, true>(p, grid, s, A, LU, (const T *)nullptr, Dinv, LU, Dinv, flags);
+            // the first sweep forms the initial inverses inv(A_jj) itself (no initialisation pass)
+            ProfScope ps(NAME("factor_sweep", "_async_fromA"), s, bytes_sweep_from_a(z, sF, false));
+            launch_sweep<T, false, true, true>(p, grid, s, A, LU, (const T *)nullptr, Dinv, LU, Dinv, flags);
             LAUNCHED();
             q0 = 1;
         } else if ((st = init_dinv_X(LU, Dinv)) != ABILU_OK) {
@@ -633,10 +634,10 @@ abilu_status factor_t(const abilu_pattern *p, const double *A, T *LU, T *Dinv, i
     auto outD = [&](int q) { return ((nsw - q) % 2 == 0) ? Dinv : D1; };
     T *D0 = outD(0);
     if (init == ABILU_INIT_FROM_A) {
-        if ((st = init_dinv_A(D0)) != ABILU_OK) return st;
-        ProfScope ps(NAME("factor_sweep", "_sync_fromA"), s, bytes_sweep(z, sF, true, true));
-        launch_sweep<T, true, true>(p, grid, s, A, (const T *)nullptr, (const T *)nullptr, D0, outX(1), outD(1),
-                                    flags);
+        // the first sweep forms the initial inverses inv(A_jj) itself (no initialisation pass)
+        ProfScope ps(NAME("factor_sweep", "_sync_fromA"), s, bytes_sweep_from_a(z, sF, true));
+        launch_sweep<T, true, true, true>(p, grid, s, A, (const T *)nullptr, (const T *)nullptr, D0, outX(1),
+                                          outD(1), flags);
         LAUNCHED();
     } else {
         // warm start: X0 = d_LU. Sweep 1 must not write where it reads.

@@ -451,13 +451,19 @@ __device__ __forceinline__ void factor_init_body(int blk, int n, int ZL, const i
 // contains the column of the block just before it in the same chunk reads that block's previous
 // value (admissible staleness in the asynchronous iteration); CHL = 1 gives the strict
 // ascending-column order of a Gauss-Seidel sweep.
-template <typename T, bool L_FROM_A, bool U_FROM_A, int CHL = CH>
+// D_FROM_A (first sweep from the initial guess X0 = A): the inverses U_jj^{-1} = A_jj^{-1} the
+// lower blocks need are formed here from A, in the same arithmetic as the initialisation kernel,
+// so no separate pass writes and re-reads them. A row whose A_ii no other row inverts this way
+// inverts it once itself, only to raise the flag the initialisation would raise when that inverse
+// is replaced: with sym (structurally symmetric pattern) those are the rows without strictly upper
+// blocks, otherwise every row checks its own.
+template <typename T, bool L_FROM_A, bool U_FROM_A, int CHL = CH, bool D_FROM_A = false>
 __device__ __forceinline__ void factor_sweep_row(int i,
     int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
     const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
     const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
-    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
+    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags, bool sym = false) {
     const int r = threadIdx.x & 3;
     if (i >= n) return;
     const int b0 = rowptr[i], b1 = rowptr[i + 1], d = diag_pos[i];
@@ -478,8 +484,18 @@ __device__ __forceinline__ void factor_sweep_row(int i,
             load_row(A + (int64_t)e * BB, r, t[u]);
             j[u] = colidx[e];
         }
+        if constexpr (D_FROM_A) {
 #pragma unroll
-        for (int u = 0; u < CHL; ++u) load_row(Dp + (int64_t)j[u] * BB, r, dr[u]);
+            for (int u = 0; u < CHL; ++u) {
+                T a[4], M[16];
+                load_row(A + (int64_t)diag_pos[j[u]] * BB, r, a);
+                gather_block(a, M);
+                if (!inv4_row(M, r, dr[u])) fl |= ABILU_FLAG_MODIFIED;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < CHL; ++u) load_row(Dp + (int64_t)j[u] * BB, r, dr[u]);
+        }
         if (pd > pb0) {
 #pragma unroll
             for (int u = 0; u < CHL; ++u)
@@ -501,6 +517,13 @@ __device__ __forceinline__ void factor_sweep_row(int i,
     {
         T t[4];
         load_row(A + (int64_t)d * BB, r, t);
+        if constexpr (D_FROM_A) {
+            if (!sym || d + 1 == b1) {
+                T M[16], unused[4];
+                gather_block(t, M);
+                if (!inv4_row(M, r, unused)) fl |= ABILU_FLAG_MODIFIED;
+            }
+        }
         update_terms<T, L_FROM_A, U_FROM_A>(pd, pd1, r, pik, pkj, sik, skj, A, XL, XU, t);
         fl |= nonfinite4(t);
         store_row(Xn + ((int64_t)ZL + i) * BB, r, t);
@@ -658,15 +681,15 @@ __device__ __forceinline__ void factor_chunk_row(int i, int c0, int ubound,
     if (fl) atomicOr(flags, fl);
 }
 
-template <typename T, bool L_FROM_A, bool U_FROM_A>
+template <typename T, bool L_FROM_A, bool U_FROM_A, bool D_FROM_A = false>
 __device__ __forceinline__ void factor_sweep_body(int blk,
     int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
     const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
     const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
-    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags) {
-    factor_sweep_row<T, L_FROM_A, U_FROM_A>(blk * ROWS_PER_WG + (threadIdx.x >> 2), n, ZL, rowptr, colidx, diag_pos,
-                                            lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags);
+    const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags, bool sym = false) {
+    factor_sweep_row<T, L_FROM_A, U_FROM_A, CH, D_FROM_A>(blk * ROWS_PER_WG + (threadIdx.x >> 2), n, ZL, rowptr, colidx, diag_pos,
+                                            lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags, sym);
 }
 
 // ------------------------------------------------------------------ per-row records of the

@@ -40,6 +40,11 @@ __global__ void k_pat_tri_cols(int n, const int32_t *__restrict__ rowptr, const 
     pat_tri_cols_body(blockIdx.x, n, rowptr, colidx, diag_pos, lrow, urow, lcol, ucol);
 }
 
+__global__ void k_pat_sym(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                          unsigned *__restrict__ asym) {
+    pat_sym_body(blockIdx.x, n, rowptr, colidx, asym);
+}
+
 void free_pattern(abilu_pattern *p) {
     if (!p) return;
     (void)hipFree(p->rowptr);
@@ -225,7 +230,19 @@ extern "C" abilu_status abilu_build_pattern(int32_t nbrows, const int32_t *d_row
         st = pattern_fill(n, Z, ZL, ZU, npairs, p->rowptr, p->colidx, p->diag_pos, p->lrow, p->urow, p->lcol,
                           p->ucol, p->pik, p->pkj, p->sik, p->skj, scratch, s);
         if (st != ABILU_OK) goto fail;
-        CK(hipStreamSynchronize(s));
+        // structural symmetry (the first factor sweep from A uses it to find the rows whose initial
+        // inverse no other row forms)
+        {
+            unsigned *asym = (unsigned *)scratch;
+            CK(hipMemsetAsync(asym, 0, sizeof(unsigned), s));
+            if (n > 0) {
+                k_pat_sym<<<div_up(n, 256), 256, 0, s>>>(n, p->rowptr, p->colidx, asym);
+                CK(hipGetLastError());
+            }
+            CK(hipMemcpyAsync(p->pinned, asym, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+            CK(hipStreamSynchronize(s));
+            p->symmetric = *(const unsigned *)p->pinned == 0;
+        }
     }
     (void)hipFree(scratch);
     *out = p;

@@ -119,11 +119,11 @@ __global__ __launch_bounds__(WG) void kb_factor_init(const Slot *slots, const Me
                                             COPY ? (T *)S.LU : (T *)nullptr, fbuf_d<T>(S, sel & 8), S.flags);
 }
 
-template <typename T, bool LA, bool UA>
+template <typename T, bool LA, bool UA, bool DA = false>
 __global__ __launch_bounds__(WG) void kb_factor_sweep(const Slot *slots, const Member *mem, int nmem, int sel) {
     MEMBER();
     const T *Xin = (LA && UA) ? (const T *)nullptr : fbuf_x<T>(S, sel & 1);
-    factor_sweep_body<T, LA, UA>(blk, S.n, S.ZL, S.rowptr, S.colidx, S.diag_pos, S.lrow, S.urow, S.pair_ptr, S.pik,
+    factor_sweep_body<T, LA, UA, DA>(blk, S.n, S.ZL, S.rowptr, S.colidx, S.diag_pos, S.lrow, S.urow, S.pair_ptr, S.pik,
                                  S.pkj, S.sik, S.skj, S.A, Xin, UA ? (const T *)nullptr : Xin,
                                  fbuf_d<T>(S, sel & 2), fbuf_x<T>(S, sel & 4), fbuf_d<T>(S, sel & 8), S.flags);
 }
@@ -914,11 +914,11 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
         if (fsw == 0) {
             if ((e = init(true, 0)) != ABILU_OK) return e;
         } else if (!sync) {
-            if ((e = init(false, 0)) != ABILU_OK) return e;
+            // the first sweep forms the initial inverses inv(A_jj) itself (no initialisation pass)
             {
                 ProfScope ps("serve_factor_sweep_fromA", st,
-                             B([&](const Sizes &z, const Req &) { return bytes_sweep(z, sF, false, true); }));
-                kb_factor_sweep<T, false, true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), 0);
+                             B([&](const Sizes &z, const Req &) { return bytes_sweep_from_a(z, sF, false); }));
+                kb_factor_sweep<T, false, true, true><<<L_(SH_ROW64)>>>(A_(SH_ROW64), 0);
             }
             CKL();
             for (int q = 1; q < fsw; ++q) {
@@ -930,11 +930,11 @@ abilu_status run_group(abilu_server *s, Group &G, hipStream_t st) {
         } else {
             // sweep q writes X1/D1 when (fsw - q) is odd, LU/Dinv when even (the last is LU/Dinv)
             auto one = [&](int q) { return ((fsw - q) % 2) != 0; };
-            if ((e = init(false, one(0) ? 8 : 0)) != ABILU_OK) return e;
+            // the first sweep forms the initial inverses inv(A_jj) itself (no initialisation pass)
             {
                 ProfScope ps("serve_factor_sweep_fromA", st,
-                             B([&](const Sizes &z, const Req &) { return bytes_sweep(z, sF, true, true); }));
-                kb_factor_sweep<T, true, true>
+                             B([&](const Sizes &z, const Req &) { return bytes_sweep_from_a(z, sF, true); }));
+                kb_factor_sweep<T, true, true, true>
                     <<<L_(SH_ROW64)>>>(A_(SH_ROW64), (one(0) ? 2 : 0) | (one(1) ? 4 : 0) | (one(1) ? 8 : 0));
             }
             CKL();

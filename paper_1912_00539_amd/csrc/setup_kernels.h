@@ -174,6 +174,20 @@ __device__ __forceinline__ void pat_fill_body(int blk, int n, int ZL, const int3
     }
 }
 
+// structural symmetry: one thread per block row; sets *asym when some (i,j) in S_B has no (j,i)
+__device__ __forceinline__ void pat_sym_body(int blk, int n, const int32_t *__restrict__ rowptr,
+                                             const int32_t *__restrict__ colidx, unsigned *__restrict__ asym) {
+    int i = blk * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int j = colidx[e];
+        if (j != i && find_col(rowptr, colidx, j, i) < 0) {
+            atomicOr(asym, 1u);
+            return;
+        }
+    }
+}
+
 // per-row counts of strictly lower / upper blocks
 __device__ __forceinline__ void pat_tri_counts_body(int blk, int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ diag_pos,
                                  int64_t *__restrict__ nl, int64_t *__restrict__ nu) {

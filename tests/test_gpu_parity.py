@@ -259,6 +259,42 @@ def test_factor_singular_and_nonfinite_flags():
     assert s.flags() & 2
 
 
+def _drop_block(c, i, j):
+    """The case without block (i, j) (a structurally non-symmetric pattern)."""
+    keep = np.ones(c.nnzb, bool)
+    e = c.rowptr[i] + int(np.nonzero(c.colidx[c.rowptr[i]:c.rowptr[i + 1]] == j)[0][0])
+    keep[e] = False
+    rowptr = np.concatenate([[0], np.cumsum(np.diff(c.rowptr) - (np.arange(c.n) == i))]).astype(np.int32)
+    return W.BSRCase(c.n, rowptr, c.colidx[keep], c.vals[keep], c.b, c.meta)
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_first_sweep_flags_every_replaced_initial_inverse(symmetric, mode):
+    """The first sweep from A forms the initial inverses inv(A_jj) where the lower blocks need them,
+    and a row whose A_ii no other row inverts inverts it itself, so the flag of a replaced initial
+    inverse is raised as the oracle (which inverts every diagonal block of X0) raises it: here a
+    zero diagonal block on a row that no strictly lower block references (the last row of a chain;
+    with the block (3, 2) removed, row 2 of the non-symmetric pattern)."""
+    c = W.case("chain", seed=8, n=7)
+    row = c.n - 1
+    if not symmetric:
+        c, row = _drop_block(c, 3, 2), 2
+    A = c.vals.copy()
+    A[c.rowptr[row] + int(np.nonzero(c.colidx[c.rowptr[row]:c.rowptr[row + 1]] == row)[0][0])] = 0.0
+    c0 = W.BSRCase(c.n, c.rowptr, c.colidx, A, c.b, c.meta)
+    _, _, fo = oracle.factor_sync(c.n, c.rowptr, c.colidx, A, 1)
+    assert fo & oracle.FLAG_MODIFIED
+    s = DS(c0, "f64")
+    s.factor(1, mode)
+    assert s.flags() & 1
+    # and none on the unmodified matrix
+    s = DS(c, "f64")
+    s.factor(1, mode)
+    _, _, fo = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    assert s.flags() == fo == 0
+
+
 # ------------------------------------------------------------------ apply sweeps (a5, a6)
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("nsw", [0, 1, 2, 3, 5])
