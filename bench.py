@@ -779,8 +779,7 @@ def chunked_bench(args):
 # gives their launches in the asynchronous FP32 step.
 TRAFFIC_KERNELS = {
     "k_spmv<false>": "spmv", "k_spmv<true>": "spmv_resid",
-    "k_factor_sweep<float, false, true>": "factor_sweep_f32_async_fromA",
-    "k_factor_init<float, double, true, false>": "factor_init_f32",
+    "k_factor_sweep<float, false, true, true>": "factor_sweep_f32_async_fromA",
     "k_fwd<float, double, false>": "apply_fwd_f32_async", "k_fwd<float, float, true>": "apply_fwd_emitz_f32_async",
     "k_bwd<float, float, float, true, false>": "apply_bwd_f32_async",
     "k_bwd<float, float, double, true, false>": "apply_bwd_last_f32_async",
