@@ -15,12 +15,14 @@ __global__ void k_pat_rows(int n, int64_t Z, const int32_t *__restrict__ rowptr,
     pat_rows_body(blockIdx.x, n, Z, rowptr, colidx, diag_pos, err);
 }
 
-__global__ void k_pat_count(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                            int64_t *__restrict__ cnt) {
-    pat_count_body(blockIdx.x, n, rowptr, colidx, cnt);
+__global__ __launch_bounds__(PAT_ROWS) void k_pat_count(int n, const int32_t *__restrict__ rowptr,
+                                                         const int32_t *__restrict__ colidx,
+                                                         const int32_t *__restrict__ diag_pos,
+                                                         int64_t *__restrict__ cnt) {
+    pat_count_body(blockIdx.x, n, rowptr, colidx, diag_pos, cnt);
 }
 
-__global__ void k_pat_fill(int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+__global__ __launch_bounds__(PAT_ROWS) void k_pat_fill(int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
                            const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow,
                            const int32_t *__restrict__ urow, const int64_t *__restrict__ ptr,
                            int32_t *__restrict__ pik, int32_t *__restrict__ pkj, int32_t *__restrict__ sik,
@@ -110,7 +112,7 @@ abilu_status pattern_count_async(int32_t n, int64_t Z, const int32_t *rowptr, co
         CK(hipMemcpyAsync(h_sizes + part, ptr64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     }
     if (n > 0) {
-        k_pat_count<<<div_up(n, 128), 128, 0, s>>>(n, rowptr, colidx, cnt);
+        k_pat_count<<<div_up(n, PAT_ROWS), PAT_ROWS, 0, s>>>(n, rowptr, colidx, diag_pos, cnt);
         CK(hipGetLastError());
     }
     CK(scan_exclusive(Z, cnt, tmp, tot, ptr64, pair_ptr, s));
@@ -157,7 +159,7 @@ abilu_status pattern_fill(int32_t n, int64_t Z, int64_t ZL, int64_t ZU, int64_t 
         if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
     }
     if (n > 0 && npairs > 0) {
-        k_pat_fill<<<div_up(n, 128), 128, 0, s>>>(n, (int)ZL, rowptr, colidx, diag_pos, lrow, urow, ptr64, pik, pkj,
+        k_pat_fill<<<div_up(n, PAT_ROWS), PAT_ROWS, 0, s>>>(n, (int)ZL, rowptr, colidx, diag_pos, lrow, urow, ptr64, pik, pkj,
                                                    sik, skj);
         if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
     }

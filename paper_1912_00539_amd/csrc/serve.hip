@@ -306,7 +306,7 @@ __global__ void kbs_pat_tri_counts(const SetupDesc *sd, const Member *mem, int n
 
 __global__ void kbs_pat_count(const SetupDesc *sd, const Member *mem, int nmem) {
     SMEMBER();
-    abilu_setup::pat_count_body(blk, D.n, D.rowptr, D.colidx, D.cnt);
+    abilu_setup::pat_count_body(blk, D.n, D.rowptr, D.colidx, D.diag_pos, D.cnt);
 }
 
 __global__ void kbs_pat_tri_cols(const SetupDesc *sd, const Member *mem, int nmem, const int64_t *adm) {
@@ -535,7 +535,7 @@ int setup_tiles(const Req &r, int shape) {
     switch (shape) {
         case SS_ROW256: return div_up(n, 256);
         case SS_ROW64: return div_up(n, ROWS_PER_WG);
-        case SS_ROW128: return div_up(n, 128);
+        case SS_ROW128: return div_up(n, abilu_setup::PAT_ROWS);
         case SS_SCAN_N: return div_up(n > 0 ? n : 1, abilu_setup::SCAN_TILE);
         case SS_SCAN_Z: return div_up(Z > 0 ? Z : 1, abilu_setup::SCAN_TILE);
         case SS_FIN_N: return div_up(n + 1, abilu_setup::SCAN_TILE);
@@ -731,7 +731,7 @@ abilu_status admit_queued(abilu_server *s, int64_t cell_budget) {
     kbs_pat_tri_counts<<<T.tiles[SS_ROW256], 256, 0, st>>>(s->d_sdesc, T.d[SS_ROW256], T.count);
     CKL();
     if (launch_scan(s, T, SC_LROW) != ABILU_OK || launch_scan(s, T, SC_UROW) != ABILU_OK) return ABILU_EDEVICE;
-    kbs_pat_count<<<T.tiles[SS_ROW128], 128, 0, st>>>(s->d_sdesc, T.d[SS_ROW128], T.count);
+    kbs_pat_count<<<T.tiles[SS_ROW128], abilu_setup::PAT_ROWS, 0, st>>>(s->d_sdesc, T.d[SS_ROW128], T.count);
     CKL();
     if (launch_scan(s, T, SC_PAIR) != ABILU_OK) return ABILU_EDEVICE;
     CKS(hipMemcpyAsync(s->h_adm, s->d_adm, sizeof(int64_t) * 4 * B, hipMemcpyDeviceToHost, st));
@@ -749,7 +749,7 @@ abilu_status admit_queued(abilu_server *s, int64_t cell_budget) {
     // per-slot events before a request's first tick
     kbs_pat_tri_cols<<<T.tiles[SS_ROW256], 256, 0, st>>>(s->d_sdesc, T.d[SS_ROW256], T.count, s->d_adm);
     CKL();
-    kbs_pat_fill<<<T.tiles[SS_ROW128], 128, 0, st>>>(s->d_sdesc, T.d[SS_ROW128], T.count, s->d_adm);
+    kbs_pat_fill<<<T.tiles[SS_ROW128], abilu_setup::PAT_ROWS, 0, st>>>(s->d_sdesc, T.d[SS_ROW128], T.count, s->d_adm);
     CKL();
     kbs_publish<<<T.tiles[SS_ONE], 64, 0, st>>>(s->d_sdesc, T.d[SS_ONE], T.count, s->d_sslot, s->d_slots, s->d_hdr,
                                                  s->d_adm);

@@ -127,49 +127,111 @@ __device__ __forceinline__ void pat_rows_body(int blk, int n, int64_t Z, const i
     if (bad) atomicOr(err, 1u);
 }
 
-// one thread per block row; counts |K(i,j)| for every block of the row
-__device__ __forceinline__ void pat_count_body(int blk, int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                            int64_t *__restrict__ cnt) {
-    int i = blk * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b0 = rowptr[i], b1 = rowptr[i + 1];
-    for (int e = b0; e < b1; ++e) {
-        int j = colidx[e];
-        int lim = i < j ? i : j;
-        int c = 0;
-        for (int f = b0; f < b1; ++f) {
-            int k = colidx[f];
-            if (k >= lim) break;
-            c += (find_col(rowptr, colidx, k, j) >= 0);
-        }
-        cnt[e] = c;
+// position of column j in the strictly upper part of row k (j > k), or -1 (binary search)
+__device__ __forceinline__ int find_upper(const int32_t *rowptr, const int32_t *colidx, const int32_t *diag_pos,
+                                          int k, int j) {
+    int lo = diag_pos[k] + 1, hi = rowptr[k + 1] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int c = colidx[mid];
+        if (c == j) return mid;
+        if (c < j) lo = mid + 1; else hi = mid - 1;
     }
+    return -1;
 }
 
-__device__ __forceinline__ void pat_fill_body(int blk, int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
-                           const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow,
-                           const int32_t *__restrict__ urow, const int64_t *__restrict__ ptr,
-                           int32_t *__restrict__ pik, int32_t *__restrict__ pkj, int32_t *__restrict__ sik,
-                           int32_t *__restrict__ skj) {
-    using abilu_dev::split_pos;
-    int i = blk * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b0 = rowptr[i], b1 = rowptr[i + 1];
-    for (int e = b0; e < b1; ++e) {
-        int j = colidx[e];
-        int lim = i < j ? i : j;
-        int64_t o = ptr[e];
-        for (int f = b0; f < b1; ++f) {
-            int k = colidx[f];
-            if (k >= lim) break;
-            int g = find_col(rowptr, colidx, k, j);
-            if (g >= 0) {
-                pik[o] = f;
-                pkj[o] = g;
-                sik[o] = split_pos(f, i, b0, diag_pos[i], lrow[i], urow[i], ZL, n);
-                skj[o] = split_pos(g, k, rowptr[k], diag_pos[k], lrow[k], urow[k], ZL, n);
-                ++o;
+// The count and fill bodies run one thread per block row, PAT_ROWS rows per workgroup. A
+// workgroup's outputs form one contiguous range; when it holds at most PAT_STAGE entries they are
+// staged in LDS and written together, so every line is written whole (a thread's own entries are
+// a few words at a row's stride, which partly written lines would write back several times).
+constexpr int PAT_ROWS = 128;
+constexpr int PAT_STAGE = 1024;
+
+// |K(i,j)| for every block (i,j) of the row: the k < min(i,j) of the row's strictly lower blocks
+// with (k,j) in S_B (an upper block of row k, since k < j)
+__device__ __forceinline__ void pat_count_body(int blk, int n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ colidx,
+                                               const int32_t *__restrict__ diag_pos, int64_t *__restrict__ cnt) {
+    __shared__ int32_t sh[PAT_STAGE];
+    const int i0 = blk * PAT_ROWS;
+    if (i0 >= n) return;   // the whole workgroup
+    const int i1 = min(n, i0 + PAT_ROWS);
+    const int base = rowptr[i0], len = rowptr[i1] - base;
+    const bool staged = len <= PAT_STAGE;
+    const int i = i0 + (int)threadIdx.x;
+    if (i < i1) {
+        const int b0 = rowptr[i], b1 = rowptr[i + 1];
+        for (int e = b0; e < b1; ++e) {
+            const int j = colidx[e];
+            const int lim = i < j ? i : j;
+            int c = 0;
+            for (int f = b0; f < b1; ++f) {
+                const int k = colidx[f];
+                if (k >= lim) break;
+                c += (find_upper(rowptr, colidx, diag_pos, k, j) >= 0);
             }
+            if (staged) sh[e - base] = c;
+            else cnt[e] = c;
+        }
+    }
+    __syncthreads();
+    if (staged)
+        for (int t = threadIdx.x; t < len; t += blockDim.x) cnt[base + t] = sh[t];
+}
+
+// The update-set lists: for block e = (i,j), entries ptr[e] .. ptr[e+1] hold, ascending in k, the
+// CSR positions of (i,k) and (k,j) and their factor-layout positions ((i,k) is strictly lower in
+// row i, (k,j) strictly upper in row k).
+__device__ __forceinline__ void pat_fill_body(int blk, int n, int ZL, const int32_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ colidx,
+                                              const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow,
+                                              const int32_t *__restrict__ urow, const int64_t *__restrict__ ptr,
+                                              int32_t *__restrict__ pik, int32_t *__restrict__ pkj,
+                                              int32_t *__restrict__ sik, int32_t *__restrict__ skj) {
+    __shared__ int32_t sh[4][PAT_STAGE];
+    const int i0 = blk * PAT_ROWS;
+    if (i0 >= n) return;   // the whole workgroup
+    const int i1 = min(n, i0 + PAT_ROWS);
+    const int64_t pbase = ptr[rowptr[i0]], plen = ptr[rowptr[i1]] - pbase;
+    const bool staged = plen <= PAT_STAGE;
+    const int i = i0 + (int)threadIdx.x;
+    if (i < i1) {
+        const int b0 = rowptr[i], b1 = rowptr[i + 1], lb = lrow[i];
+        for (int e = b0; e < b1; ++e) {
+            const int j = colidx[e];
+            const int lim = i < j ? i : j;
+            int64_t o = ptr[e];
+            for (int f = b0; f < b1; ++f) {
+                const int k = colidx[f];
+                if (k >= lim) break;
+                const int g = find_upper(rowptr, colidx, diag_pos, k, j);
+                if (g >= 0) {
+                    const int v2 = lb + (f - b0);
+                    const int v3 = ZL + n + urow[k] + (g - diag_pos[k] - 1);
+                    if (staged) {
+                        const int t = (int)(o - pbase);
+                        sh[0][t] = f;
+                        sh[1][t] = g;
+                        sh[2][t] = v2;
+                        sh[3][t] = v3;
+                    } else {
+                        pik[o] = f;
+                        pkj[o] = g;
+                        sik[o] = v2;
+                        skj[o] = v3;
+                    }
+                    ++o;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (staged) {
+        for (int t = threadIdx.x; t < (int)plen; t += blockDim.x) {
+            pik[pbase + t] = sh[0][t];
+            pkj[pbase + t] = sh[1][t];
+            sik[pbase + t] = sh[2][t];
+            skj[pbase + t] = sh[3][t];
         }
     }
 }
