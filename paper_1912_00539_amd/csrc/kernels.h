@@ -446,11 +446,12 @@ __device__ __forceinline__ void factor_init_body(int blk, int n, int ZL, const i
     if (!ok && r == 0) atomicOr(flags, ABILU_FLAG_MODIFIED);
 }
 
-// One sweep over block row i (a quad of 4 lanes). The strictly lower blocks are computed in
-// chunks of CHL, each chunk's results stored together: with CHL = 2 a block whose update set
-// contains the column of the block just before it in the same chunk reads that block's previous
-// value (admissible staleness in the asynchronous iteration); CHL = 1 gives the strict
-// ascending-column order of a Gauss-Seidel sweep.
+// One sweep over block row i (a quad of 4 lanes). The strictly lower blocks are loaded in chunks
+// of CHL (their A blocks and inverses fetched together) and computed and stored one at a time in
+// ascending column order, so a block whose update set holds an earlier block of the row reads that
+// block's value from this sweep when the sweep works in place (the strict Gauss-Seidel order within
+// the row). This also keeps the first in-place sweep from A from reading the output buffer before
+// this sweep has written it: there X_ik of the row is never taken from the initial guess.
 // D_FROM_A (first sweep from the initial guess X0 = A): the inverses U_jj^{-1} = A_jj^{-1} the
 // lower blocks need are formed here from A, in the same arithmetic as the initialisation kernel,
 // so no separate pass writes and re-reads them. A row whose A_ii no other row inverts this way
@@ -496,18 +497,14 @@ __device__ __forceinline__ void factor_sweep_row(int i,
 #pragma unroll
             for (int u = 0; u < CHL; ++u) load_row(Dp + (int64_t)j[u] * BB, r, dr[u]);
         }
-        if (pd > pb0) {
-#pragma unroll
-            for (int u = 0; u < CHL; ++u)
-                if (e0 + u < d)
-                    update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
-                                                        skj, A, XL, XU, t[u]);
-        }
 #pragma unroll
         for (int u = 0; u < CHL; ++u) {
-            T x[4];
-            row_times_block(t[u], dr[u], x);
             if (e0 + u < d) {
+                if (pd > pb0)
+                    update_terms<T, L_FROM_A, U_FROM_A>(pair_ptr[e0 + u], pair_ptr[e0 + u + 1], r, pik, pkj, sik,
+                                                        skj, A, XL, XU, t[u]);
+                T x[4];
+                row_times_block(t[u], dr[u], x);
                 fl |= nonfinite4(x);
                 store_row(XnL + (int64_t)(e0 + u - b0) * BB, r, x);
             }

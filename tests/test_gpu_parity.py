@@ -295,6 +295,46 @@ def test_first_sweep_flags_every_replaced_initial_inverse(symmetric, mode):
     assert s.flags() == fo == 0
 
 
+def _lower_pairs_in_one_load_chunk(c, chunk=2):
+    """Rows with strictly lower blocks (i, j1), (i, j2) in one load chunk of the sweep (positions
+    b0 + 2m, b0 + 2m + 1) where j1 is in the update set of (i, j2), i.e. (j1, j2) is in the
+    pattern."""
+    S = {(i, int(j)) for i in range(c.n) for j in c.colidx[c.rowptr[i]:c.rowptr[i + 1]]}
+    hits = 0
+    for i in range(c.n):
+        b0 = int(c.rowptr[i])
+        low = [int(j) for j in c.colidx[b0:c.rowptr[i + 1]] if j < i]
+        for m in range(0, len(low) - 1, chunk):
+            hits += (low[m], low[m + 1]) in S
+    return hits
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["nine23x17", "random1000"])
+def test_first_async_sweep_from_A_ignores_the_output_buffer(name, prec):
+    """The first in-place sweep from X0 = A takes U_kj and the inverses inv(A_jj) from A and the
+    row's own L_ik from this sweep, each lower block computed after the ones before it in the row:
+    it reads nothing of the output buffer before writing it. Its result is therefore the same
+    whatever the buffers held (NaN, zero, a huge value), finite, and raises no flag, also where a
+    lower block's update set holds the block loaded beside it (nine-point and random patterns)."""
+    c = get(name)
+    assert _lower_pairs_in_one_load_chunk(c) > 0
+    s = DS(c, prec)
+    out = []
+    for fill in (float("nan"), 0.0, 1e30):
+        s.LU.fill_(fill)
+        s.Dinv.fill_(fill)
+        s.flags(clear=True)
+        s.factor(1, "async")
+        assert s.flags() == 0, fill
+        X, D = s.factor_host()
+        assert np.isfinite(X).all() and np.isfinite(D).all(), fill
+        out.append((X, D))
+    for X, D in out[1:]:
+        assert_same_bits(X, out[0][0], "X")
+        assert_same_bits(D, out[0][1], "Dinv")
+
+
 # ------------------------------------------------------------------ apply sweeps (a5, a6)
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("nsw", [0, 1, 2, 3, 5])
