@@ -52,7 +52,7 @@ __global__ __launch_bounds__(WG) void k_factor_init(int n, int ZL, const int32_t
 // One sweep (D_FROM_A: the first sweep from A, forming the initial inverses itself; sym: the
 // pattern is structurally symmetric).
 template <typename T, bool L_FROM_A, bool U_FROM_A, bool D_FROM_A = false>
-__global__ __launch_bounds__(WG) void k_factor_sweep(
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sweep_waves<T>()))) void k_factor_sweep(
     int n, int ZL, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const int32_t *__restrict__ diag_pos, const int32_t *__restrict__ lrow, const int32_t *__restrict__ urow,
     const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(WG) void kb_factor_init(const Slot *slots, const Me
 }
 
 template <typename T, bool LA, bool UA, bool DA = false>
-__global__ __launch_bounds__(WG) void kb_factor_sweep(const Slot *slots, const Member *mem, int nmem, int sel) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sweep_waves<T>()))) void kb_factor_sweep(const Slot *slots, const Member *mem, int nmem, int sel) {
     MEMBER();
     const T *Xin = (LA && UA) ? (const T *)nullptr : fbuf_x<T>(S, sel & 1);
     factor_sweep_body<T, LA, UA, DA>(blk, S.n, S.ZL, S.rowptr, S.colidx, S.diag_pos, S.lrow, S.urow, S.pair_ptr, S.pik,
