@@ -1184,9 +1184,22 @@ def _pick(d, *keys):
     return {k: d.get(k) for k in keys} if d else None
 
 
+def _sig(x, n=4):
+    """x with every float rounded to n significant digits (nested dicts and lists too)."""
+    if isinstance(x, float):
+        return float(f"{x:.{n - 1}e}") if x == x and abs(x) != float("inf") else x
+    if isinstance(x, dict):
+        return {k: _sig(v, n) for k, v in x.items()}
+    if isinstance(x, list):
+        return [_sig(v, n) for v in x]
+    return x
+
+
 def headline(out, detail_path=None):
     """The compact result line (a few KB): the headline figures of `out` and a summary of every
-    sub-benchmark, the full object being in the detail file."""
+    sub-benchmark, the full object being in the detail file. Secondary figures (residuals, errors,
+    serving and convergence summaries) are rounded to 4 significant digits; the detail file keeps
+    them whole."""
     h = {k: out.get(k) for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
                                  "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")}
     h["value_covers"] = "whole step (factor, FGMRES with apply sweeps, SpMV, Gram-Schmidt): algorithmic bytes / wall time"
@@ -1217,7 +1230,8 @@ def headline(out, detail_path=None):
         h["serving"] = {
             "requests": (sat.get("batched_f32") or {}).get("converged"),
             "saturation": {k: form(sat.get(k), ("solves_per_s", "p50_ms", "p99_ms", "solve_path_GBps", "mean_iters",
-                                                "max_rel_true_residual")) for k in sat},
+                                                "max_rel_true_residual") if k != "one_at_a_time_f32"
+                                   else ("solves_per_s",)) for k in sat},
             "speedup_solves_per_s": sv.get("speedup_solves_per_s"),
             "poisson_rate_per_s": po.get("rate_per_s"),
             "poisson": {k: form(po.get(k), ("p50_ms", "p99_ms")) for k in po if k != "rate_per_s"}}
@@ -1235,8 +1249,8 @@ def headline(out, detail_path=None):
         pair = lambda e: [sig3(e.get("rel")), sig3(e.get("max_block_rel"))] if e else None
         h["precision"] = {
             "f32_speedup_step": pr.get("f32_speedup_step"),
-            "f32_vs_f64_legend": "[rel Frobenius, max block rel] FP32 vs FP64 (= oracle): X, Dinv after 1, 2 SYNC "
-                                 "sweeps; z of a SYNC apply",
+            "f32_vs_f64_legend": "[rel Frobenius, max block rel] vs the FP64 oracle: X, Dinv after 1, 2 SYNC sweeps; "
+                                 "z: SYNC apply",
             "f32_vs_f64": {k: {"X1": pair(v.get("sweeps1", {}).get("X")), "D1": pair(v.get("sweeps1", {}).get("Dinv")),
                                "X2": pair(v.get("sweeps2", {}).get("X")), "D2": pair(v.get("sweeps2", {}).get("Dinv")),
                                "z": pair(v.get("apply"))}
@@ -1253,6 +1267,14 @@ def headline(out, detail_path=None):
     fc = out.get("factor_convergence")
     if fc:
         h["factor_convergence"] = fc.get("summary")
+    for k in ("max_rel_true_residual", "ilu_residual", "serving"):
+        h[k] = _sig(h.get(k))
+    h["factor_convergence"] = _sig(h.get("factor_convergence"), 3)
+    oc = (h.get("cpu_baseline") or {}).get("oracle_check")
+    if oc:
+        if oc.get("f64_bitwise_equal"):
+            oc = {k: v for k, v in oc.items() if k != "f64"}   # all zeros when bitwise equal
+        h["cpu_baseline"]["oracle_check"] = _sig(oc)
     h["detail_file"] = detail_path
     h["source_hash"] = out.get("source_hash")
     return h

@@ -36,9 +36,9 @@ def test_cpu_baseline_fields():
 
 def _stub_detail():
     """A result object shaped like the one bench.py builds on the GPU, with its long per-step arrays."""
-    err = {"rel": 1.234e-06, "max_block_rel": 5.678e-05}
+    err = {"rel": 1.2345678901234567e-06, "max_block_rel": 5.678901234567891e-05}
     serve = {"solves_per_s": 2959.12, "elapsed_s": 0.676, "p50_ms": 2.57, "p99_ms": 8.88, "mean_ms": 3.08,
-             "max_ms": 11.534, "converged": 2000, "max_rel_true_residual": 0.00866, "mean_iters": 2.0,
+             "max_ms": 11.534, "converged": 2000, "max_rel_true_residual": 0.0008631065690128775, "mean_iters": 2.0,
              "solve_path_GBps": 4145.5, "ticks": 8000, "launches": 100000, "max_admitted": 200}
     steps = [{"step": t, "cfl": 10.0 * 1.5 ** t,
               "cold": {"ilu_residual": 0.01, "iters": 2, "converged": 1, "factor_ms": 0.3, "solve_ms": 0.5},
@@ -56,7 +56,8 @@ def _stub_detail():
                      "algorithmic_bytes_per_launch": 2383208004},
         "frac_hbm_peak": 0.6986, "stream_copy_GBps": 5700.0, "frac_stream": 0.98, "factor_apply_GBps": 5600.0,
         "factor_sweeps_per_s": 1100.0, "solves_per_s": 232.2, "timing": "without per-launch profiling events",
-        "fgmres_iters": [2] * 20, "ilu_residual": 0.0123, "converged": True, "max_rel_true_residual": 0.004,
+        "fgmres_iters": [2] * 20, "ilu_residual": 0.004760681767857292, "converged": True,
+        "max_rel_true_residual": 0.0007444273330686531,
         "kernels": {f"kernel_{q}": {"launches": 100, "ms": 1.0, "GBps": 5000.0} for q in range(40)},
         "compare": [{"mode": "sync", "fgmres_iters": [100] * 3}] * 2,
         "precision": {"f32_speedup_step": 1.6, "steps": {},
@@ -96,7 +97,7 @@ def test_headline_line_is_compact_and_parseable(tmp_path, capsys):
     bench.emit(out, path)
     lines = capsys.readouterr().out.strip().splitlines()
     last = lines[-1]
-    assert len(last) < 4096, len(last)
+    assert len(last) < 3900, len(last)   # a margin below 4 KB for longer figures of a real run
     h = json.loads(last)
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
               "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline", "serving", "value_covers",
