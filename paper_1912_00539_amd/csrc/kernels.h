@@ -13,15 +13,12 @@ using namespace abilu;
 using namespace abilu_dev;
 
 constexpr int CH = 2;                        // factor sweep: blocks of a row loaded together
-// The first sweep from A forms an inverse inv(A_jj) per strictly lower block, each from a whole
-// gathered 4x4 block; one block at a time keeps that sweep's registers low enough for more waves.
-template <bool D_FROM_A>
-constexpr int sweep_chunk() { return D_FROM_A ? 1 : CH; }
-// Waves per SIMD the single-precision factor sweeps are compiled for (at most 72 VGPRs): their
-// gathers need many waves in flight, and the FP32 sweeps fit without spilling; the FP64 sweeps
+// Waves per SIMD the single-precision factor sweeps are compiled for (at most 102 VGPRs). The
+// first sweep from A, which inverts a gathered A_jj for each of the two lower blocks in flight,
+// would otherwise take 107 VGPRs and run 4 waves; it fits 5 without spilling. The FP64 sweeps
 // keep the compiler's choice (at this budget they would spill).
 template <typename T>
-constexpr int sweep_waves() { return sizeof(T) == 4 ? 7 : 1; }
+constexpr int sweep_waves() { return sizeof(T) == 4 ? 5 : 1; }
 // apply sweeps: block rows per quad (FP32: two rows keep enough loads in flight; FP64 rows carry
 // twice the bytes and run faster one per quad) and rows per workgroup
 template <typename T>
@@ -694,7 +691,7 @@ __device__ __forceinline__ void factor_sweep_body(int blk,
     const int32_t *__restrict__ pair_ptr, const int32_t *__restrict__ pik, const int32_t *__restrict__ pkj,
     const int32_t *__restrict__ sik, const int32_t *__restrict__ skj, const double *__restrict__ A, const T *XL,
     const T *XU, const T *Dp, T *Xn, T *Dn, unsigned *flags, bool sym = false) {
-    factor_sweep_row<T, L_FROM_A, U_FROM_A, sweep_chunk<D_FROM_A>(), D_FROM_A>(blk * ROWS_PER_WG + (threadIdx.x >> 2), n, ZL, rowptr, colidx, diag_pos,
+    factor_sweep_row<T, L_FROM_A, U_FROM_A, CH, D_FROM_A>(blk * ROWS_PER_WG + (threadIdx.x >> 2), n, ZL, rowptr, colidx, diag_pos,
                                             lrow, urow, pair_ptr, pik, pkj, sik, skj, A, XL, XU, Dp, Xn, Dn, flags, sym);
 }
 
