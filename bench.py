@@ -560,6 +560,64 @@ def configs_bench(args):
     return out
 
 
+def graphs_bench(args):
+    """Launch overhead of small systems: a factor plus one application, issued as eager library
+    calls and as one captured HIP graph replayed (the entry points launch kernels only, so they
+    capture as they are). The plain FP64 32x32 grid (1,024 cells; 3 SYNC factor sweeps, 3 apply
+    sweep pairs) and the 180,000-triangle mesh (FP32, 1 SYNC sweep, 3 pairs); the replayed factor
+    and z are checked equal to the eager ones bit for bit."""
+    import torch
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    out = {}
+    for label, c, prec, nf in (("quad32_f64", W.case("quad32"), "f64", 3),
+                               ("tri300_f32", W.case("tri300", cfl=100.0), "f32", 1)):
+        s = DeviceSystem(c, prec=prec, restart=1)
+        g_ = torch.Generator(device="cpu").manual_seed(args.serve_seed)
+        r = (2 * torch.rand(4 * c.n, dtype=torch.float64, generator=g_) - 1).cuda()
+        z = torch.zeros_like(r)
+
+        def work():
+            s.factor(nf, "sync")
+            s.apply(r, z, args.apply_sweeps, "sync")
+
+        work()
+        torch.cuda.synchronize()
+        X0, z0 = s.LU.clone(), z.clone()
+        reps = 200
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            work()
+        torch.cuda.synchronize()
+        eager = (time.perf_counter() - t0) / reps
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            work()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            work()
+        s.LU.fill_(float("nan"))
+        z.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(s.LU, X0) and torch.equal(z, z0))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph = (time.perf_counter() - t0) / reps
+        out[label] = {"n": c.n, "factor_sweeps": nf, "apply_sweeps": args.apply_sweeps,
+                      "eager_us": round(eager * 1e6, 1), "graph_us": round(graph * 1e6, 1),
+                      "speedup": round(eager / graph, 2), "replay_bits_equal": same}
+        log(f"graphs {label}: {out[label]}")
+        del g, s
+        torch.cuda.empty_cache()
+    return out
+
+
 def tri300_sweep_bench():
     """The 180,000-triangle workload at CFL 10, 100 and 1000: ILU residual after 1 to 4 FP32 factor
     sweeps, SYNC and ASYNC, and the FGMRES(30) iterations to 1e-2 with 2 apply sweep pairs."""
@@ -1006,6 +1064,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-chunked", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--no-orderings", action="store_true")
     ap.add_argument("--no-factor-convergence", action="store_true")
     ap.add_argument("--fixed-point-cap", type=int, default=400,
@@ -1154,6 +1213,7 @@ def main():
     out["precision"] = None if args.no_precision else precision_bench(case, args)
     out["chunked"] = None if args.no_chunked else chunked_bench(args)
     out["configs"] = None if args.no_configs else configs_bench(args)
+    out["graphs"] = None if args.no_graphs else graphs_bench(args)
     out["orderings"] = None if args.no_orderings else orderings_bench(args)
     out["serving"] = None if args.no_serving else serving_bench(args)
     out["warm_start"] = None if args.no_warm_start else warm_start_bench(args)

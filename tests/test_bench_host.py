@@ -74,6 +74,8 @@ def _stub_detail():
                                         "batched_f32": dict(serve, max_iters=31),
                                         "one_at_a_time_f64": dict(serve, max_iters=30)}},
         "warm_start": {"totals": {"cold": {"iters": 24}, "warm": {"iters": 12}}, "steps": steps},
+        "graphs": {k: {"n": 1024, "factor_sweeps": 3, "apply_sweeps": 3, "eager_us": 123.4, "graph_us": 56.7,
+                       "speedup": 2.18, "replay_bits_equal": True} for k in ("quad32_f64", "tri300_f32")},
         "factor_convergence": {"summary": {k: {"D": 11085, "fixed_point_sweeps": 37,
                                                "f32_async_E_L": [0.03239, 0.001111, 4.155e-05, 1.88e-06, 7.728e-08],
                                                "f32_async_E_U": [0.08257, 0.002898, 0.000103, 3.774e-06, 1.348e-06]}
