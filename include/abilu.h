@@ -258,6 +258,10 @@ size_t abilu_workspace_bytes(const abilu_pattern *p, abilu_prec prec, int32_t fg
  *                     overwritten as soon as they are computed and later updates read whatever
  *                     values are in memory; sums accumulate in registers only; no atomics on
  *                     values. One kernel launch per sweep bounds the delay by one sweep.
+ *                     A row's blocks are computed in ascending column order, each reading the
+ *                     row's blocks computed before it; the first sweep from A takes every other
+ *                     operand (U_kj, the initial inverses) from A itself, so the prior contents
+ *                     of d_LU and d_Dinv are never read.
  *   mode ABILU_ASYNC_SERIAL, ABILU_CHUNK_SYNC, ABILU_CHUNK_ASYNC: see abilu_mode (the chunked
  *                     modes need the pattern's chunk schedule, else ABILU_EINVAL).
  *   init  ABILU_INIT_FROM_A : initial guess X0 = A (the paper's choice, Section 6 setup)
