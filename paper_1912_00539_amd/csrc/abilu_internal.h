@@ -159,15 +159,26 @@ inline double bytes_spmv(const Sizes &z, bool resid) {
 
 // ------------------------------------------------------------------ device prefix sums (scan.hip)
 // Tiles needed by scan_exclusive for `len` elements; the `tot` scratch needs scan_tiles(len) + 1
-// int64 entries, `tmp` len entries. out64 (optional) gets len + 1 offsets, out32 len + 1 offsets.
+// int64 entries. out64 (optional) gets len + 1 offsets, out32 len + 1 offsets.
 int scan_tiles(int64_t len);
-hipError_t scan_exclusive(int64_t len, const int64_t *in, int64_t *tmp, int64_t *tot, int64_t *out64,
-                          int32_t *out32, hipStream_t s);
+hipError_t scan_exclusive(int64_t len, const int64_t *in, int64_t *tot, int64_t *out64, int32_t *out32,
+                          hipStream_t s);
 
 // ------------------------------------------------------------------ pattern analysis into caller buffers
 // (pattern.hip; used by abilu_build_pattern and by the server, which carves the arrays out of its
 // pool). Scratch: pattern_scratch_bytes(n, Z) device bytes, kept between the two stages.
 size_t pattern_scratch_bytes(int32_t n, int64_t Z);
+// The pattern-analysis scratch of pattern_scratch_bytes(n, Z) bytes: a 256-byte header (the
+// validation error word), then int64 cnt[Z + n + 2] (counts to scan), ptr64[Z + n + 2] (int64
+// offsets, kept for the fill) and the scan's tile sums. The one definition of these offsets.
+struct PatScratch {
+    int64_t *cnt, *ptr64, *tot;
+};
+inline PatScratch pat_scratch(void *scratch, int32_t n, int64_t Z) {
+    const int64_t len = Z + n + 2;
+    int64_t *cnt = (int64_t *)((char *)scratch + 256);
+    return PatScratch{cnt, cnt + len, cnt + 2 * len};
+}
 abilu_status pattern_validate_async(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx,
                                     int32_t *diag_pos, void *scratch, unsigned *h_err, hipStream_t s);
 abilu_status pattern_count_async(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx,

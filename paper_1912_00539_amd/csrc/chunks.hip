@@ -208,15 +208,14 @@ extern "C" abilu_status abilu_pattern_set_chunks(abilu_pattern *p, int32_t rows_
     const int nch = div_up(n, R);
     abilu_status st = ABILU_OK;
     char *scratch = nullptr;
-    // scratch: lev[2][n], cnt[2][nch + 1], scan tmp[nch + 1], scan tiles, maxlev[2]
+    // scratch: lev[2][n], cnt[2][nch + 1], scan tiles, maxlev[2]
     const size_t o_lev = 0;
     const size_t o_cnt = o_lev + 256 * (size_t)div_up(2 * sizeof(int32_t) * (size_t)n, 256);
-    const size_t o_tmp = o_cnt + 2 * sizeof(int64_t) * (size_t)(nch + 1);
-    const size_t o_tot = o_tmp + sizeof(int64_t) * (size_t)(nch + 1);
+    const size_t o_tot = o_cnt + 2 * sizeof(int64_t) * (size_t)(nch + 1);
     const size_t o_max = o_tot + sizeof(int64_t) * (size_t)(scan_tiles(nch) + 1);
     const size_t sbytes = o_max + 64;
     int32_t *lev = nullptr;
-    int64_t *cnt = nullptr, *tmp = nullptr, *tot = nullptr;
+    int64_t *cnt = nullptr, *tot = nullptr;
     int *maxlev = nullptr;
     int32_t *h = (int32_t *)p->pinned;
 #define CK(x)                                  \
@@ -236,7 +235,6 @@ extern "C" abilu_status abilu_pattern_set_chunks(abilu_pattern *p, int32_t rows_
     CKA(hipMalloc(&scratch, sbytes));
     lev = (int32_t *)(scratch + o_lev);
     cnt = (int64_t *)(scratch + o_cnt);
-    tmp = (int64_t *)(scratch + o_tmp);
     tot = (int64_t *)(scratch + o_tot);
     maxlev = (int *)(scratch + o_max);
     for (int q = 0; q < 2; ++q) {
@@ -248,7 +246,7 @@ extern "C" abilu_status abilu_pattern_set_chunks(abilu_pattern *p, int32_t rows_
                                                    cnt, cnt + (nch + 1), maxlev);
     CK(hipGetLastError());
     for (int q = 0; q < 2; ++q) {
-        CK(scan_exclusive(nch, cnt + q * (nch + 1), tmp, tot, nullptr, p->lvptr[q], s));
+        CK(scan_exclusive(nch, cnt + q * (nch + 1), tot, nullptr, p->lvptr[q], s));
         CK(hipMemcpyAsync(h + q, p->lvptr[q] + nch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }
     CK(hipMemcpyAsync(h + 2, maxlev, 2 * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -51,7 +51,7 @@ extern "C" abilu_status abilu_gen_sizes(const abilu_gen_spec *spec, int32_t *n, 
 extern "C" size_t abilu_gen_scratch_bytes(const abilu_gen_spec *spec) {
     int64_t nn, zz;
     if (!sizes_of(spec, &nn, &zz)) return 0;
-    return sizeof(int64_t) * (size_t)(2 * (nn + 1) + scan_tiles(nn) + 1);
+    return sizeof(int64_t) * (size_t)((nn + 1) + scan_tiles(nn) + 1);
 }
 
 extern "C" abilu_status abilu_gen_build(const abilu_gen_spec *spec, int32_t *d_rowptr, int32_t *d_colidx,
@@ -62,8 +62,7 @@ extern "C" abilu_status abilu_gen_build(const abilu_gen_spec *spec, int32_t *d_r
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)nn;
     int64_t *len = (int64_t *)d_scratch;
-    int64_t *tmp = len + (nn + 1);
-    int64_t *tot = tmp + (nn + 1);
+    int64_t *tot = len + (nn + 1);
     {
         ProfScope ps("gen_rowlen", s, 8.0 * nn);
         if (spec->kind == ABILU_GEN_TRI)
@@ -72,7 +71,7 @@ extern "C" abilu_status abilu_gen_build(const abilu_gen_spec *spec, int32_t *d_r
             k_gen_rowlen<ABILU_GEN_ANISO><<<div_up(n, 256), 256, 0, s>>>(spec->nx, spec->ny, spec->seed, n, len);
     }
     if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
-    if (!hip_ok(scan_exclusive(nn, len, tmp, tot, nullptr, d_rowptr, s), "gen rowptr scan")) return ABILU_EDEVICE;
+    if (!hip_ok(scan_exclusive(nn, len, tot, nullptr, d_rowptr, s), "gen rowptr scan")) return ABILU_EDEVICE;
     {
         ProfScope ps("gen_fill", s, 4.0 * (nn + 1) + 132.0 * zz + 32.0 * nn);
         if (spec->kind == ABILU_GEN_TRI)

@@ -72,7 +72,7 @@ namespace abilu {
 
 size_t pattern_scratch_bytes(int32_t n, int64_t Z) {
     const int64_t len = Z + n + 2;
-    return 256 + sizeof(int64_t) * (size_t)(3 * len + scan_tiles(Z > n ? Z : n) + 1);
+    return 256 + sizeof(int64_t) * (size_t)(2 * len + scan_tiles(Z > n ? Z : n) + 1);
 }
 
 // Non-blocking stage 1a: validation and diagonal positions; the error word (nonzero: invalid
@@ -96,9 +96,8 @@ abilu_status pattern_validate_async(int32_t n, int64_t Z, const int32_t *rowptr,
 abilu_status pattern_count_async(int32_t n, int64_t Z, const int32_t *rowptr, const int32_t *colidx,
                                  const int32_t *diag_pos, int32_t *lrow, int32_t *urow, int32_t *pair_ptr,
                                  void *scratch, int64_t *h_sizes, hipStream_t s) {
-    const int64_t len = Z + n + 2;
-    int64_t *cnt = (int64_t *)((char *)scratch + 256);
-    int64_t *tmp = cnt + len, *ptr64 = tmp + len, *tot = ptr64 + len;
+    const PatScratch S = pat_scratch(scratch, n, Z);
+    int64_t *cnt = S.cnt, *ptr64 = S.ptr64, *tot = S.tot;
 #define CK(x)                                              \
     do {                                                   \
         if (!hip_ok((x), #x)) return ABILU_EDEVICE;        \
@@ -108,14 +107,14 @@ abilu_status pattern_count_async(int32_t n, int64_t Z, const int32_t *rowptr, co
         CK(hipGetLastError());
     }
     for (int part = 0; part < 2; ++part) {
-        CK(scan_exclusive(n, cnt + (part == 0 ? 0 : (n + 1)), tmp, tot, ptr64, part == 0 ? lrow : urow, s));
+        CK(scan_exclusive(n, cnt + (part == 0 ? 0 : (n + 1)), tot, ptr64, part == 0 ? lrow : urow, s));
         CK(hipMemcpyAsync(h_sizes + part, ptr64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     }
     if (n > 0) {
         k_pat_count<<<div_up(n, PAT_ROWS), PAT_ROWS, 0, s>>>(n, rowptr, colidx, diag_pos, cnt);
         CK(hipGetLastError());
     }
-    CK(scan_exclusive(Z, cnt, tmp, tot, ptr64, pair_ptr, s));
+    CK(scan_exclusive(Z, cnt, tot, ptr64, pair_ptr, s));
     CK(hipMemcpyAsync(h_sizes + 2, ptr64 + Z, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     return ABILU_OK;
 #undef CK
@@ -149,8 +148,7 @@ abilu_status pattern_fill(int32_t n, int64_t Z, int64_t ZL, int64_t ZU, int64_t 
                           const int32_t *colidx, const int32_t *diag_pos, const int32_t *lrow, const int32_t *urow,
                           int32_t *lcol, int32_t *ucol, int32_t *pik, int32_t *pkj, int32_t *sik, int32_t *skj,
                           const void *scratch, hipStream_t s) {
-    const int64_t len = Z + n + 2;
-    const int64_t *ptr64 = (const int64_t *)((const char *)scratch + 256) + 2 * len;
+    const int64_t *ptr64 = pat_scratch(const_cast<void *>(scratch), n, Z).ptr64;
     if (!hip_ok(hipMemsetAsync(lcol, 0, sizeof(int32_t) * (ZL + 1), s), "lcol clear") ||
         !hip_ok(hipMemsetAsync(ucol, 0, sizeof(int32_t) * (ZU + 1), s), "ucol clear"))
         return ABILU_EDEVICE;

@@ -232,7 +232,7 @@ struct SetupDesc {
     uint64_t seed;
     int32_t *rowptr, *colidx, *diag_pos, *lrow, *urow, *lcol, *ucol, *pair_ptr, *pik, *pkj, *sik, *skj;
     double *A, *b;
-    int64_t *cnt, *tmp, *ptr64, *tot;   // scratch: 3 x (Z + n + 2) + tiles + 1 int64
+    int64_t *cnt, *ptr64, *tot;   // scratch: 2 x (Z + n + 2) + tiles + 1 int64
     int32_t slot, pad;
 };
 
@@ -267,10 +267,10 @@ __global__ __launch_bounds__(WG) void kbs_gen_fill(const SetupDesc *sd, const Me
         abilu_setup::gen_fill_body<ABILU_GEN_ANISO>(blk, D.nx, D.ny, D.cfl, D.seed, D.n, D.rowptr, D.colidx, D.A, D.b);
 }
 
-__global__ __launch_bounds__(abilu_setup::SCAN_T) void kbs_scan_tiles(const SetupDesc *sd, const Member *mem, int nmem,
-                                                                     int which) {
+__global__ __launch_bounds__(abilu_setup::SCAN_T) void kbs_scan_reduce(const SetupDesc *sd, const Member *mem, int nmem,
+                                                                      int which) {
     SMEMBER();
-    abilu_setup::scan_tiles_body(blk, scan_len(D, which), scan_in(D, which), D.tmp, D.tot);
+    abilu_setup::scan_reduce_body(blk, scan_len(D, which), scan_in(D, which), D.tot);
 }
 
 // one workgroup per member
@@ -288,7 +288,8 @@ __global__ __launch_bounds__(abilu_setup::SCAN_T) void kbs_scan_finish(const Set
     const int64_t len = scan_len(D, which);
     const int nt = div_up(len > 0 ? len : 1, abilu_setup::SCAN_TILE);
     int32_t *out32 = which == SC_ROWPTR ? D.rowptr : (which == SC_LROW ? D.lrow : (which == SC_UROW ? D.urow : D.pair_ptr));
-    abilu_setup::scan_finish_body(blk, len, D.tmp, D.tot, D.tot + nt, which == SC_PAIR ? D.ptr64 : nullptr, out32);
+    abilu_setup::scan_finish_body(blk, len, scan_in(D, which), D.tot, D.tot + nt, which == SC_PAIR ? D.ptr64 : nullptr,
+                                  out32);
     // the member's last workgroup (the one holding index len) records the total for admission
     if (which != SC_ROWPTR && threadIdx.x == 0 && (int64_t)blk == len / abilu_setup::SCAN_TILE)
         adm[4 * m_ + which] = D.tot[nt];
@@ -575,7 +576,7 @@ abilu_status upload_setup_tables(abilu_server *s, const std::vector<int64_t> &id
 abilu_status launch_scan(abilu_server *s, const SetupTables &T, int which) {
     const bool z = which == SC_PAIR;
     hipStream_t st = s->setup;
-    kbs_scan_tiles<<<T.tiles[z ? SS_SCAN_Z : SS_SCAN_N], abilu_setup::SCAN_T, 0, st>>>(
+    kbs_scan_reduce<<<T.tiles[z ? SS_SCAN_Z : SS_SCAN_N], abilu_setup::SCAN_T, 0, st>>>(
         s->d_sdesc, T.d[z ? SS_SCAN_Z : SS_SCAN_N], T.count, which);
     if (launch_status() != ABILU_OK) return ABILU_EDEVICE;
     kbs_scan_totals<<<T.tiles[SS_ONE], abilu_setup::SCAN_T, 0, st>>>(s->d_sdesc, T.d[SS_ONE], T.count, which);
@@ -611,11 +612,10 @@ void stage_request(abilu_server *s, Req &r, int m) {
     D.skj = (int32_t *)P(L.skj);
     D.A = (double *)P(L.A);
     D.b = (double *)P(L.b);
-    const int64_t len = r.Z + r.n + 2;
-    D.cnt = (int64_t *)((char *)P(L.scratch) + 256);
-    D.tmp = D.cnt + len;
-    D.ptr64 = D.tmp + len;
-    D.tot = D.ptr64 + len;
+    const PatScratch S = pat_scratch(P(L.scratch), r.n, r.Z);
+    D.cnt = S.cnt;
+    D.ptr64 = S.ptr64;
+    D.tot = S.tot;
     D.slot = r.slot;
     // the slot descriptor the tick kernels will use (ZL is filled in on the device)
     Slot &d = s->h_slots[m];

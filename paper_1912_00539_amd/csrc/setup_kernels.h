@@ -15,8 +15,10 @@ using namespace abilu;
 using namespace abilu_dev;
 
 // ------------------------------------------------------------------ exclusive prefix sums
-// Three phases over int64 counts: per-tile scan (SCAN_T threads, SCAN_TILE elements), scan of
-// the tile totals in one workgroup, then add the tile offsets and write len + 1 offsets.
+// Three phases over int64 counts: the sum of each tile (SCAN_T threads, SCAN_TILE elements), an
+// exclusive scan of the tile sums in one workgroup, then each tile scanned again from its offset
+// and written as len + 1 offsets. The counts are read twice and only the offsets are written: no
+// intermediate array goes to memory and back.
 constexpr int SCAN_T = 256, SCAN_E = 8, SCAN_TILE = SCAN_T * SCAN_E;
 
 __device__ __forceinline__ long long block_exclusive(long long v, long long *sh, long long *total) {
@@ -35,23 +37,19 @@ __device__ __forceinline__ long long block_exclusive(long long v, long long *sh,
     return inc - v;
 }
 
-__device__ __forceinline__ void scan_tiles_body(int blk, int64_t len, const int64_t *__restrict__ in,
-                                                       int64_t *__restrict__ out, int64_t *__restrict__ tot) {
+// tot[blk] = sum of the tile's counts (read strided, so each load instruction is coalesced)
+__device__ __forceinline__ void scan_reduce_body(int blk, int64_t len, const int64_t *__restrict__ in,
+                                                 int64_t *__restrict__ tot) {
     __shared__ long long sh[SCAN_T];
-    int64_t base = (int64_t)blk * SCAN_TILE + (int64_t)threadIdx.x * SCAN_E;
-    long long v[SCAN_E], s = 0;
+    const int64_t first = (int64_t)blk * SCAN_TILE;
+    long long s = 0;
 #pragma unroll
     for (int q = 0; q < SCAN_E; ++q) {
-        v[q] = (base + q < len) ? in[base + q] : 0;
-        s += v[q];
+        const int64_t e = first + (int64_t)q * SCAN_T + threadIdx.x;
+        if (e < len) s += in[e];
     }
     long long total;
-    long long pre = block_exclusive(s, sh, &total);
-#pragma unroll
-    for (int q = 0; q < SCAN_E; ++q) {
-        if (base + q < len) out[base + q] = pre;
-        pre += v[q];
-    }
+    (void)block_exclusive(s, sh, &total);
     if (threadIdx.x == 0) tot[blk] = total;
 }
 
@@ -70,20 +68,30 @@ __device__ __forceinline__ void scan_totals_body(int ntiles, int64_t *__restrict
     if (threadIdx.x == 0) *grand = carry;
 }
 
-__device__ __forceinline__ void scan_finish_body(int blk, int64_t len, const int64_t *__restrict__ scan, const int64_t *__restrict__ tot,
-                              const int64_t *__restrict__ grand, int64_t *__restrict__ ptr64,
-                              int32_t *__restrict__ ptr32) {
-    // one scan tile per workgroup (SCAN_T threads, SCAN_E elements each, strided for coalescing);
-    // the workgroup past the last full tile also writes the grand total at index len
+// One tile per workgroup, SCAN_E consecutive counts per thread: offsets out[e] = tot[blk] + the
+// tile's exclusive sum before e, for e < len; the workgroup holding index len writes the grand
+// total there (a workgroup past the last full tile exists for that alone).
+__device__ __forceinline__ void scan_finish_body(int blk, int64_t len, const int64_t *__restrict__ in,
+                                                 const int64_t *__restrict__ tot, const int64_t *__restrict__ grand,
+                                                 int64_t *__restrict__ ptr64, int32_t *__restrict__ ptr32) {
+    __shared__ long long sh[SCAN_T];
     const int64_t first = (int64_t)blk * SCAN_TILE;
-    const int64_t add = first < len ? tot[blk] : 0;
+    const int64_t base = first + (int64_t)threadIdx.x * SCAN_E;
+    long long v[SCAN_E], s = 0;
 #pragma unroll
     for (int q = 0; q < SCAN_E; ++q) {
-        const int64_t e = first + (int64_t)q * SCAN_T + threadIdx.x;
+        v[q] = (base + q < len) ? in[base + q] : 0;
+        s += v[q];
+    }
+    long long total;
+    long long pre = block_exclusive(s, sh, &total) + (first < len ? tot[blk] : 0);
+#pragma unroll
+    for (int q = 0; q < SCAN_E; ++q) {
+        const int64_t e = base + q;
         if (e < len) {
-            const int64_t v = scan[e] + add;
-            if (ptr64) ptr64[e] = v;
-            ptr32[e] = (int32_t)v;
+            if (ptr64) ptr64[e] = pre;
+            ptr32[e] = (int32_t)pre;
+            pre += v[q];
         } else if (e == len) {
             if (ptr64) ptr64[len] = *grand;
             ptr32[len] = (int32_t)*grand;
