@@ -711,6 +711,31 @@ def test_full_size_tri300(cfl):
 
 
 @pytest.mark.slow
+def test_full_size_tri300_fgmres_f64_matches_oracle():
+    """FGMRES(30) at full size in FP64 to a tight tolerance (1e-8, about ten Arnoldi steps): the
+    synchronous two-sweep factor and apply are the oracle's bit for bit, so the GPU's classical
+    Gram-Schmidt (twice when needed) and the oracle's modified Gram-Schmidt must reach the same
+    iteration count within one, true residuals below rtol on both, and, at equal counts, the same
+    x to 1e-10 relative."""
+    c = W.case("tri300", cfl=100.0)
+    s = DS(c, "f64", restart=30)
+    s.factor(2, "sync")
+    st, res = s.solve(apply_sweeps=2, mode="sync", rtol=1e-8, maxit=300)
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 2)
+    ref = oracle.fgmres(c.n, c.rowptr, c.colidx, c.vals, c.b, Xo, Do, restart=30, maxit=300, rtol=1e-8, apply_nsw=2)
+    x = s.x.cpu().numpy()
+    bn = np.linalg.norm(c.b)
+    true = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, x)) / bn
+    true_ref = np.linalg.norm(c.b - oracle.spmv(c.n, c.rowptr, c.colidx, c.vals, ref["x"])) / bn
+    print(f"tri300 FP64 FGMRES to 1e-8: gpu {res['iters']} iterations ({true:.2e}), oracle {ref['iters']} ({true_ref:.2e})")
+    assert st == 0 and res["converged"] and ref["converged"]
+    assert abs(res["iters"] - ref["iters"]) <= 1
+    assert true <= 1e-8 and true_ref <= 1e-8 and abs(true - res["rel_true_residual"]) <= 1e-12
+    if res["iters"] == ref["iters"]:
+        assert rel(x, ref["x"]) <= 1e-10
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("order", ["line", "rcm"])
 def test_full_size_aniso1000(order):
     """The 500,000-cell anisotropic workload (1000 x 500, aspect ratio 1000 at the wall) in line
