@@ -64,8 +64,12 @@ def get(name):
 # ------------------------------------------------------------------ pattern analysis (a1)
 @pytest.mark.parametrize("name", CASES)
 def test_pattern_bit_exact(name):
+    _check_pattern(get(name))
+
+
+def _check_pattern(c):
+    """diag_pos, the update-set offsets and pair lists exported by the library equal the oracle's."""
     from paper_1912_00539_amd import abilu as L
-    c = get(name)
     s = DS(c)
     n, z, npairs = s.pattern.info()
     ptr, pik, pkj = oracle.pairs(c.n, c.rowptr, c.colidx)
@@ -81,6 +85,20 @@ def test_pattern_bit_exact(name):
     np.testing.assert_array_equal(pp.cpu().numpy(), ptr)
     np.testing.assert_array_equal(a.cpu().numpy()[:npairs], pik)
     np.testing.assert_array_equal(b.cpu().numpy()[:npairs], pkj)
+
+
+# chain lengths whose prefix scans end at, just before and just after a 2,048-entry scan tile:
+# over the N rows (lower/upper offsets) and over the Z = 3N - 2 blocks (update-set offsets)
+@pytest.mark.parametrize("n", [2047, 2048, 2049, 1365, 1366, 1367, 6145])
+def test_pattern_and_factor_at_scan_tile_boundaries(n):
+    c = W.case("chain", seed=n, n=n)
+    _check_pattern(c)
+    s = DS(c, "f64")
+    s.factor(1, "sync")
+    X, D = s.factor_host()
+    Xo, Do, _ = oracle.factor_sync(c.n, c.rowptr, c.colidx, c.vals, 1)
+    assert_same_bits(X, Xo, "X")
+    assert_same_bits(D, Do, "Dinv")
 
 
 def test_pattern_invalid_rejected():
