@@ -556,7 +556,39 @@ def configs_bench(args):
                                     else "exceeds the 256 MB Infinity Cache")
         log(f"config {label}: {rows}")
         out[label] = rows
+    out["quad32"] = config0_bench(args)
     out["tri300_cfl_sweep"] = tri300_sweep_bench()
+    return out
+
+
+def config0_bench(args):
+    """The plain FP64 32x32 grid (1,024 cells) as specified: 3 synchronous factor sweeps, then one
+    FGMRES(30) solve to 1e-2 with 3 synchronous apply sweep pairs, from a zero initial guess. A
+    launch-bound workload: the time per factor and per solve (means over 200 repetitions) and the
+    solve's iterations."""
+    import torch
+    from paper_1912_00539_amd import workloads as W
+    from paper_1912_00539_amd.runtime import DeviceSystem
+    c = W.case("quad32")
+    s = DeviceSystem(c, prec="f64", restart=30)
+    s.factor(3, "sync")
+    st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-2, maxit=300)
+    torch.cuda.synchronize()
+    reps = 200
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.factor(3, "sync")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        st, res = s.solve(apply_sweeps=3, mode="sync", rtol=1e-2, maxit=300)
+    t2 = time.perf_counter()
+    out = {"n": c.n, "nnzb": c.nnzb, "factor_us": round((t1 - t0) / reps * 1e6, 1),
+           "solve_us": round((t2 - t1) / reps * 1e6, 1), "fgmres_iters": res["iters"],
+           "rel_true_residual": float(f"{res['rel_true_residual']:.4e}"), "converged": bool(res["converged"])}
+    log(f"config 0 (quad32): {out}")
+    del s
+    torch.cuda.empty_cache()
     return out
 
 
