@@ -16,6 +16,9 @@ BIN = os.path.join(ROOT, "paper_1912_00539_amd", "lib", "abilu_c_solve")
 
 @pytest.mark.parametrize("nx,ny", [(40, 30), (7, 3), (1, 1)])
 def test_c_program_solves(nx, ny):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
     if not os.path.exists(BIN):
         pytest.fail("abilu_c_solve is not built: run __graft_entry__.build()")
     out = subprocess.run([BIN, str(nx), str(ny)], capture_output=True, text=True, timeout=120)
