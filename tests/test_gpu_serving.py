@@ -146,6 +146,29 @@ def test_isolation_sync_bitwise(prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_results_do_not_depend_on_the_pool_contents(prec):
+    """Every request reads only what admission and its own ticks wrote: with the pool's bytes set to
+    0xFF (NaN in either precision) beforehand, SYNC results are the bits of a zeroed pool, and ASYNC
+    solves still converge with finite x."""
+    cfg = cfg_of(prec, "sync", 2, max_active=16)
+    runs = []
+    for fill in (0xFF, 0x00):
+        pool = pool_for(cfg, MIX)
+        pool.fill_(fill)
+        runs.append(serve(cfg, MIX, pool=pool))
+    (ra, xa), (rb, xb) = runs
+    for q in range(len(MIX)):
+        assert ra[q]["status"] in (0, 1, 2) and ra[q]["flags"] == 0, ra[q]
+        same(ra[q], xa[q], rb[q], xb[q])
+    cfg = cfg_of(prec, "async", 1, rtol=1e-2, restart=30, maxit=300, max_active=16)
+    pool = pool_for(cfg, MIX)
+    pool.fill_(0xFF)
+    res, xs = serve(cfg, MIX, pool=pool)
+    for q in range(len(MIX)):
+        assert res[q]["converged"] and res[q]["flags"] == 0 and bool(torch.isfinite(xs[q]).all()), res[q]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_served_equals_single_system_path(prec):
     """In SYNC mode the served solve is bitwise abilu_factor + fgmres_solve on the same system."""
     res, xs = serve(cfg_of(prec, "sync", 2, max_active=16), MIX)
