@@ -48,6 +48,29 @@ struct KPtrs {
     int *guard, *done;
 };
 
+// The single-lane step OP on the column sums in P.red (run by one lane of the last workgroup).
+template <int OP>
+__device__ __forceinline__ void step_tail(const KPtrs &P, int k, int m) {
+    if constexpr (OP == RS_BETA_START_ZERO) {   // the solve's first reduction (one column): also
+        beta_body(0, m, P.red, P.g, P.misc, P.status, ST_NUM);   // clears the completion count
+        beta_body(0, m, P.red, nullptr, P.misc, P.status, ST_BETA);
+        *P.done = 0;
+    } else if constexpr (OP == RS_BETA_START_X) {
+        beta_body(0, m, P.red, nullptr, P.misc, P.status, ST_NUM);
+        *P.done = 0;
+    } else if constexpr (OP == RS_BETA) {
+        beta_body(0, m, P.red, P.g, P.misc, P.status, ST_BETA);
+    } else if constexpr (OP == RS_GS1) {
+        gs1_body(0, k, m, P.red, P.H, P.coef, P.misc);
+    } else if constexpr (OP == RS_GS1_DONE) {
+        gs1_done_body(0, P.red, P.misc, P.guard);
+    } else if constexpr (OP == RS_GS2) {
+        gs2_body(0, k, m, P.red, P.H, P.coef, P.guard);
+    } else {
+        givens_body(0, k, m, P.red, P.guard, P.H, P.cs, P.sn, P.g, P.misc, P.status);
+    }
+}
+
 // k_reduce_cols followed by single-lane step OP on the column sums, in one launch: each
 // workgroup reduces its column (or nothing when the guard says skip), then counts itself done;
 // the last one (agent-scope fences on both sides of the count, so the other columns' sums are
@@ -72,24 +95,56 @@ __global__ __launch_bounds__(WG) void k_reduce_step(KPtrs P, int nb, const int *
     }
     __syncthreads();
     if (!last || threadIdx.x != 0) return;
-    if constexpr (OP == RS_BETA_START_ZERO) {   // the solve's first reduction (one column): also
-        beta_body(0, m, P.red, P.g, P.misc, P.status, ST_NUM);   // clears the completion count
-        beta_body(0, m, P.red, nullptr, P.misc, P.status, ST_BETA);
-        *P.done = 0;
-    } else if constexpr (OP == RS_BETA_START_X) {
-        beta_body(0, m, P.red, nullptr, P.misc, P.status, ST_NUM);
-        *P.done = 0;
-    } else if constexpr (OP == RS_BETA) {
-        beta_body(0, m, P.red, P.g, P.misc, P.status, ST_BETA);
-    } else if constexpr (OP == RS_GS1) {
-        gs1_body(0, k, m, P.red, P.H, P.coef, P.misc);
-    } else if constexpr (OP == RS_GS1_DONE) {
-        gs1_done_body(0, P.red, P.misc, P.guard);
-    } else if constexpr (OP == RS_GS2) {
-        gs2_body(0, k, m, P.red, P.H, P.coef, P.guard);
-    } else {
-        givens_body(0, k, m, P.red, P.guard, P.H, P.cs, P.sn, P.g, P.misc, P.status);
+    step_tail<OP>(P, k, m);
+}
+
+// ---- small systems (at most FOLD_NB vector workgroups): the dot and update kernels reduce their
+// own partials in their last workgroup and run the step there, one launch instead of two. The
+// columns are summed by reduce_cols_body, in the same order, so the results are those of the
+// two-launch form bit for bit.
+constexpr int FOLD_NB = 64;
+
+// true in the last workgroup to finish (every workgroup's partials then visible to all its
+// lanes); clears the count for the next launch
+__device__ __forceinline__ bool last_workgroup(int *done) {
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int is_last = 1;
+        if (gridDim.x > 1) {
+            is_last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+            if (is_last) *done = 0;
+        }
+        last = is_last;
     }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+template <int OP>
+__global__ __launch_bounds__(WG) void k_mdot_step(int64_t len, const double *__restrict__ V, int64_t ldv, int q,
+                                                  const double *__restrict__ w, KPtrs P, int nb, const int *guard,
+                                                  int k, int m) {
+    mdot_body(blockIdx.x, len, V, ldv, q, w, P.partials, nb, guard);
+    if (!last_workgroup(P.done)) return;
+    for (int c = 0; c <= q; ++c) {
+        reduce_cols_body(c, P.partials, nb, P.red, guard);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) step_tail<OP>(P, k, m);
+}
+
+template <int OP>
+__global__ __launch_bounds__(WG) void k_update_step(int64_t len, const double *__restrict__ V, int64_t ldv, int q,
+                                                    const double *__restrict__ c, double alpha, double *__restrict__ w,
+                                                    KPtrs P, int nb, const int *guard, int k, int m) {
+    update_body(gridDim.x - 1 - blockIdx.x, len, V, ldv, q, c, alpha, w, P.partials, guard);
+    if (!last_workgroup(P.done)) return;
+    reduce_cols_body(0, P.partials, nb, P.red, guard);
+    __syncthreads();
+    if (threadIdx.x == 0) step_tail<OP>(P, k, m);
 }
 
 // v = w / h (h read from device memory; left unchanged if h == 0)
@@ -207,10 +262,29 @@ abilu_status reduce_step(Ctx &c, int ncols, const int *guard, int op, int k) {
     return ABILU_OK;
 }
 
+// one launch of kernel template K<OP> for a runtime op (the steps after a dot or update kernel)
+#define ABILU_STEP_SWITCH(K, ARGS)                                                  \
+    switch (op) {                                                                   \
+        case RS_BETA: K<RS_BETA><<<nb, WG, 0, c.s>>> ARGS; break;                   \
+        case RS_GS1: K<RS_GS1><<<nb, WG, 0, c.s>>> ARGS; break;                     \
+        case RS_GS1_DONE: K<RS_GS1_DONE><<<nb, WG, 0, c.s>>> ARGS; break;           \
+        case RS_GS2: K<RS_GS2><<<nb, WG, 0, c.s>>> ARGS; break;                     \
+        default: K<RS_GIVENS><<<nb, WG, 0, c.s>>> ARGS; break;                      \
+    }
+
 // c.red[0..q] <- dots of w with V_0..V_{q-1}, then ||w||^2; then step op
 abilu_status mdot_reduce(Ctx &c, const double *Vb, int q, const double *w, const int *guard, int op, int k) {
     const int nb = c.W.nb_vec;
     const double n8 = 8.0 * (double)c.nv;
+    if (nb <= FOLD_NB && op != RS_BETA_START_ZERO && op != RS_BETA_START_X) {
+        {
+            ProfScope ps("fgmres_mdot", c.s, (q + 1) * n8 + 8.0 * (q + 1) * nb);
+            const KPtrs P = c.ptrs();
+            ABILU_STEP_SWITCH(k_mdot_step, (c.nv, Vb, c.nv, q, w, P, nb, guard, k, c.m))
+        }
+        CKL();
+        return ABILU_OK;
+    }
     {
         ProfScope ps("fgmres_mdot", c.s, (q + 1) * n8);
         k_mdot<<<nb, WG, 0, c.s>>>(c.nv, Vb, c.nv, q, w, c.partials, nb, guard);
@@ -224,6 +298,15 @@ abilu_status update_reduce(Ctx &c, const double *Vb, int q, double alpha, double
     const int nb = c.W.nb_vec;
     const double n8 = 8.0 * (double)c.nv;
     const bool with_norm = op >= 0;
+    if (with_norm && nb <= FOLD_NB) {
+        {
+            ProfScope ps("fgmres_update", c.s, (q + 2) * n8 + 8.0 * nb);
+            const KPtrs P = c.ptrs();
+            ABILU_STEP_SWITCH(k_update_step, (c.nv, Vb, c.nv, q, c.coef, alpha, w, P, nb, guard, k, c.m))
+        }
+        CKL();
+        return ABILU_OK;
+    }
     {
         ProfScope ps("fgmres_update", c.s, (q + 2) * n8);
         k_update<<<nb, WG, 0, c.s>>>(c.nv, Vb, c.nv, q, c.coef, alpha, w, with_norm ? c.partials : nullptr, guard);
